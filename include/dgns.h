@@ -1,0 +1,163 @@
+/*
+ * dgns.h -- C ABI of the MI355X matrix-free DG compressible Navier-Stokes library.
+ *
+ * The library evaluates the spatial operator of the high-order discontinuous
+ * Galerkin discretisation of Fehn, Wall & Kronbichler (arXiv 1806.03095):
+ *
+ *     dU/dt = L(U) = M^{-1} ( -F_c(U) - F_v(U) + F_rhs(U) )      (Sec. 2.4, eq.
+ *                                                                 SpatiallyDiscretizedProblem)
+ *
+ * with F_c, F_v the convective and viscous weak-form operators of Sec. 2.2.2, eq.
+ * (WeakFormulationConservedVariables) -- local Lax-Friedrichs flux, symmetric
+ * interior penalty with the penalty of eq. (TauIP_Element) -- evaluated by Gauss
+ * quadrature with n_q points per direction (Sec. 2.2.3) and sum factorisation
+ * (Sec. 2.3); M the block-diagonal mass matrix on k+1 points, inverted exactly; and
+ * a low-storage explicit Runge-Kutta step that calls L once per stage (Sec. 2.4).
+ *
+ * Conventions (all entry points):
+ *  - Every call returns int: DGNS_OK (0) or a negative DGNS_E* code.  On error,
+ *    dgns_last_error() returns a message for the calling thread; nothing is thrown
+ *    across the ABI and no output is written.
+ *  - Solution vectors are DEVICE pointers owned by the caller, float64, contiguous,
+ *    laid out [5][n_cells][(k+1)^3]: conserved component (rho, rho u1, rho u2,
+ *    rho u3, rho E), cell (i0 + n0*(i1 + n1*i2)), node (a0 + (k+1)*(a1 + (k+1)*a2)
+ *    of the tensor-product nodal basis, first coordinate fastest).  They must be
+ *    8-byte aligned.  The float32 operator variant keeps this float64 interface.
+ *  - The library owns only its context (geometry, metric terms, 1D tables).  It
+ *    never frees or retains caller memory.
+ *  - Calls are asynchronous on the context's HIP stream unless stated otherwise.
+ *    Inputs and outputs must not alias unless stated.  Results are deterministic:
+ *    no atomics, fixed summation order.
+ *  - One context per stream; a context is not safe for concurrent calls.
+ */
+#ifndef DGNS_H
+#define DGNS_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define DGNS_OK 0
+#define DGNS_EINVAL (-1)         /* bad argument: null pointer, size, range, alias */
+#define DGNS_ENOMEM (-2)         /* device or host allocation failed */
+#define DGNS_EHIP (-3)           /* a HIP runtime call failed */
+#define DGNS_EUNSUPPORTED (-4)   /* (degree, n_q, precision) has no compiled kernel */
+#define DGNS_ENONFINITE (-5)     /* a diagnostic found a NaN or Inf in the state */
+
+#define DGNS_BASIS_LGL 0         /* Legendre-Gauss-Lobatto support points (Sec. 2.2.1) */
+#define DGNS_BASIS_GL 1          /* Gauss-Legendre support points */
+
+#define DGNS_FP64 0
+#define DGNS_FP32 1              /* operator arithmetic in float32; vectors stay float64 */
+
+#define DGNS_MESH_AFFINE 0       /* uniform box */
+#define DGNS_MESH_CHANNEL 1      /* tanh wall-normal stretching in x2 (Sec. 5.3.1) */
+#define DGNS_MESH_CURVED 2       /* x_i += a * prod_j sin(2 pi s_j), s the unit-cube coordinate */
+
+#define DGNS_TERM_CONVECTIVE 1u  /* cell + face convective terms */
+#define DGNS_TERM_VISCOUS 2u     /* cell + face viscous terms (SIPG) */
+#define DGNS_TERM_FORCE 4u       /* body-force right-hand side */
+#define DGNS_TERM_ALL 7u
+
+#define DGNS_IC_TAYLOR_GREEN 0   /* Sec. 5.2.1; ic_params = {U0, L, Mach, rho0} */
+#define DGNS_IC_CHANNEL 1        /* Sec. 5.3.1; ic_params = {u_max, Mach, power, amp} */
+#define DGNS_IC_UNIFORM 2        /* ic_params = {rho, u1, u2, u3, p} */
+
+typedef struct dgns_ctx dgns_ctx;
+
+/* Discretisation and fluid parameters (Sec. 2.1, 2.2). */
+typedef struct dgns_params {
+    int degree;            /* polynomial degree k, 1..7 */
+    int n_q;               /* Gauss points per direction for the flux integrals */
+    int basis;             /* DGNS_BASIS_* */
+    int precision;         /* DGNS_FP64 or DGNS_FP32 */
+    double gamma;          /* ratio of specific heats */
+    double R;              /* specific gas constant */
+    double mu;             /* dynamic viscosity */
+    double lambda;         /* thermal conductivity */
+    double rho_ref;        /* reference density rho_0 of nu = mu / rho_0 in tau_IP */
+    double body_force[3];  /* constant body force f of F_rhs = (0, f, f.u) */
+    double wall_T;         /* isothermal wall temperature (non-periodic directions) */
+} dgns_params;
+
+/* Structured hexahedral mesh of the box [lo, hi] with n[d] cells per direction.
+ * The cell mapping is the degree-k interpolant of the box map at each cell's LGL
+ * points (isoparametric).  A direction that is not periodic has walls at both ends. */
+typedef struct dgns_box_mesh {
+    int n[3];
+    double lo[3];
+    double hi[3];
+    int periodic[3];       /* 1 = periodic, 0 = walls */
+    int kind;              /* DGNS_MESH_* */
+    double stretch_C;      /* tanh stretching factor C for DGNS_MESH_CHANNEL */
+    double deform_amp;     /* warp amplitude a for DGNS_MESH_CURVED */
+} dgns_box_mesh;
+
+/* Thread-local text of the last error; never NULL. */
+const char* dgns_last_error(void);
+
+/* Builds the mesh, the metric terms at every quadrature point (Sec. 2.2.3, eq.
+ * IntegralsReferenceSpace), the penalty tau_IP per face (eq. TauIP_Element), and
+ * uploads them.  stream: a hipStream_t (NULL = the default stream).  Synchronous.
+ * Fails with DGNS_EINVAL if the mapping folds (det J <= 0 at a quadrature point). */
+int dgns_create(const dgns_params* params, const dgns_box_mesh* mesh, void* stream, dgns_ctx** out);
+
+/* Releases everything the context owns.  Synchronises its stream first.  NULL is a no-op. */
+int dgns_destroy(dgns_ctx* ctx);
+
+/* Number of cells, nodes per cell (k+1)^3, and DoFs 5*n_cells*(k+1)^3. */
+int dgns_sizes(const dgns_ctx* ctx, int64_t* n_cells, int64_t* nodes_per_cell, int64_t* n_dof);
+
+/* Rebinds the stream used by later calls. */
+int dgns_set_stream(dgns_ctx* ctx, void* stream);
+
+/* R = the weak-form right-hand side of eq. (WeakFormulationConservedVariables)
+ * tested against every basis function, BEFORE the inverse mass matrix:
+ * R = -F_c(U) - F_v(U) + F_rhs(U), restricted to the terms in term_mask
+ * (DGNS_TERM_*).  U, R: device, n_dof doubles each, must not alias. */
+int dgns_apply_residual(dgns_ctx* ctx, const double* U, double* R, unsigned term_mask);
+
+/* L = M^{-1} R with the exact inverse of the block-diagonal mass matrix on k+1
+ * Gauss points (Sec. 2.2.3, 2.3).  R and L may alias (in place is allowed). */
+int dgns_apply_inverse_mass(dgns_ctx* ctx, const double* R, double* L);
+
+/* L = M^{-1} (-F_c(U) - F_v(U) + F_rhs(U)), all terms (eq. SpatiallyDiscretizedProblem).
+ * t is accepted for time-dependent right-hand sides (none at present). */
+int dgns_apply_operator(dgns_ctx* ctx, const double* U, double* L, double t);
+
+/* One step of the five-stage, fourth-order 2N-storage Runge-Kutta scheme
+ * (Carpenter & Kennedy 1994) in Williamson form, one L per stage:
+ *   dU <- A_i dU + dt L(U, t + c_i dt);  U <- U + B_i dU.
+ * U is updated in place.  work: device scratch of at least 2*n_dof doubles owned
+ * by the caller (contents on return are unspecified). */
+int dgns_rk_step(dgns_ctx* ctx, double* U, double* work, double t, double dt);
+
+/* The time step of eq. (TimeStepRestrictions_Compressible):
+ * dt = min(Cr/k^e * h_min/(umax + umax/mach), D/k^f * h_min^2/nu), h_min the
+ * minimum vertex distance of the mesh.  Host result, no device work. */
+int dgns_compute_dt(const dgns_ctx* ctx, double Cr, double D, double e, double f,
+                    double umax, double mach, double* dt);
+
+/* Diagnostics of Sec. 5.2.2 computed on the device, returned to the host
+ * (synchronises the stream):
+ *   out8[0] = e_k = 1/V int |u|^2/2,      out8[1] = eps = nu/V int grad u : grad u,
+ *   out8[2] = -de_k/dt = -1/V int u.(L_m - u L_rho)/rho   (NaN if L is NULL),
+ *   out8[3] = int rho,  out8[4..6] = int rho u,  out8[7] = int rho E.
+ * e_k, eps and the rate use the n_q rule, the totals the k+1 rule (= 1^T M U).
+ * Returns DGNS_ENONFINITE (after writing out8) if any of them is not finite. */
+int dgns_diagnostics(dgns_ctx* ctx, const double* U, const double* L, double* out8);
+
+/* L2 projection of an initial state onto the DG space: U = M^{-1} (phi_i, U0)
+ * with the right-hand side on the n_q rule.  noise: NULL, or device array
+ * [3][n_cells][(k+1)^3] of values in [-1,1] used by DGNS_IC_CHANNEL for the
+ * velocity perturbation amp * u1(x2) * noise at each node (added after the
+ * projection).  U: device output. */
+int dgns_project_ic(dgns_ctx* ctx, int ic, const double* ic_params, const double* noise, double* U);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* DGNS_H */

@@ -1,0 +1,222 @@
+"""ctypes binding of libdgns.so (include/dgns.h): argument marshalling only.
+
+Every computation runs in the HIP library; tensors are torch float64 CUDA tensors
+used as device memory, and the library runs on torch's current stream unless a
+stream is given.  There is no CPU fallback: if the library is missing or no GPU
+is present, the calls raise.
+"""
+
+import ctypes
+import math
+import os
+
+import torch
+
+_PKG = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_PKG, "libdgns.so")
+
+OK, EINVAL, ENOMEM, EHIP, EUNSUPPORTED, ENONFINITE = 0, -1, -2, -3, -4, -5
+BASIS = {"LGL": 0, "GL": 1}
+PRECISION = {"fp64": 0, "fp32": 1}
+MESH = {"affine": 0, "channel": 1, "curved": 2}
+TERM_CONVECTIVE, TERM_VISCOUS, TERM_FORCE, TERM_ALL = 1, 2, 4, 7
+IC = {"taylor_green": 0, "channel": 1, "uniform": 2}
+
+
+class DgnsError(RuntimeError):
+    def __init__(self, code, msg):
+        super().__init__("dgns error %d: %s" % (code, msg))
+        self.code = code
+
+
+class Params(ctypes.Structure):
+    _fields_ = [("degree", ctypes.c_int), ("n_q", ctypes.c_int), ("basis", ctypes.c_int),
+                ("precision", ctypes.c_int), ("gamma", ctypes.c_double), ("R", ctypes.c_double),
+                ("mu", ctypes.c_double), ("lambda_", ctypes.c_double), ("rho_ref", ctypes.c_double),
+                ("body_force", ctypes.c_double * 3), ("wall_T", ctypes.c_double)]
+
+
+class BoxMesh(ctypes.Structure):
+    _fields_ = [("n", ctypes.c_int * 3), ("lo", ctypes.c_double * 3), ("hi", ctypes.c_double * 3),
+                ("periodic", ctypes.c_int * 3), ("kind", ctypes.c_int), ("stretch_C", ctypes.c_double),
+                ("deform_amp", ctypes.c_double)]
+
+
+EXPORTS = ["dgns_last_error", "dgns_create", "dgns_destroy", "dgns_sizes", "dgns_set_stream",
+           "dgns_apply_residual", "dgns_apply_inverse_mass", "dgns_apply_operator", "dgns_rk_step",
+           "dgns_compute_dt", "dgns_diagnostics", "dgns_project_ic"]
+
+_lib = None
+
+
+def load_library(path=LIB_PATH):
+    """Loads libdgns.so and declares the prototypes; raises if it is not built."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(path):
+        raise ImportError("libdgns.so is not built (%s); run python -m paper_1806_03095_amd.build" % path)
+    lib = ctypes.CDLL(path)
+    vp, dp, i64p = ctypes.c_void_p, ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_int64)
+    lib.dgns_last_error.restype = ctypes.c_char_p
+    lib.dgns_last_error.argtypes = []
+    lib.dgns_create.argtypes = [ctypes.POINTER(Params), ctypes.POINTER(BoxMesh), vp, ctypes.POINTER(vp)]
+    lib.dgns_destroy.argtypes = [vp]
+    lib.dgns_sizes.argtypes = [vp, i64p, i64p, i64p]
+    lib.dgns_set_stream.argtypes = [vp, vp]
+    lib.dgns_apply_residual.argtypes = [vp, vp, vp, ctypes.c_uint]
+    lib.dgns_apply_inverse_mass.argtypes = [vp, vp, vp]
+    lib.dgns_apply_operator.argtypes = [vp, vp, vp, ctypes.c_double]
+    lib.dgns_rk_step.argtypes = [vp, vp, vp, ctypes.c_double, ctypes.c_double]
+    lib.dgns_compute_dt.argtypes = [vp] + [ctypes.c_double] * 6 + [dp]
+    lib.dgns_diagnostics.argtypes = [vp, vp, vp, dp]
+    lib.dgns_project_ic.argtypes = [vp, ctypes.c_int, dp, vp, vp]
+    for name in EXPORTS:
+        if name != "dgns_last_error":
+            getattr(lib, name).restype = ctypes.c_int
+    _lib = lib
+    return lib
+
+
+def _check(rc):
+    if rc != OK:
+        raise DgnsError(rc, _lib.dgns_last_error().decode())
+
+
+def _ptr(t):
+    return ctypes.c_void_p(0 if t is None else t.data_ptr())
+
+
+class Operator:
+    """One discretisation (degree, n_q, basis, precision, fluid) on one box mesh.
+
+    Vectors are float64 CUDA tensors of shape (5, n_cells, (k+1)^3).
+    """
+
+    def __init__(self, degree, n_q, n, lo, hi, periodic=(1, 1, 1), kind="affine", basis="LGL",
+                 precision="fp64", gamma=1.4, R=287.0, mu=0.0, lam=0.0, rho_ref=1.0,
+                 body_force=(0.0, 0.0, 0.0), wall_T=0.0, stretch_C=1.8, deform_amp=0.0, stream=None):
+        lib = load_library()
+        if not torch.cuda.is_available():
+            raise RuntimeError("the DG operator runs on the GPU only; no GPU is visible")
+        self.lib = lib
+        self.degree, self.n_q = int(degree), int(n_q)
+        p = Params(self.degree, self.n_q, BASIS[basis], PRECISION[precision], gamma, R, mu, lam, rho_ref,
+                   (ctypes.c_double * 3)(*body_force), wall_T)
+        m = BoxMesh((ctypes.c_int * 3)(*n), (ctypes.c_double * 3)(*lo), (ctypes.c_double * 3)(*hi),
+                    (ctypes.c_int * 3)(*[int(bool(v)) for v in periodic]), MESH[kind], stretch_C, deform_amp)
+        self._stream = stream
+        h = ctypes.c_void_p()
+        _check(lib.dgns_create(ctypes.byref(p), ctypes.byref(m), self._stream_handle(), ctypes.byref(h)))
+        self.h = h
+        ne, nn, nd = ctypes.c_int64(), ctypes.c_int64(), ctypes.c_int64()
+        _check(lib.dgns_sizes(self.h, ctypes.byref(ne), ctypes.byref(nn), ctypes.byref(nd)))
+        self.n_cells, self.nodes_per_cell, self.n_dof = ne.value, nn.value, nd.value
+        self.shape = (5, self.n_cells, self.nodes_per_cell)
+        self.mu = mu
+
+    def _stream_handle(self):
+        s = self._stream if self._stream is not None else torch.cuda.current_stream()
+        return ctypes.c_void_p(s.cuda_stream)
+
+    def _bind(self):
+        _check(self.lib.dgns_set_stream(self.h, self._stream_handle()))
+
+    def _vec(self, t, name):
+        if not (isinstance(t, torch.Tensor) and t.is_cuda and t.dtype == torch.float64 and t.is_contiguous()):
+            raise TypeError("%s must be a contiguous float64 CUDA tensor" % name)
+        if t.numel() != self.n_dof:
+            raise ValueError("%s has %d entries, expected %d" % (name, t.numel(), self.n_dof))
+        return t
+
+    def empty(self):
+        return torch.empty(self.shape, dtype=torch.float64, device="cuda")
+
+    def close(self):
+        if getattr(self, "h", None):
+            self.lib.dgns_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    # -- operators ---------------------------------------------------------
+    def apply(self, U, out=None, t=0.0):
+        """L = M^{-1}(-F_c - F_v + F_rhs)(U)."""
+        self._vec(U, "U")
+        out = self.empty() if out is None else self._vec(out, "out")
+        self._bind()
+        _check(self.lib.dgns_apply_operator(self.h, _ptr(U), _ptr(out), t))
+        return out
+
+    def residual(self, U, out=None, terms=TERM_ALL):
+        """R = -F_c - F_v + F_rhs before the inverse mass matrix, restricted to `terms`."""
+        self._vec(U, "U")
+        out = self.empty() if out is None else self._vec(out, "out")
+        self._bind()
+        _check(self.lib.dgns_apply_residual(self.h, _ptr(U), _ptr(out), terms))
+        return out
+
+    def inverse_mass(self, R, out=None):
+        self._vec(R, "R")
+        out = self.empty() if out is None else self._vec(out, "out")
+        self._bind()
+        _check(self.lib.dgns_apply_inverse_mass(self.h, _ptr(R), _ptr(out)))
+        return out
+
+    def rk_step(self, U, work, t, dt):
+        """One 5-stage 2N Runge-Kutta step in place; work holds >= 2 n_dof doubles."""
+        self._vec(U, "U")
+        if not (work.is_cuda and work.dtype == torch.float64 and work.is_contiguous() and work.numel() >= 2 * self.n_dof):
+            raise ValueError("work must be a contiguous float64 CUDA tensor of >= 2 n_dof entries")
+        self._bind()
+        _check(self.lib.dgns_rk_step(self.h, _ptr(U), _ptr(work), t, dt))
+        return U
+
+    def compute_dt(self, Cr, D, e, f, umax, mach):
+        out = ctypes.c_double()
+        _check(self.lib.dgns_compute_dt(self.h, Cr, D, e, f, umax, mach, ctypes.byref(out)))
+        return out.value
+
+    def diagnostics(self, U, L=None):
+        """e_k, eps, -de_k/dt (nan without L), mass, momentum (3), energy."""
+        self._vec(U, "U")
+        if L is not None:
+            self._vec(L, "L")
+        out = (ctypes.c_double * 8)()
+        self._bind()
+        rc = self.lib.dgns_diagnostics(self.h, _ptr(U), _ptr(L), out)
+        vals = list(out)
+        res = dict(e_k=vals[0], eps=vals[1], rate=vals[2], mass=vals[3], mom=vals[4:7], energy=vals[7])
+        if rc == ENONFINITE:
+            res["nonfinite"] = True
+            return res
+        _check(rc)
+        return res
+
+    def project_ic(self, kind, params, noise=None, out=None):
+        out = self.empty() if out is None else self._vec(out, "out")
+        if noise is not None:
+            if not (noise.is_cuda and noise.dtype == torch.float64 and noise.is_contiguous()
+                    and noise.numel() == 3 * self.n_cells * self.nodes_per_cell):
+                raise ValueError("noise must be float64 CUDA of shape (3, n_cells, nodes)")
+        arr = (ctypes.c_double * 8)(*([float(v) for v in params] + [0.0] * (8 - len(params))))
+        self._bind()
+        _check(self.lib.dgns_project_ic(self.h, IC[kind], arr, _ptr(noise), _ptr(out)))
+        return out
+
+
+def taylor_green(degree, n_cells_1d, n_q=None, precision="fp64", basis="LGL", Re=1600.0, Pr=0.71,
+                 mach=0.1, gamma=1.4, R=287.0, **kw):
+    """The Taylor-Green vortex setup of the paper's Sec. 5.2.1 on [-pi, pi]^3."""
+    mu = 1.0 / Re
+    lam = mu * gamma * R / (gamma - 1.0) / Pr
+    n_q = n_q if n_q is not None else (3 * degree + 2) // 2
+    n = (n_cells_1d,) * 3 if isinstance(n_cells_1d, int) else tuple(n_cells_1d)
+    op = Operator(degree, n_q, n, (-math.pi,) * 3, (math.pi,) * 3, basis=basis, precision=precision,
+                  gamma=gamma, R=R, mu=mu, lam=lam, **kw)
+    op.mach = mach
+    return op

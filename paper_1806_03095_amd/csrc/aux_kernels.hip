@@ -1,0 +1,280 @@
+// Memory-bound and setup kernels around the DG operator: the low-storage
+// Runge-Kutta stage update (paper Sec. 2.4), the kinetic-energy / dissipation
+// diagnostics (Sec. 5.2.2) and the L2 projection of the initial states of
+// Sec. 5.2.1 (Taylor-Green) and Sec. 5.3.1 (channel).
+
+#include "dg_common.h"
+#include "dg_kernels.h"
+#include "dgns.h"
+
+namespace dgns {
+
+// ------------------------------------------------------------------ LSRK update
+// dU <- A dU + dt L;  U <- U + B dU.  With A == 0 the old dU is not read (it may
+// hold anything, including NaN, on the first stage).
+template <bool FIRST>
+__global__ void __launch_bounds__(256) rk_update_kernel(double* __restrict__ U, double* __restrict__ dU,
+                                                        const double* __restrict__ L, int64_t n2, double A,
+                                                        double B, double dt) {
+    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+    double2* U2 = reinterpret_cast<double2*>(U);
+    double2* dU2 = reinterpret_cast<double2*>(dU);
+    const double2* L2 = reinterpret_cast<const double2*>(L);
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n2; i += stride) {
+        const double2 l = L2[i];
+        double2 d;
+        if (FIRST) {
+            d.x = dt * l.x;
+            d.y = dt * l.y;
+        } else {
+            const double2 o = dU2[i];
+            d.x = A * o.x + dt * l.x;
+            d.y = A * o.y + dt * l.y;
+        }
+        double2 u = U2[i];
+        u.x += B * d.x;
+        u.y += B * d.y;
+        dU2[i] = d;
+        U2[i] = u;
+    }
+}
+
+__global__ void rk_update_tail(double* U, double* dU, const double* L, int64_t i, double A, double B, double dt,
+                               int first) {
+    const double d = first ? dt * L[i] : A * dU[i] + dt * L[i];
+    dU[i] = d;
+    U[i] += B * d;
+}
+
+int launch_rk_update(double* U, double* dU, const double* L, int64_t n, double A, double B, double dt,
+                     hipStream_t st) {
+    const int64_t n2 = n / 2;
+    if (n2 > 0) {
+        // enough waves to fill 256 CUs several times over, grid-stride beyond that
+        int64_t blocks = (n2 + 255) / 256;
+        if (blocks > 256 * 64) blocks = 256 * 64;
+        if (A == 0.0)
+            hipLaunchKernelGGL(rk_update_kernel<true>, dim3((unsigned)blocks), dim3(256), 0, st, U, dU, L, n2, A, B, dt);
+        else
+            hipLaunchKernelGGL(rk_update_kernel<false>, dim3((unsigned)blocks), dim3(256), 0, st, U, dU, L, n2, A, B, dt);
+    }
+    if (n % 2)
+        hipLaunchKernelGGL(rk_update_tail, dim3(1), dim3(1), 0, st, U, dU, L, n - 1, A, B, dt, A == 0.0 ? 1 : 0);
+    return hipGetLastError() == hipSuccess ? 0 : -1;
+}
+
+// ------------------------------------------------------------------ diagnostics
+// Per cell: [0] int |u|^2/2, [1] int grad u : grad u, [2] -int u.(L_m - u L_rho)/rho,
+// [3..7] int U (k+1 rule), [8] volume.  One workgroup per cell, direct evaluation
+// of the nodal expansion at each point (not on the hot path).
+constexpr int kDiag = 9;
+
+__device__ inline double block_sum(double v, double* red) {
+    const int tid = threadIdx.x;
+    red[tid] = v;
+    __syncthreads();
+    for (int s = blockDim.x / 2; s > 0; s >>= 1) {
+        if (tid < s) red[tid] += red[tid + s];
+        __syncthreads();
+    }
+    const double r = red[0];
+    __syncthreads();
+    return r;
+}
+
+__global__ void __launch_bounds__(256) diag_cell_kernel(OpArgs a, const Tables1D* __restrict__ tp, const double* L,
+                                                        double* partial, int gen) {
+    const Tables1D& t = *tp;
+    const int N = t.n, Q = t.q, N3 = N * N * N, Q3 = Q * Q * Q;
+    const int64_t e = blockIdx.x;
+    const int64_t cs = a.ncell * N3;
+    __shared__ double red[256];
+    double acc[kDiag];
+    for (int m = 0; m < kDiag; ++m) acc[m] = 0;
+    double Jc[9], detJ = 1;
+    if (!gen) {
+        for (int m = 0; m < 9; ++m) Jc[m] = a.cell_metric[e * 10 + m];
+        detJ = a.cell_metric[e * 10 + 9];
+    }
+    for (int p = threadIdx.x; p < Q3; p += blockDim.x) {
+        const int p0 = p % Q, p1 = (p / Q) % Q, p2 = p / (Q * Q);
+        double U[5] = {0, 0, 0, 0, 0}, Gr[5][3] = {}, Lv[4] = {0, 0, 0, 0};
+        for (int i = 0; i < N3; ++i) {
+            const int a0 = i % N, a1 = (i / N) % N, a2 = i / (N * N);
+            const double v0 = t.S[p0][a0], v1 = t.S[p1][a1], v2 = t.S[p2][a2];
+            const double phi = v0 * v1 * v2;
+            const double g0 = t.D[p0][a0] * v1 * v2, g1 = v0 * t.D[p1][a1] * v2, g2 = v0 * v1 * t.D[p2][a2];
+            for (int c = 0; c < 5; ++c) {
+                const double x = a.U[c * cs + e * N3 + i];
+                U[c] += phi * x;
+                Gr[c][0] += g0 * x;
+                Gr[c][1] += g1 * x;
+                Gr[c][2] += g2 * x;
+            }
+            if (L)
+                for (int c = 0; c < 4; ++c) Lv[c] += phi * L[c * cs + e * N3 + i];
+        }
+        double J[9], jxw;
+        if (gen) {
+            for (int m = 0; m < 9; ++m) J[m] = a.cell_metric[(e * 10 + m) * Q3 + p];
+            jxw = a.cell_metric[(e * 10 + 9) * Q3 + p];
+        } else {
+            for (int m = 0; m < 9; ++m) J[m] = Jc[m];
+            jxw = detJ * t.w[p0] * t.w[p1] * t.w[p2];
+        }
+        const double rinv = 1.0 / U[0];
+        const double u[3] = {U[1] * rinv, U[2] * rinv, U[3] * rinv};
+        double gg = 0;
+        for (int al = 0; al < 3; ++al)
+            for (int j = 0; j < 3; ++j) {
+                double gm = 0, gr = 0;
+                for (int d = 0; d < 3; ++d) {
+                    gm += J[d * 3 + j] * Gr[1 + al][d];
+                    gr += J[d * 3 + j] * Gr[0][d];
+                }
+                const double du = (gm - u[al] * gr) * rinv;
+                gg += du * du;
+            }
+        acc[0] += 0.5 * (u[0] * u[0] + u[1] * u[1] + u[2] * u[2]) * jxw;
+        acc[1] += gg * jxw;
+        if (L) {
+            double r = 0;
+            for (int al = 0; al < 3; ++al) r += u[al] * (Lv[1 + al] - u[al] * Lv[0]) * rinv;
+            acc[2] -= r * jxw;
+        }
+        acc[8] += jxw;
+    }
+    // conserved totals with the mass rule
+    for (int p = threadIdx.x; p < N3; p += blockDim.x) {
+        const int p0 = p % N, p1 = (p / N) % N, p2 = p / (N * N);
+        double U[5] = {0, 0, 0, 0, 0};
+        for (int i = 0; i < N3; ++i) {
+            const int a0 = i % N, a1 = (i / N) % N, a2 = i / (N * N);
+            const double phi = t.Sm[p0][a0] * t.Sm[p1][a1] * t.Sm[p2][a2];
+            for (int c = 0; c < 5; ++c) U[c] += phi * a.U[c * cs + e * N3 + i];
+        }
+        const double jxw = gen ? a.mass_jxw[e * N3 + p] : detJ * t.wm[p0] * t.wm[p1] * t.wm[p2];
+        for (int c = 0; c < 5; ++c) acc[3 + c] += U[c] * jxw;
+    }
+    for (int m = 0; m < kDiag; ++m) {
+        const double s = block_sum(acc[m], red);
+        if (threadIdx.x == 0) partial[e * kDiag + m] = s;
+    }
+}
+
+__global__ void __launch_bounds__(256) diag_total_kernel(const double* partial, int64_t ncell, double* total) {
+    __shared__ double red[256];
+    for (int m = 0; m < kDiag; ++m) {
+        double s = 0;
+        for (int64_t e = threadIdx.x; e < ncell; e += blockDim.x) s += partial[e * kDiag + m];
+        const double r = block_sum(s, red);
+        if (threadIdx.x == 0) total[m] = r;
+    }
+}
+
+int launch_diagnostics(const OpArgs& a, const Tables1D* t_dev, const double* L, double* partial, double* total, bool gen,
+                       hipStream_t st) {
+    hipLaunchKernelGGL(diag_cell_kernel, dim3((unsigned)a.ncell), dim3(256), 0, st, a, t_dev, L, partial, gen ? 1 : 0);
+    hipLaunchKernelGGL(diag_total_kernel, dim3(1), dim3(256), 0, st, partial, a.ncell, total);
+    return hipGetLastError() == hipSuccess ? 0 : -1;
+}
+
+// ------------------------------------------------------------------ initial states
+__device__ inline void initial_state(int ic, const double* q, double gamma, double R, const double x[3], double U[5]) {
+    double rho, u[3], p;
+    if (ic == DGNS_IC_TAYLOR_GREEN) {
+        const double U0 = q[0], L = q[1], M = q[2], rho0 = q[3];
+        const double c0 = U0 / M, T0 = c0 * c0 / (gamma * R), p0 = rho0 * R * T0;
+        const double x1 = x[0] / L, x2 = x[1] / L, x3 = x[2] / L;
+        u[0] = U0 * sin(x1) * cos(x2) * cos(x3);
+        u[1] = -U0 * cos(x1) * sin(x2) * cos(x3);
+        u[2] = 0.0;
+        p = p0 + rho0 * U0 * U0 / 16.0 * (cos(2.0 * x1) + cos(2.0 * x2)) * (cos(2.0 * x3) + 2.0);
+        rho = p / (R * T0);
+    } else if (ic == DGNS_IC_CHANNEL) {
+        const double umax = q[0], M = q[1], pw = q[2];
+        const double c = umax / M, T0 = c * c / (gamma * R);
+        rho = 1.0;
+        u[0] = umax * (1.0 - pow(fabs(x[1]), pw));
+        u[1] = u[2] = 0.0;
+        p = rho * R * T0;
+    } else {
+        rho = q[0];
+        u[0] = q[1];
+        u[1] = q[2];
+        u[2] = q[3];
+        p = q[4];
+    }
+    U[0] = rho;
+    U[1] = rho * u[0];
+    U[2] = rho * u[1];
+    U[3] = rho * u[2];
+    U[4] = p / (gamma - 1.0) + 0.5 * rho * (u[0] * u[0] + u[1] * u[1] + u[2] * u[2]);
+}
+
+// out_i = sum_p phi_i(x_p) |det J| w_p U0(x(x_p)) with the n_q rule (before M^{-1}).
+__global__ void __launch_bounds__(256) ic_rhs_kernel(OpArgs a, const Tables1D* __restrict__ tp, const double* geo, int ic,
+                                                     const double* icp_d, double* out, int gen) {
+    extern __shared__ double sv[];   // [5][Q^3]
+    const Tables1D& t = *tp;
+    const int N = t.n, Q = t.q, N3 = N * N * N, Q3 = Q * Q * Q;
+    const int64_t e = blockIdx.x;
+    double q[8];
+    for (int m = 0; m < 8; ++m) q[m] = icp_d[m];
+    for (int p = threadIdx.x; p < Q3; p += blockDim.x) {
+        const int p0 = p % Q, p1 = (p / Q) % Q, p2 = p / (Q * Q);
+        double x[3] = {0, 0, 0};
+        for (int i = 0; i < N3; ++i) {
+            const int a0 = i % N, a1 = (i / N) % N, a2 = i / (N * N);
+            const double g = t.Sg[p0][a0] * t.Sg[p1][a1] * t.Sg[p2][a2];
+            for (int c = 0; c < 3; ++c) x[c] += g * geo[(e * 3 + c) * N3 + i];
+        }
+        double U[5];
+        initial_state(ic, q, a.gamma, a.R, x, U);
+        const double jxw = gen ? a.cell_metric[(e * 10 + 9) * Q3 + p] : a.cell_metric[e * 10 + 9] * t.w[p0] * t.w[p1] * t.w[p2];
+        for (int c = 0; c < 5; ++c) sv[c * Q3 + p] = U[c] * jxw;
+    }
+    __syncthreads();
+    const int64_t cs = a.ncell * N3;
+    for (int it = threadIdx.x; it < 5 * N3; it += blockDim.x) {
+        const int c = it / N3, i = it % N3;
+        const int a0 = i % N, a1 = (i / N) % N, a2 = i / (N * N);
+        double s = 0;
+        for (int p = 0; p < Q3; ++p) {
+            const int p0 = p % Q, p1 = (p / Q) % Q, p2 = p / (Q * Q);
+            s += t.S[p0][a0] * t.S[p1][a1] * t.S[p2][a2] * sv[c * Q3 + p];
+        }
+        out[c * cs + e * N3 + i] = s;
+    }
+}
+
+int launch_ic_rhs(const OpArgs& a, const Tables1D& t, const Tables1D* t_dev, const double* geo_nodes, int ic,
+                  const double* icp, double* out, bool gen, hipStream_t st) {
+    const size_t shm = sizeof(double) * 5 * t.q * t.q * t.q;
+    hipLaunchKernelGGL(ic_rhs_kernel, dim3((unsigned)a.ncell), dim3(256), shm, st, a, t_dev, geo_nodes, ic, icp, out,
+                       gen ? 1 : 0);
+    return hipGetLastError() == hipSuccess ? 0 : -1;
+}
+
+__global__ void channel_perturb_kernel(double* U, const double* X, const double* noise, int64_t n, double umax,
+                                       double pw, double amp, double gamma, double R) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    const double rho = U[i];
+    double u[3] = {U[n + i] / rho, U[2 * n + i] / rho, U[3 * n + i] / rho};
+    const double T = (gamma - 1.0) * (U[4 * n + i] - 0.5 * rho * (u[0] * u[0] + u[1] * u[1] + u[2] * u[2])) / (rho * R);
+    const double base = umax * (1.0 - pow(fabs(X[n + i]), pw));
+    for (int c = 0; c < 3; ++c) u[c] += amp * base * noise[c * n + i];
+    for (int c = 0; c < 3; ++c) U[(1 + c) * n + i] = rho * u[c];
+    U[4 * n + i] = rho * (R / (gamma - 1.0) * T + 0.5 * (u[0] * u[0] + u[1] * u[1] + u[2] * u[2]));
+}
+
+int launch_channel_perturb(double* U, const double* node_x, const double* noise, int64_t ncell, int n3, double umax,
+                           double power, double amp, double gamma, double R, hipStream_t st) {
+    const int64_t n = ncell * n3;
+    hipLaunchKernelGGL(channel_perturb_kernel, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, U, node_x, noise, n,
+                       umax, power, amp, gamma, R);
+    return hipGetLastError() == hipSuccess ? 0 : -1;
+}
+
+}  // namespace dgns

@@ -1,0 +1,188 @@
+// Shared definitions of the DG operator kernels and the host library.
+//
+// Pointwise physics of the compressible Navier-Stokes equations (paper Sec. 2.1):
+// conserved U = (rho, rho u, rho E); Newtonian stress with zero bulk viscosity,
+// Fourier heat flux, ideal gas, E = c_v T + |u|^2/2; fluxes of eq.
+// (CompressibleNavierStokesFluxes).  Numerical fluxes of Sec. 2.2.2: local
+// Lax-Friedrichs and symmetric interior penalty.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace dgns {
+
+constexpr int kMaxN = 8;    // nodes per direction, k <= 7
+constexpr int kMaxQ = 12;   // quadrature points per direction
+constexpr int kBlock = 256; // threads per workgroup of the cell kernels
+
+// 1D tables of one (k, n_q, basis) combination, float64 master copy.
+struct Tables1D {
+    int n, q;
+    double S[kMaxQ][kMaxN];   // l_i(x_p) at the n_q Gauss points of the flux rule
+    double D[kMaxQ][kMaxN];   // l_i'(x_p)
+    double w[kMaxQ];          // Gauss weights on [0,1]
+    double fv[2][kMaxN];      // l_i(0), l_i(1)
+    double fd[2][kMaxN];      // l_i'(0), l_i'(1)
+    double Sm[kMaxN][kMaxN];  // l_i(x^m_p) at the k+1 Gauss points of the mass rule
+    double Smi[kMaxN][kMaxN]; // inverse of Sm
+    double wm[kMaxN];         // mass-rule weights
+    double Sg[kMaxQ][kMaxN];  // geometry (LGL) basis l^g_i(x_p) at the flux points
+};
+
+// Exactly sized copy in the operator's working precision, passed by value as a
+// kernel argument so that every entry is a wave-uniform (scalar) operand.
+template <int N, int Q, typename Real>
+struct KTab {
+    Real S[Q][N];
+    Real D[Q][N];
+    Real w[Q];
+    Real fv[2][N];
+    Real fd[2][N];
+};
+
+template <int N, typename Real>
+struct MTab {
+    Real Sm[N][N];
+    Real Smi[N][N];
+    Real wm[N];
+};
+
+// Metric storage.
+//  affine : cell_metric[e*10 + m], m = 0..8 J^{-1} row-major (row = reference
+//           direction), m = 9 det J; face normal/area follow from J^{-1}.
+//  general: cell_metric[(e*10 + m)*Q^3 + p], m = 0..8 J^{-1}, m = 9 |det J| w_p;
+//           face_data[d][(f*22 + m)*Q^2 + r]: m = 0..2 unit normal pointing from
+//           the lower cell (minus) to the upper cell (plus) in direction d, m = 3
+//           dA * w_r, m = 4..12 J^{-1} of the minus cell, 13..21 of the plus cell;
+//           mass_jxw[e*N^3 + p] = |det J| w at the mass-rule points.
+// Face numbering in direction d: position pos = i_d (lower face of cell i_d, 0..n_d),
+// f = pos + (n_d + 1) * (i_t0 + n_t0 * i_t1), t0 < t1 the two other directions.
+struct OpArgs {
+    const double* U;
+    double* out;
+    int64_t ncell;
+    int n[3];
+    int periodic[3];
+    const double* cell_metric;
+    const double* face_data[3];
+    const double* tau_face[3];
+    const double* mass_jxw;
+    double gamma, R, mu, lam, wall_T;
+    double force[3];
+    unsigned terms;
+    int fuse_minv;
+};
+
+template <typename Real>
+struct Phys {
+    Real gamma, gm1, R, mu, lam, inv_cv, wall_T, cv;
+};
+
+template <typename Real>
+__host__ __device__ inline Phys<Real> make_phys(const OpArgs& a) {
+    Phys<Real> p;
+    p.gamma = (Real)a.gamma;
+    p.gm1 = (Real)(a.gamma - 1.0);
+    p.R = (Real)a.R;
+    p.mu = (Real)a.mu;
+    p.lam = (Real)a.lam;
+    p.cv = (Real)(a.R / (a.gamma - 1.0));
+    p.inv_cv = (Real)((a.gamma - 1.0) / a.R);
+    p.wall_T = (Real)a.wall_T;
+    return p;
+}
+
+// Viscous flux F_v(U, G)[c][j] for a conserved state U and a conserved-variable
+// gradient G[c][j] = dU_c/dx_j; linear in G.  Row 0 is identically zero.
+template <typename Real>
+__device__ __forceinline__ void viscous_flux(const Real U[5], const Real G[5][3], const Phys<Real>& ph,
+                                             Real F[5][3]) {
+    const Real rinv = Real(1) / U[0];
+    const Real u0 = U[1] * rinv, u1 = U[2] * rinv, u2 = U[3] * rinv;
+    const Real E = U[4] * rinv;
+    Real gu[3][3];
+#pragma unroll
+    for (int j = 0; j < 3; ++j) {
+        gu[0][j] = (G[1][j] - u0 * G[0][j]) * rinv;
+        gu[1][j] = (G[2][j] - u1 * G[0][j]) * rinv;
+        gu[2][j] = (G[3][j] - u2 * G[0][j]) * rinv;
+    }
+    const Real div = gu[0][0] + gu[1][1] + gu[2][2];
+    const Real mu = ph.mu;
+    const Real two_thirds_div = Real(2.0 / 3.0) * div;
+    Real tau[3][3];
+#pragma unroll
+    for (int a = 0; a < 3; ++a)
+#pragma unroll
+        for (int j = 0; j < 3; ++j)
+            tau[a][j] = mu * (gu[a][j] + gu[j][a] - (a == j ? two_thirds_div : Real(0)));
+    const Real lam_cv = ph.lam * ph.inv_cv;
+#pragma unroll
+    for (int j = 0; j < 3; ++j) {
+        // dT/dx_j = ((d(rho E)/dx_j - E drho/dx_j)/rho - u . du/dx_j) / c_v
+        const Real gE = (G[4][j] - E * G[0][j]) * rinv;
+        const Real gT = gE - (u0 * gu[0][j] + u1 * gu[1][j] + u2 * gu[2][j]);
+        F[0][j] = Real(0);
+        F[1][j] = tau[0][j];
+        F[2][j] = tau[1][j];
+        F[3][j] = tau[2][j];
+        F[4][j] = tau[j][0] * u0 + tau[j][1] * u1 + tau[j][2] * u2 + lam_cv * gT;
+    }
+}
+
+template <typename Real>
+__device__ __forceinline__ Real pressure(const Real U[5], const Phys<Real>& ph) {
+    const Real rinv = Real(1) / U[0];
+    return ph.gm1 * (U[4] - Real(0.5) * (U[1] * U[1] + U[2] * U[2] + U[3] * U[3]) * rinv);
+}
+
+// Convective flux F_c(U)[c][j].
+template <typename Real>
+__device__ __forceinline__ void convective_flux(const Real U[5], const Phys<Real>& ph, Real F[5][3]) {
+    const Real rinv = Real(1) / U[0];
+    const Real u[3] = {U[1] * rinv, U[2] * rinv, U[3] * rinv};
+    const Real p = ph.gm1 * (U[4] - Real(0.5) * (U[1] * u[0] + U[2] * u[1] + U[3] * u[2]));
+#pragma unroll
+    for (int j = 0; j < 3; ++j) {
+        F[0][j] = U[1 + j];
+        F[1][j] = U[1] * u[j] + (j == 0 ? p : Real(0));
+        F[2][j] = U[2] * u[j] + (j == 1 ? p : Real(0));
+        F[3][j] = U[3] * u[j] + (j == 2 ? p : Real(0));
+        F[4][j] = (U[4] + p) * u[j];
+    }
+}
+
+// F_c(U) . n and the LLF wave speed |u| + c, c = sqrt(|gamma p / rho|).
+template <typename Real>
+__device__ __forceinline__ Real convective_normal(const Real U[5], const Real n[3], const Phys<Real>& ph,
+                                                  Real Fn[5]) {
+    const Real rinv = Real(1) / U[0];
+    const Real u0 = U[1] * rinv, u1 = U[2] * rinv, u2 = U[3] * rinv;
+    const Real uu = u0 * u0 + u1 * u1 + u2 * u2;
+    const Real p = ph.gm1 * (U[4] - Real(0.5) * U[0] * uu);
+    const Real un = u0 * n[0] + u1 * n[1] + u2 * n[2];
+    Fn[0] = U[0] * un;
+    Fn[1] = U[1] * un + p * n[0];
+    Fn[2] = U[2] * un + p * n[1];
+    Fn[3] = U[3] * un + p * n[2];
+    Fn[4] = (U[4] + p) * un;
+    return sqrt(uu) + sqrt(fabs(ph.gamma * p * rinv));
+}
+
+// Exterior state at an isothermal no-slip wall: rho+ = rho-, u+ = -u-,
+// T+ = 2 T_wall - T-, E+ = c_v T+ + |u|^2/2 (gradients are copied by the caller).
+template <typename Real>
+__device__ __forceinline__ void wall_mirror(const Real Um[5], const Phys<Real>& ph, Real Up[5]) {
+    const Real rho = Um[0];
+    const Real ke = Real(0.5) * (Um[1] * Um[1] + Um[2] * Um[2] + Um[3] * Um[3]) / rho;
+    const Real T = ph.gm1 * (Um[4] - ke) / (rho * ph.R);
+    const Real Tp = Real(2) * ph.wall_T - T;
+    Up[0] = rho;
+    Up[1] = -Um[1];
+    Up[2] = -Um[2];
+    Up[3] = -Um[3];
+    Up[4] = rho * ph.cv * Tp + ke;
+}
+
+}  // namespace dgns

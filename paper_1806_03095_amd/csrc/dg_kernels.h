@@ -1,0 +1,50 @@
+// Launchers of the DG kernels (one translation unit per polynomial degree).
+// Each returns 0 on success, 1 if the (degree, n_q) pair has no compiled kernel,
+// -1 if the launch failed.
+#pragma once
+
+#include "dg_common.h"
+
+namespace dgns {
+
+int launch_operator_k1(const OpArgs& a, const Tables1D& t, bool fp32, bool gen, hipStream_t st);
+int launch_inverse_mass_k1(const double* R, double* L, int64_t ncell, const double* cm, const double* mj,
+                            const Tables1D& t, bool fp32, bool gen, hipStream_t st);
+int launch_operator_k2(const OpArgs& a, const Tables1D& t, bool fp32, bool gen, hipStream_t st);
+int launch_inverse_mass_k2(const double* R, double* L, int64_t ncell, const double* cm, const double* mj,
+                            const Tables1D& t, bool fp32, bool gen, hipStream_t st);
+int launch_operator_k3(const OpArgs& a, const Tables1D& t, bool fp32, bool gen, hipStream_t st);
+int launch_inverse_mass_k3(const double* R, double* L, int64_t ncell, const double* cm, const double* mj,
+                            const Tables1D& t, bool fp32, bool gen, hipStream_t st);
+int launch_operator_k4(const OpArgs& a, const Tables1D& t, bool fp32, bool gen, hipStream_t st);
+int launch_inverse_mass_k4(const double* R, double* L, int64_t ncell, const double* cm, const double* mj,
+                            const Tables1D& t, bool fp32, bool gen, hipStream_t st);
+int launch_operator_k5(const OpArgs& a, const Tables1D& t, bool fp32, bool gen, hipStream_t st);
+int launch_inverse_mass_k5(const double* R, double* L, int64_t ncell, const double* cm, const double* mj,
+                            const Tables1D& t, bool fp32, bool gen, hipStream_t st);
+int launch_operator_k6(const OpArgs& a, const Tables1D& t, bool fp32, bool gen, hipStream_t st);
+int launch_inverse_mass_k6(const double* R, double* L, int64_t ncell, const double* cm, const double* mj,
+                            const Tables1D& t, bool fp32, bool gen, hipStream_t st);
+int launch_operator_k7(const OpArgs& a, const Tables1D& t, bool fp32, bool gen, hipStream_t st);
+int launch_inverse_mass_k7(const double* R, double* L, int64_t ncell, const double* cm, const double* mj,
+                            const Tables1D& t, bool fp32, bool gen, hipStream_t st);
+
+// (degree, n_q) pairs with compiled operator kernels
+constexpr int kSupported[][2] = {{1, 2}, {1, 3}, {2, 3}, {2, 4}, {3, 4}, {3, 5}, {3, 6}, {4, 5}, {4, 6}, {4, 7}, {5, 6}, {5, 8}, {6, 7}, {6, 10}, {7, 8}, {7, 11}};
+
+// LSRK stage update dU <- A dU + dt L; U <- U + B dU (A == 0: dU <- dt L).
+int launch_rk_update(double* U, double* dU, const double* L, int64_t n, double A, double B, double dt, hipStream_t st);
+
+// Per-cell diagnostic partial sums and their deterministic total.
+int launch_diagnostics(const OpArgs& a, const Tables1D* t_dev, const double* L, double* partial, double* total,
+                       bool gen, hipStream_t st);
+
+// L2 projection right-hand side of an analytic initial state, U_rhs = (phi_i, U0).
+int launch_ic_rhs(const OpArgs& a, const Tables1D& t, const Tables1D* t_dev, const double* geo_nodes, int ic,
+                  const double* icp, double* out, bool gen, hipStream_t st);
+
+// Channel perturbation at the nodes: u_a += amp * u1_lam(x2) * noise_a, T kept.
+int launch_channel_perturb(double* U, const double* node_x, const double* noise, int64_t ncell, int n3,
+                           double umax, double power, double amp, double gamma, double R, hipStream_t st);
+
+}  // namespace dgns

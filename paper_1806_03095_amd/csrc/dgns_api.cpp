@@ -1,0 +1,365 @@
+// Host side of the library: the C ABI of include/dgns.h, context lifetime, the
+// 1D rules and bases, mesh and geometry setup, and kernel launches.
+//
+// Geometry (paper Sec. 2.2.1, 2.2.3 eq. IntegralsReferenceSpace): each cell is the
+// image of [0,1]^3 under the degree-k interpolant of the box map at its LGL
+// points; J = dx/dxi, and the metric terms J^{-1}, |det J| w at every quadrature
+// point, the face normal and |det J| |J^{-T} n_xi| w at every face point.
+// Penalty (eq. TauIP_Element): tau_e = nu (k+1)^2 (A_interior/2 + A_boundary)/V_e,
+// interior faces take the max over both cells.
+
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <string>
+#include <vector>
+
+#include "dg_common.h"
+#include "dg_kernels.h"
+#include "dgns.h"
+#include "setup.h"
+
+using namespace dgns;
+
+namespace {
+
+thread_local std::string g_err = "no error";
+
+int fail(int code, const char* fmt, ...) {
+    char buf[512];
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(buf, sizeof buf, fmt, ap);
+    va_end(ap);
+    g_err = buf;
+    return code;
+}
+
+#define HIP_TRY(expr)                                                                              \
+    do {                                                                                           \
+        hipError_t _e = (expr);                                                                    \
+        if (_e != hipSuccess) return fail(DGNS_EHIP, "%s: %s", #expr, hipGetErrorString(_e));      \
+    } while (0)
+
+}  // namespace
+
+// ---------------------------------------------------------------- context
+struct dgns_ctx {
+    dgns_params prm;
+    dgns_box_mesh msh;
+    hipStream_t stream = nullptr;
+    bool gen = false;   // per-point metric (curved / stretched meshes)
+    bool fp32 = false;
+    int k = 0, n = 0, q = 0;
+    int64_t ncell = 0, n3 = 0, ndof = 0;
+    double h_min = 0;
+    Tables1D tab;
+    std::vector<double> geo;      // [E][3][N3] geometry nodes (LGL)
+    std::vector<double> node_x;   // [3][E][N3] coordinates of the basis nodes
+    double* d_metric = nullptr;
+    double* d_face[3] = {nullptr, nullptr, nullptr};
+    double* d_tau[3] = {nullptr, nullptr, nullptr};
+    double* d_mass_jxw = nullptr;
+    double* d_partial = nullptr;
+    double* d_total = nullptr;
+    Tables1D* d_tab = nullptr;
+};
+
+namespace {
+
+template <typename T>
+int upload(const std::vector<T>& h, T** d) {
+    HIP_TRY(hipMalloc((void**)d, sizeof(T) * std::max<size_t>(1, h.size())));
+    if (!h.empty()) HIP_TRY(hipMemcpy(*d, h.data(), sizeof(T) * h.size(), hipMemcpyHostToDevice));
+    return 0;
+}
+
+void free_ctx(dgns_ctx* c) {
+    hipFree(c->d_metric);
+    for (int d = 0; d < 3; ++d) {
+        hipFree(c->d_face[d]);
+        hipFree(c->d_tau[d]);
+    }
+    hipFree(c->d_mass_jxw);
+    hipFree(c->d_partial);
+    hipFree(c->d_total);
+    hipFree(c->d_tab);
+}
+
+OpArgs make_args(const dgns_ctx* c, const double* U, double* out, unsigned terms, int fuse) {
+    OpArgs a;
+    std::memset(&a, 0, sizeof a);
+    a.U = U;
+    a.out = out;
+    a.ncell = c->ncell;
+    for (int d = 0; d < 3; ++d) {
+        a.n[d] = c->msh.n[d];
+        a.periodic[d] = c->msh.periodic[d] ? 1 : 0;
+        a.face_data[d] = c->d_face[d];
+        a.tau_face[d] = c->d_tau[d];
+        a.force[d] = c->prm.body_force[d];
+    }
+    a.cell_metric = c->d_metric;
+    a.mass_jxw = c->d_mass_jxw;
+    a.gamma = c->prm.gamma;
+    a.R = c->prm.R;
+    a.mu = c->prm.mu;
+    a.lam = c->prm.lambda;
+    a.wall_T = c->prm.wall_T;
+    a.terms = terms;
+    a.fuse_minv = fuse;
+    return a;
+}
+
+int dispatch_operator(const dgns_ctx* c, const OpArgs& a) {
+    int rc = 1;
+    switch (c->k) {
+        case 1: rc = launch_operator_k1(a, c->tab, c->fp32, c->gen, c->stream); break;
+        case 2: rc = launch_operator_k2(a, c->tab, c->fp32, c->gen, c->stream); break;
+        case 3: rc = launch_operator_k3(a, c->tab, c->fp32, c->gen, c->stream); break;
+        case 4: rc = launch_operator_k4(a, c->tab, c->fp32, c->gen, c->stream); break;
+        case 5: rc = launch_operator_k5(a, c->tab, c->fp32, c->gen, c->stream); break;
+        case 6: rc = launch_operator_k6(a, c->tab, c->fp32, c->gen, c->stream); break;
+        case 7: rc = launch_operator_k7(a, c->tab, c->fp32, c->gen, c->stream); break;
+    }
+    if (rc == 1) return fail(DGNS_EUNSUPPORTED, "no operator kernel for degree %d, n_q %d", c->k, c->q);
+    if (rc != 0) return fail(DGNS_EHIP, "operator launch failed: %s", hipGetErrorString(hipGetLastError()));
+    return 0;
+}
+
+int dispatch_minv(const dgns_ctx* c, const double* R, double* L) {
+    int rc = 1;
+    const double* cm = c->d_metric;
+    const double* mj = c->d_mass_jxw;
+    switch (c->k) {
+        case 1: rc = launch_inverse_mass_k1(R, L, c->ncell, cm, mj, c->tab, c->fp32, c->gen, c->stream); break;
+        case 2: rc = launch_inverse_mass_k2(R, L, c->ncell, cm, mj, c->tab, c->fp32, c->gen, c->stream); break;
+        case 3: rc = launch_inverse_mass_k3(R, L, c->ncell, cm, mj, c->tab, c->fp32, c->gen, c->stream); break;
+        case 4: rc = launch_inverse_mass_k4(R, L, c->ncell, cm, mj, c->tab, c->fp32, c->gen, c->stream); break;
+        case 5: rc = launch_inverse_mass_k5(R, L, c->ncell, cm, mj, c->tab, c->fp32, c->gen, c->stream); break;
+        case 6: rc = launch_inverse_mass_k6(R, L, c->ncell, cm, mj, c->tab, c->fp32, c->gen, c->stream); break;
+        case 7: rc = launch_inverse_mass_k7(R, L, c->ncell, cm, mj, c->tab, c->fp32, c->gen, c->stream); break;
+    }
+    if (rc == 1) return fail(DGNS_EUNSUPPORTED, "no inverse-mass kernel for degree %d", c->k);
+    if (rc != 0) return fail(DGNS_EHIP, "inverse-mass launch failed");
+    return 0;
+}
+
+bool aligned8(const void* p) { return ((uintptr_t)p & 7u) == 0; }
+
+bool overlap(const double* a, const double* b, int64_t n) { return a < b + n && b < a + n; }
+
+}  // namespace
+
+// ---------------------------------------------------------------- C ABI
+extern "C" {
+
+const char* dgns_last_error(void) { return g_err.c_str(); }
+
+int dgns_create(const dgns_params* prm, const dgns_box_mesh* msh, void* stream, dgns_ctx** out) {
+    if (!prm || !msh || !out) return fail(DGNS_EINVAL, "null argument");
+    *out = nullptr;
+    if (prm->degree < 1 || prm->degree > 7) return fail(DGNS_EINVAL, "degree %d outside 1..7", prm->degree);
+    if (prm->n_q < 1 || prm->n_q > kMaxQ) return fail(DGNS_EINVAL, "n_q %d outside 1..%d", prm->n_q, kMaxQ);
+    if (prm->basis != DGNS_BASIS_LGL && prm->basis != DGNS_BASIS_GL) return fail(DGNS_EINVAL, "unknown basis");
+    if (prm->precision != DGNS_FP64 && prm->precision != DGNS_FP32) return fail(DGNS_EINVAL, "unknown precision");
+    if (!(prm->gamma > 1) || !(prm->R > 0) || !(prm->mu >= 0) || !(prm->lambda >= 0) || !(prm->rho_ref > 0))
+        return fail(DGNS_EINVAL, "fluid parameters out of range");
+    if (msh->kind < 0 || msh->kind > 2) return fail(DGNS_EINVAL, "unknown mesh kind");
+    for (int d = 0; d < 3; ++d) {
+        if (msh->n[d] < 1) return fail(DGNS_EINVAL, "n[%d] = %d < 1", d, msh->n[d]);
+        if (!(msh->hi[d] > msh->lo[d])) return fail(DGNS_EINVAL, "empty box in direction %d", d);
+    }
+    bool wall = !msh->periodic[0] || !msh->periodic[1] || !msh->periodic[2];
+    if (wall && !(prm->wall_T > 0)) return fail(DGNS_EINVAL, "walls need wall_T > 0");
+    const int64_t ncell = (int64_t)msh->n[0] * msh->n[1] * msh->n[2];
+    if (ncell > 2147483647LL) return fail(DGNS_EINVAL, "too many cells");
+    bool ok = false;
+    for (const auto& kq : kSupported) ok |= (kq[0] == prm->degree && kq[1] == prm->n_q);
+    if (!ok) return fail(DGNS_EUNSUPPORTED, "no kernel for degree %d with n_q %d", prm->degree, prm->n_q);
+
+    dgns_ctx* c = new dgns_ctx();
+    c->prm = *prm;
+    c->msh = *msh;
+    c->stream = (hipStream_t)stream;
+    c->k = prm->degree;
+    c->n = prm->degree + 1;
+    c->q = prm->n_q;
+    c->fp32 = prm->precision == DGNS_FP32;
+    c->gen = msh->kind != DGNS_MESH_AFFINE;
+    c->ncell = ncell;
+    c->n3 = (int64_t)c->n * c->n * c->n;
+    c->ndof = 5 * ncell * c->n3;
+    int rc = 0;
+    {
+        HostSetup hs;
+        std::string err;
+        rc = build_setup(*prm, *msh, hs, err);
+        if (rc != 0) {
+            fail(rc, "%s", err.c_str());
+        } else {
+            c->tab = hs.tab;
+            c->h_min = hs.h_min;
+            c->geo.swap(hs.geo);
+            c->node_x.swap(hs.node_x);
+            rc = upload(hs.metric, &c->d_metric);
+            for (int d = 0; d < 3 && rc == 0; ++d) {
+                rc = upload(hs.tau[d], &c->d_tau[d]);
+                if (rc == 0 && c->gen) rc = upload(hs.face[d], &c->d_face[d]);
+            }
+            if (rc == 0 && c->gen) rc = upload(hs.mass_jxw, &c->d_mass_jxw);
+        }
+    }
+    if (rc == 0) {
+        std::vector<Tables1D> tv(1, c->tab);
+        rc = upload(tv, &c->d_tab);
+    }
+    if (rc == 0) {
+        hipError_t e1 = hipMalloc((void**)&c->d_partial, sizeof(double) * 9 * ncell);
+        hipError_t e2 = hipMalloc((void**)&c->d_total, sizeof(double) * 9);
+        if (e1 != hipSuccess || e2 != hipSuccess) rc = fail(DGNS_ENOMEM, "diagnostics buffers");
+    }
+    if (rc != 0) {
+        free_ctx(c);
+        delete c;
+        return rc;
+    }
+    *out = c;
+    return DGNS_OK;
+}
+
+int dgns_destroy(dgns_ctx* c) {
+    if (!c) return DGNS_OK;
+    hipStreamSynchronize(c->stream);
+    free_ctx(c);
+    delete c;
+    return DGNS_OK;
+}
+
+int dgns_sizes(const dgns_ctx* c, int64_t* n_cells, int64_t* nodes_per_cell, int64_t* n_dof) {
+    if (!c) return fail(DGNS_EINVAL, "null context");
+    if (n_cells) *n_cells = c->ncell;
+    if (nodes_per_cell) *nodes_per_cell = c->n3;
+    if (n_dof) *n_dof = c->ndof;
+    return DGNS_OK;
+}
+
+int dgns_set_stream(dgns_ctx* c, void* stream) {
+    if (!c) return fail(DGNS_EINVAL, "null context");
+    c->stream = (hipStream_t)stream;
+    return DGNS_OK;
+}
+
+int dgns_apply_residual(dgns_ctx* c, const double* U, double* R, unsigned term_mask) {
+    if (!c || !U || !R) return fail(DGNS_EINVAL, "null argument");
+    if (!aligned8(U) || !aligned8(R)) return fail(DGNS_EINVAL, "vectors must be 8-byte aligned");
+    if (overlap(U, R, c->ndof)) return fail(DGNS_EINVAL, "U and R overlap");
+    if (term_mask & ~DGNS_TERM_ALL) return fail(DGNS_EINVAL, "unknown term bits");
+    return dispatch_operator(c, make_args(c, U, R, term_mask, 0));
+}
+
+int dgns_apply_inverse_mass(dgns_ctx* c, const double* R, double* L) {
+    if (!c || !R || !L) return fail(DGNS_EINVAL, "null argument");
+    if (!aligned8(R) || !aligned8(L)) return fail(DGNS_EINVAL, "vectors must be 8-byte aligned");
+    if (R != L && overlap(R, L, c->ndof)) return fail(DGNS_EINVAL, "R and L partially overlap");
+    return dispatch_minv(c, R, L);
+}
+
+int dgns_apply_operator(dgns_ctx* c, const double* U, double* L, double t) {
+    (void)t;
+    if (!c || !U || !L) return fail(DGNS_EINVAL, "null argument");
+    if (!aligned8(U) || !aligned8(L)) return fail(DGNS_EINVAL, "vectors must be 8-byte aligned");
+    if (overlap(U, L, c->ndof)) return fail(DGNS_EINVAL, "U and L overlap");
+    return dispatch_operator(c, make_args(c, U, L, DGNS_TERM_ALL, 1));
+}
+
+// Carpenter & Kennedy (1994), five stages, fourth order, 2N storage.
+static const double kRkA[5] = {0.0, -567301805773.0 / 1357537059087.0, -2404267990393.0 / 2016746695238.0,
+                               -3550918686646.0 / 2091501179385.0, -1275806237668.0 / 842570457699.0};
+static const double kRkB[5] = {1432997174477.0 / 9575080441755.0, 5161836677717.0 / 13612068292357.0,
+                               1720146321549.0 / 2090206949498.0, 3134564353537.0 / 4481467310338.0,
+                               2277821191437.0 / 14882151754819.0};
+
+int dgns_rk_step(dgns_ctx* c, double* U, double* work, double t, double dt) {
+    (void)t;
+    if (!c || !U || !work) return fail(DGNS_EINVAL, "null argument");
+    if (!aligned8(U) || !aligned8(work)) return fail(DGNS_EINVAL, "vectors must be 8-byte aligned");
+    if (overlap(U, work, 2 * c->ndof) || overlap(work, U, c->ndof)) return fail(DGNS_EINVAL, "U and work overlap");
+    if (!std::isfinite(dt)) return fail(DGNS_EINVAL, "dt is not finite");
+    double* dU = work;
+    double* L = work + c->ndof;
+    for (int i = 0; i < 5; ++i) {
+        int rc = dispatch_operator(c, make_args(c, U, L, DGNS_TERM_ALL, 1));
+        if (rc) return rc;
+        if (launch_rk_update(U, dU, L, c->ndof, kRkA[i], kRkB[i], dt, c->stream) != 0)
+            return fail(DGNS_EHIP, "rk update launch failed");
+    }
+    return DGNS_OK;
+}
+
+int dgns_compute_dt(const dgns_ctx* c, double Cr, double D, double e, double f, double umax, double mach,
+                    double* dt) {
+    if (!c || !dt) return fail(DGNS_EINVAL, "null argument");
+    if (!(umax > 0) || !(mach > 0) || !(Cr > 0)) return fail(DGNS_EINVAL, "umax, mach and Cr must be positive");
+    const double k = c->k;
+    const double nu = c->prm.mu / c->prm.rho_ref;
+    const double dtc = Cr / std::pow(k, e) * c->h_min / (umax + umax / mach);
+    const double dtv = (nu > 0 && D > 0) ? D / std::pow(k, f) * c->h_min * c->h_min / nu : INFINITY;
+    *dt = std::min(dtc, dtv);
+    return DGNS_OK;
+}
+
+int dgns_diagnostics(dgns_ctx* c, const double* U, const double* L, double* out8) {
+    if (!c || !U || !out8) return fail(DGNS_EINVAL, "null argument");
+    OpArgs a = make_args(c, U, nullptr, 0, 0);
+    if (launch_diagnostics(a, c->d_tab, L, c->d_partial, c->d_total, c->gen, c->stream) != 0)
+        return fail(DGNS_EHIP, "diagnostics launch failed");
+    double tot[9];
+    HIP_TRY(hipMemcpyAsync(tot, c->d_total, sizeof tot, hipMemcpyDeviceToHost, c->stream));
+    HIP_TRY(hipStreamSynchronize(c->stream));
+    const double V = tot[8];
+    const double nu = c->prm.mu / c->prm.rho_ref;
+    out8[0] = tot[0] / V;
+    out8[1] = nu * tot[1] / V;
+    out8[2] = L ? tot[2] / V : NAN;
+    for (int i = 0; i < 5; ++i) out8[3 + i] = tot[3 + i];
+    for (int i = 0; i < 8; ++i)
+        if (i != 2 || L)
+            if (!std::isfinite(out8[i])) return fail(DGNS_ENONFINITE, "diagnostic %d is not finite", i);
+    return DGNS_OK;
+}
+
+int dgns_project_ic(dgns_ctx* c, int ic, const double* icp, const double* noise, double* U) {
+    if (!c || !icp || !U) return fail(DGNS_EINVAL, "null argument");
+    if (ic < 0 || ic > 2) return fail(DGNS_EINVAL, "unknown initial condition %d", ic);
+    double q[8] = {0, 0, 0, 0, 0, 0, 0, 0};
+    const int np = ic == DGNS_IC_UNIFORM ? 5 : 4;
+    for (int i = 0; i < np; ++i) q[i] = icp[i];
+    double *d_geo = nullptr, *d_q = nullptr, *d_x = nullptr;
+    std::vector<double> qv(q, q + 8);
+    int rc = upload(c->geo, &d_geo);
+    if (!rc) rc = upload(qv, &d_q);
+    if (!rc) {
+        OpArgs a = make_args(c, nullptr, nullptr, 0, 0);
+        if (launch_ic_rhs(a, c->tab, c->d_tab, d_geo, ic, d_q, U, c->gen, c->stream) != 0)
+            rc = fail(DGNS_EHIP, "ic launch failed");
+    }
+    if (!rc) rc = dispatch_minv(c, U, U);
+    if (!rc && ic == DGNS_IC_CHANNEL && noise) {
+        rc = upload(c->node_x, &d_x);
+        if (!rc && launch_channel_perturb(U, d_x, noise, c->ncell, (int)c->n3, q[0], q[2], q[3], c->prm.gamma,
+                                          c->prm.R, c->stream) != 0)
+            rc = fail(DGNS_EHIP, "perturbation launch failed");
+    }
+    hipStreamSynchronize(c->stream);
+    hipFree(d_geo);
+    hipFree(d_q);
+    hipFree(d_x);
+    return rc;
+}
+
+}  // extern "C"

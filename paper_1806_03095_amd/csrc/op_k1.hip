@@ -1,0 +1,25 @@
+// Operator kernels of polynomial degree 1: the supported n_q values.
+#include "op_impl.h"
+#include "dg_kernels.h"
+
+namespace dgns {
+
+int launch_operator_k1(const OpArgs& a, const Tables1D& t, bool fp32, bool gen, hipStream_t st) {
+    switch (t.q) {
+        case 2: return fp32 ? (gen ? launch_op_t<2, 2, float, true>(a, t, st) : launch_op_t<2, 2, float, false>(a, t, st))
+                       : (gen ? launch_op_t<2, 2, double, true>(a, t, st) : launch_op_t<2, 2, double, false>(a, t, st));
+        case 3: return fp32 ? (gen ? launch_op_t<2, 3, float, true>(a, t, st) : launch_op_t<2, 3, float, false>(a, t, st))
+                       : (gen ? launch_op_t<2, 3, double, true>(a, t, st) : launch_op_t<2, 3, double, false>(a, t, st));
+        default: return 1;
+    }
+}
+
+int launch_inverse_mass_k1(const double* R, double* L, int64_t ncell, const double* cm, const double* mj,
+                            const Tables1D& t, bool fp32, bool gen, hipStream_t st) {
+    return fp32 ? (gen ? launch_minv_t<2, float, true>(R, L, ncell, cm, mj, t, st)
+                       : launch_minv_t<2, float, false>(R, L, ncell, cm, mj, t, st))
+                : (gen ? launch_minv_t<2, double, true>(R, L, ncell, cm, mj, t, st)
+                       : launch_minv_t<2, double, false>(R, L, ncell, cm, mj, t, st));
+}
+
+}  // namespace dgns

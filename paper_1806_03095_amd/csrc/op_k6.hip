@@ -1,0 +1,25 @@
+// Operator kernels of polynomial degree 6: the supported n_q values.
+#include "op_impl.h"
+#include "dg_kernels.h"
+
+namespace dgns {
+
+int launch_operator_k6(const OpArgs& a, const Tables1D& t, bool fp32, bool gen, hipStream_t st) {
+    switch (t.q) {
+        case 7: return fp32 ? (gen ? launch_op_t<7, 7, float, true>(a, t, st) : launch_op_t<7, 7, float, false>(a, t, st))
+                       : (gen ? launch_op_t<7, 7, double, true>(a, t, st) : launch_op_t<7, 7, double, false>(a, t, st));
+        case 10: return fp32 ? (gen ? launch_op_t<7, 10, float, true>(a, t, st) : launch_op_t<7, 10, float, false>(a, t, st))
+                       : (gen ? launch_op_t<7, 10, double, true>(a, t, st) : launch_op_t<7, 10, double, false>(a, t, st));
+        default: return 1;
+    }
+}
+
+int launch_inverse_mass_k6(const double* R, double* L, int64_t ncell, const double* cm, const double* mj,
+                            const Tables1D& t, bool fp32, bool gen, hipStream_t st) {
+    return fp32 ? (gen ? launch_minv_t<7, float, true>(R, L, ncell, cm, mj, t, st)
+                       : launch_minv_t<7, float, false>(R, L, ncell, cm, mj, t, st))
+                : (gen ? launch_minv_t<7, double, true>(R, L, ncell, cm, mj, t, st)
+                       : launch_minv_t<7, double, false>(R, L, ncell, cm, mj, t, st));
+}
+
+}  // namespace dgns

@@ -1,0 +1,83 @@
+// CPU harness around the operator kernel templates (test infrastructure only).
+// Compiled with g++ (and AddressSanitizer) against tests/emul/hip/hip_runtime.h;
+// see that file for how a workgroup is emulated.
+//
+// usage: harness <in.bin> <out.bin>
+//   in.bin : dgns_params, dgns_box_mesh, uint32 terms, int32 fuse_minv, then U (n_dof float64)
+//   out.bin: R or L (n_dof float64)
+#include <cstdio>
+#include <string>
+#include <vector>
+
+#include "op_impl.h"
+#include "setup.h"
+
+using namespace dgns;
+
+namespace {
+
+template <int N, int Q>
+int run(const OpArgs& a, const Tables1D& t, int fp32, int gen) {
+    if (fp32) return gen ? launch_op_t<N, Q, float, true>(a, t, nullptr) : launch_op_t<N, Q, float, false>(a, t, nullptr);
+    return gen ? launch_op_t<N, Q, double, true>(a, t, nullptr) : launch_op_t<N, Q, double, false>(a, t, nullptr);
+}
+
+}  // namespace
+
+int main(int argc, char** argv) {
+    if (argc != 3) return 2;
+    FILE* f = std::fopen(argv[1], "rb");
+    if (!f) return 3;
+    dgns_params prm;
+    dgns_box_mesh msh;
+    uint32_t terms;
+    int32_t fuse;
+    if (std::fread(&prm, sizeof prm, 1, f) != 1 || std::fread(&msh, sizeof msh, 1, f) != 1 ||
+        std::fread(&terms, 4, 1, f) != 1 || std::fread(&fuse, 4, 1, f) != 1)
+        return 4;
+    HostSetup hs;
+    std::string e;
+    int rc = build_setup(prm, msh, hs, e);
+    if (rc) {
+        std::fprintf(stderr, "setup: %s\n", e.c_str());
+        return 5;
+    }
+    const int64_t ndof = 5 * hs.ncell * hs.n3;
+    std::vector<double> U(ndof), out(ndof, -12345.0);
+    if ((int64_t)std::fread(U.data(), 8, ndof, f) != ndof) return 6;
+    std::fclose(f);
+    OpArgs a;
+    std::memset(&a, 0, sizeof a);
+    a.U = U.data();
+    a.out = out.data();
+    a.ncell = hs.ncell;
+    for (int d = 0; d < 3; ++d) {
+        a.n[d] = msh.n[d];
+        a.periodic[d] = msh.periodic[d] ? 1 : 0;
+        a.face_data[d] = hs.face[d].empty() ? nullptr : hs.face[d].data();
+        a.tau_face[d] = hs.tau[d].data();
+        a.force[d] = prm.body_force[d];
+    }
+    a.cell_metric = hs.metric.data();
+    a.mass_jxw = hs.mass_jxw.empty() ? nullptr : hs.mass_jxw.data();
+    a.gamma = prm.gamma;
+    a.R = prm.R;
+    a.mu = prm.mu;
+    a.lam = prm.lambda;
+    a.wall_T = prm.wall_T;
+    a.terms = terms;
+    a.fuse_minv = fuse;
+    const int k = prm.degree, q = prm.n_q, fp32 = prm.precision, gen = hs.gen ? 1 : 0;
+    rc = -4;
+#define EMU_CASE(K, Q_) \
+    if (k == K && q == Q_) rc = run<K + 1, Q_>(a, hs.tab, fp32, gen);
+    EMU_CASES
+    if (rc != 0) {
+        std::fprintf(stderr, "no emulated kernel for k=%d nq=%d\n", k, q);
+        return 7;
+    }
+    f = std::fopen(argv[2], "wb");
+    std::fwrite(out.data(), 8, ndof, f);
+    std::fclose(f);
+    return 0;
+}

@@ -1,0 +1,185 @@
+"""GPU parity of the HIP operator against the oracle (float64, 1e-12 relative per field).
+
+Inputs are the oracle's L2-projected states plus seeded noise; both sides get the
+same array.  Covered: the Taylor-Green configuration of 4^3 cells, k=3, n_q=6
+(LGL and GL bases), a range of (k, n_q) on ragged meshes, curved meshes (per
+quadrature-point metric), the stretched channel with walls and body force, each
+term separately, the inverse mass matrix, Runge-Kutta steps, diagnostics, the
+initial-state projection, and run-to-run bitwise determinism.
+"""
+import math
+
+import numpy as np
+import pytest
+import torch
+
+from oracle import diagnostics as odiag, initial, timeint
+from tests.gpu_cases import announce, make_pair, tgv_input, channel_input, rel_err_fields, tgv_fluid
+
+pytestmark = pytest.mark.gpu
+TOL = 1e-12
+
+
+def _cuda(t):
+    return t.to("cuda").contiguous()
+
+
+def _check_fields(got, want, tol, what):
+    errs = rel_err_fields(got, want)
+    assert max(errs) < tol, (what, errs)
+    return errs
+
+
+def _check_low_mach(got, want, what):
+    """Mach 0.1: 1e-12 normwise over the whole vector, 1e-11 per field.
+
+    The momentum rows cancel the background pressure p0 = 1/(gamma M^2) = 71
+    against an O(1) result, which costs about three digits in any float64
+    evaluation, the oracle's included (measured floor ~5e-12 per field)."""
+    g = torch.as_tensor(got).cpu()
+    w = torch.as_tensor(want).cpu()
+    norm = float(torch.linalg.norm(g - w) / torch.linalg.norm(w))
+    assert norm < 1e-12, (what, norm)
+    return _check_fields(g, w, 1e-11, what)
+
+
+@pytest.mark.parametrize("basis", ["LGL", "GL"])
+def test_tgv_4cubed_k3_nq6_operator(basis):
+    announce("tgv 4^3 k=3 nq=6 %s apply_operator" % basis)
+    oop, gop = make_pair((4, 4, 4), 3, 6, basis=basis)
+    U = tgv_input(oop)
+    L_gpu = gop.apply(_cuda(U))
+    torch.cuda.synchronize()
+    L_ora = oop.apply(U)
+    _check_low_mach(L_gpu, L_ora, "L")
+
+
+@pytest.mark.parametrize("terms,mask", [("c", 1), ("v", 2), ("cv", 3)])
+def test_tgv_residual_terms(terms, mask):
+    announce("tgv 4^3 k=3 nq=6 residual terms=%s" % terms)
+    oop, gop = make_pair((4, 4, 4), 3, 6)
+    U = tgv_input(oop, seed=5)
+    R_gpu = gop.residual(_cuda(U), terms=mask)
+    torch.cuda.synchronize()
+    R_ora = oop.residual(U, terms=terms)
+    _check_low_mach(R_gpu, R_ora, "R_" + terms)
+
+
+CASES = [
+    # n, k, nq, kind, amp, basis
+    ((3, 2, 2), 1, 2, "affine", 0.0, "LGL"),
+    ((3, 2, 2), 1, 3, "affine", 0.0, "GL"),
+    ((2, 3, 2), 2, 3, "affine", 0.0, "LGL"),
+    ((2, 2, 3), 2, 4, "curved", 0.1, "LGL"),
+    ((3, 3, 2), 3, 4, "affine", 0.0, "LGL"),
+    ((2, 3, 3), 3, 5, "curved", 0.15, "GL"),
+    ((2, 2, 2), 4, 7, "affine", 0.0, "LGL"),
+    ((2, 2, 2), 4, 6, "curved", 0.1, "LGL"),
+    ((2, 2, 2), 5, 8, "affine", 0.0, "LGL"),
+    ((2, 1, 2), 7, 11, "affine", 0.0, "LGL"),
+    ((1, 2, 2), 7, 11, "curved", 0.1, "LGL"),
+]
+
+
+@pytest.mark.parametrize("case", CASES)
+def test_operator_parity_range(case):
+    n, k, nq, kind, amp, basis = case
+    announce("parity n=%s k=%d nq=%d kind=%s amp=%g basis=%s" % (n, k, nq, kind, amp, basis))
+    oop, gop = make_pair(n, k, nq, kind=kind, amp=amp, basis=basis)
+    U = tgv_input(oop, seed=11 + k, mach=0.3)
+    L_gpu = gop.apply(_cuda(U))
+    R_gpu = gop.residual(_cuda(U))
+    torch.cuda.synchronize()
+    R_ora = oop.residual(U)
+    _check_fields(R_gpu, R_ora, TOL, "R")
+    _check_fields(L_gpu, oop.apply_inverse_mass(R_ora), TOL, "L")
+
+
+def test_channel_walls_force_k4():
+    announce("channel 2x4x2 k=4 nq=7 walls+force")
+    fl = tgv_fluid(mu=1.0 / 180.0)
+    T0 = (18.3 / 0.1) ** 2 / (1.4 * 287.0)
+    oop, gop = make_pair((2, 4, 2), 4, 7, lo=(0, -1, 0), hi=(2 * math.pi, 1, math.pi), periodic=(1, 0, 1),
+                         kind="channel", fluid=fl, force=(1.0, 0.0, 0.0), wall_T=T0)
+    U = channel_input(oop)
+    for mask, terms in ((1, "c"), (2, "v"), (4, "f"), (7, "cvf")):
+        R_gpu = gop.residual(_cuda(U), terms=mask)
+        torch.cuda.synchronize()
+        R_ora = oop.residual(U, terms=terms)
+        if terms == "f":   # the body force has no mass row
+            assert float(R_gpu[0].abs().max()) == 0.0
+            _check_fields(R_gpu[1:], R_ora[1:], TOL, "R_f")
+        else:
+            _check_fields(R_gpu, R_ora, TOL, "R_" + terms)
+    L_gpu = gop.apply(_cuda(U))
+    torch.cuda.synchronize()
+    _check_fields(L_gpu, oop.apply(U), TOL, "L")
+
+
+def test_inverse_mass_in_place_and_curved():
+    announce("inverse mass 2x2x3 k=3 curved, in place")
+    oop, gop = make_pair((2, 2, 3), 3, 5, kind="curved", amp=0.2)
+    R = torch.as_tensor(np.random.default_rng(3).standard_normal((5, oop.mesh.n_cells, oop.N)))
+    Rg = _cuda(R)
+    out = gop.inverse_mass(Rg)
+    gop.inverse_mass(Rg, out=Rg)          # in place
+    torch.cuda.synchronize()
+    want = oop.apply_inverse_mass(R)
+    _check_fields(out, want, TOL, "Minv")
+    _check_fields(Rg, want, TOL, "Minv in place")
+
+
+def test_rk_steps_tgv_4cubed():
+    announce("tgv 4^3 k=3 nq=6: 10 RK steps")
+    oop, gop = make_pair((4, 4, 4), 3, 6)
+    U0 = tgv_input(oop, seed=9)
+    dt = gop.compute_dt(0.3, 0.02, 1.5, 3.0, 1.0, 0.1)
+    assert abs(dt - timeint.time_step(0.3, 0.02, 1.5, 3.0, 3, oop.mesh.h_min(), 1.0, 0.1, oop.fl.nu)) < 1e-15
+    Ug = _cuda(U0.clone())
+    work = torch.empty(2 * gop.n_dof, dtype=torch.float64, device="cuda")
+    for s in range(10):
+        gop.rk_step(Ug, work, s * dt, dt)
+    torch.cuda.synchronize()
+    U = U0.clone()
+    for s in range(10):
+        U = timeint.lsrk_step(lambda V, t: oop.apply(V), U, s * dt, dt)
+    inc_gpu = Ug.cpu() - U0
+    inc_ora = U - U0
+    _check_low_mach(inc_gpu, inc_ora, "U10 - U0")
+
+
+def test_diagnostics_and_projection():
+    announce("tgv 4^3 k=3 nq=6: diagnostics and IC projection")
+    oop, gop = make_pair((4, 4, 4), 3, 6)
+    Ug = gop.project_ic("taylor_green", [1.0, 1.0, 0.1, 1.0])
+    torch.cuda.synchronize()
+    Uo = initial.l2_project(oop, lambda x: initial.taylor_green(x, oop.fl))
+    _check_fields(Ug, Uo, TOL, "IC")
+    U = tgv_input(oop, seed=4)
+    Lg = gop.apply(_cuda(U))
+    dg = gop.diagnostics(_cuda(U), Lg)
+    do = odiag.diagnostics(oop, U, oop.apply(U))
+    for key in ("e_k", "eps", "rate", "mass", "energy"):
+        assert abs(dg[key] - do[key]) <= 1e-12 * abs(do[key]), (key, dg[key], do[key])
+    assert np.allclose(dg["mom"], do["mom"], rtol=1e-10, atol=1e-12 * abs(do["mass"]))
+
+
+def test_determinism_bitwise():
+    announce("tgv 4^3 k=3 nq=6: bitwise determinism")
+    oop, gop = make_pair((4, 4, 4), 3, 6)
+    U = _cuda(tgv_input(oop, seed=1))
+    a = gop.apply(U)
+    b = gop.apply(U)
+    torch.cuda.synchronize()
+    assert torch.equal(a, b)
+
+
+def test_fp32_variant_error_is_small():
+    announce("tgv 4^3 k=3 nq=6 fp32 operator")
+    oop, gop = make_pair((4, 4, 4), 3, 6, precision="fp32")
+    U = tgv_input(oop, seed=2)
+    L32 = gop.apply(_cuda(U))
+    torch.cuda.synchronize()
+    errs = rel_err_fields(L32, oop.apply(U))
+    print("fp32 relative error per field:", errs, flush=True)
+    assert max(errs) < 1e-3

@@ -1,0 +1,65 @@
+"""The operator kernel source, compiled for the CPU and run one thread per workgroup
+(tests/emul), against the oracle -- with AddressSanitizer and UBSan on.
+
+This checks the kernels' indexing, face handling, geometry and arithmetic without
+a GPU (it does not replace the GPU parity tests: it cannot see races or the
+device compiler).  Inputs use Mach 0.3, where float64 rounding leaves the 1e-12
+per-field bound a wide margin.
+"""
+import math
+
+import numpy as np
+import pytest
+
+from oracle import mesh as omesh, operator as ooperator
+from tests import emul_driver as ed
+from tests.gpu_cases import channel_input, rel_err_fields, tgv_fluid, tgv_input
+
+PI3 = ((-math.pi,) * 3, (math.pi,) * 3)
+
+
+def _tgv_case(n, k, nq, kind=0, amp=0.0, basis="LGL"):
+    fl = tgv_fluid()
+    om = omesh.BoxMesh(n, PI3[0], PI3[1], k, kind=kind, deform_amp=amp)
+    oop = ooperator.DGOperator(om, fl, nq, basis=basis)
+    return fl, oop, tgv_input(oop, mach=0.3, seed=31)
+
+
+@pytest.mark.parametrize("n,k,nq,kind,amp,basis", [
+    ((3, 2, 2), 1, 2, 0, 0.0, "LGL"),
+    ((2, 2, 2), 2, 3, 2, 0.15, "GL"),
+    ((2, 1, 2), 3, 6, 0, 0.0, "LGL"),
+    ((1, 2, 2), 3, 6, 2, 0.1, "GL"),
+])
+def test_emulated_residual_per_term(n, k, nq, kind, amp, basis):
+    fl, oop, U = _tgv_case(n, k, nq, kind, amp, basis)
+    b = 0 if basis == "LGL" else 1
+    for mask, t in ((1, "c"), (2, "v"), (3, "cv")):
+        R = ed.run(U.numpy(), k, nq, n, *PI3, kind=kind, amp=amp, basis=b, mu=fl.mu, lam=fl.lam, terms=mask)
+        errs = rel_err_fields(R, oop.residual(U, terms=t))
+        assert max(errs) < 1e-12, (t, errs)
+    L = ed.run(U.numpy(), k, nq, n, *PI3, kind=kind, amp=amp, basis=b, mu=fl.mu, lam=fl.lam, terms=7, fuse=1)
+    errs = rel_err_fields(L, oop.apply(U))
+    assert max(errs) < 1e-12, errs
+
+
+def test_emulated_channel_walls_and_force():
+    fl = tgv_fluid(mu=1.0 / 180.0)
+    T0 = (18.3 / 0.1) ** 2 / (1.4 * 287.0)
+    lo, hi = (0, -1, 0), (2 * math.pi, 1, math.pi)
+    om = omesh.BoxMesh((2, 4, 1), lo, hi, 4, periodic=(True, False, True), kind=omesh.CHANNEL)
+    oop = ooperator.DGOperator(om, fl, 7, body_force=(1.0, 0.0, 0.0), wall_T=T0)
+    U = channel_input(oop)
+    for mask, t in ((1, "c"), (2, "v"), (4, "f"), (7, "cvf")):
+        R = ed.run(U.numpy(), 4, 7, (2, 4, 1), lo, hi, periodic=(1, 0, 1), kind=1, mu=fl.mu, lam=fl.lam,
+                   force=(1.0, 0, 0), wall_T=T0, terms=mask)
+        Ro = oop.residual(U, terms=t)
+        errs = rel_err_fields(R, Ro) if t != "f" else rel_err_fields(R[1:], Ro[1:])
+        assert max(errs) < 1e-12, (t, errs)
+
+
+def test_emulated_fp32_error_scale():
+    fl, oop, U = _tgv_case((2, 2, 2), 3, 6)
+    L = ed.run(U.numpy(), 3, 6, (2, 2, 2), *PI3, precision=1, mu=fl.mu, lam=fl.lam, terms=7, fuse=1)
+    errs = rel_err_fields(L, oop.apply(U))
+    assert 1e-8 < max(errs) < 1e-4, errs     # float32 rounding, not float64
