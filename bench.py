@@ -1,0 +1,187 @@
+"""Throughput of the DG compressible Navier-Stokes operator on one MI355X.
+
+Workload (default): Taylor-Green vortex on [-pi, pi]^3, 32^3 affine cells,
+degree k = 3 (LGL nodes), n_q = 6 Gauss points per direction (over-integration),
+10,485,760 float64 DoFs, Ma = 0.1, Re = 1600, Pr = 0.71.  One step = one time step
+of the five-stage 2N Runge-Kutta scheme: five evaluations of L = M^{-1}(-F_c - F_v)
+(one fused cell+face+inverse-mass kernel each) and five stage updates.
+The reported value is DoFs processed per second per operator evaluation,
+N_dof * stages * steps / time, with the inputs resident in HBM.
+
+    python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-cpu-baseline]
+
+Prints one JSON line.  Extra keys: the float32-operator variant's throughput and
+dissipation-rate error, the operator kernel alone, its HBM fraction and the
+roofline of the dominant kernel, and the oracle timed on host cores.
+"""
+import argparse
+import json
+import math
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "DoFs/s per DG operator eval (TGV k=3, 32^3 cells) FP64 vs FP32; % HBM roofline"
+PEAK_FP64_VALU = 78.6e12        # MI355X FP64 vector, FLOP/s
+PEAK_HBM = 8.0e12               # MI355X HBM3E, B/s
+# Algorithmic work of one evaluation of L per DoF (k=3, n_q=6): sum factorisation
+# without even-odd splitting, faces counted once, ~280 flop per cell point and
+# ~700 per face point; and the compulsory traffic, read U + write L.
+FLOP_PER_DOF = {(3, 6): 1197.0, (3, 5): 769.0, (3, 4): 474.0, (4, 7): 1049.0, (5, 8): 976.0, (7, 11): 1178.0}
+BYTES_PER_DOF = 16.0
+
+
+def log(msg):
+    print("[bench] " + msg, file=sys.stderr, flush=True)
+
+
+def time_rk(op, U, work, dt, steps, warmup):
+    import torch
+    t = 0.0
+    for _ in range(warmup):
+        op.rk_step(U, work, t, dt)
+        t += dt
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    w0 = time.perf_counter()
+    e0.record()
+    for _ in range(steps):
+        op.rk_step(U, work, t, dt)
+        t += dt
+    e1.record()
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - w0
+    return e0.elapsed_time(e1) / 1e3, wall
+
+
+def time_operator(op, U, L, calls):
+    import torch
+    for _ in range(5):
+        op.apply(U, L)
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(calls):
+        op.apply(U, L)
+    e1.record()
+    torch.cuda.synchronize()
+    return e0.elapsed_time(e1) / 1e3 / calls
+
+
+def cpu_baseline(ne, k, nq, n_sample):
+    """The oracle, as it stands, on a sample of cells of the same workload."""
+    import numpy as np
+    import torch
+    from oracle import initial, mesh, operator, physics
+    fl = physics.Fluid.from_reynolds(1600.0, 0.71)
+    m = mesh.BoxMesh((ne,) * 3, (-math.pi,) * 3, (math.pi,) * 3, k)
+    op = operator.DGOperator(m, fl, nq)
+    cells = np.linspace(0, m.n_cells - 1, n_sample).astype(np.int64)
+    need = np.unique(np.concatenate([cells, m.nb[cells].reshape(-1)]))
+    U = torch.zeros(5, m.n_cells, (k + 1) ** 3, dtype=torch.float64)
+    U[:, need, :] = initial.l2_project(op, lambda x: initial.taylor_green(x, fl), cells=need)
+    op.tau_of(need)
+    t0 = time.perf_counter()
+    op.apply(U, cells=cells)
+    el = time.perf_counter() - t0
+    cpu = "unknown"
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                cpu = line.split(":", 1)[1].strip()
+                break
+    except OSError:
+        pass
+    dofs = n_sample * 5 * (k + 1) ** 3
+    return {"value": dofs / el, "unit": "DoF/s", "cores": torch.get_num_threads(), "kind": "oracle",
+            "sample": "one evaluation of L on %d of %d cells (%d DoFs) of the same workload, %.2f s, %s"
+                      % (n_sample, m.n_cells, dofs, el, cpu)}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=100)
+    ap.add_argument("--warmup", type=int, default=10)
+    ap.add_argument("--cells", type=int, default=32)
+    ap.add_argument("--degree", type=int, default=3)
+    ap.add_argument("--nq", type=int, default=6)
+    ap.add_argument("--op-calls", type=int, default=200)
+    ap.add_argument("--cpu-sample-cells", type=int, default=4096)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-fp32", action="store_true")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print("bench.py measures one GPU only: this build has no multi-GPU path (the halo-exchange "
+              "design is described in DESIGN.md); run with --gpus 1", file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+    from paper_1806_03095_amd import taylor_green
+
+    k, nq, ne = args.degree, args.nq, args.cells
+    log("workload: TGV %d^3 cells, k=%d, n_q=%d" % (ne, k, nq))
+    op = taylor_green(k, ne, n_q=nq, precision="fp64")
+    ndof = op.n_dof
+    U0 = op.project_ic("taylor_green", [1.0, 1.0, 0.1, 1.0])
+    dt = op.compute_dt(0.4, 0.02, 1.5, 3.0, 1.0, 0.1)
+    work = torch.empty(2 * ndof, dtype=torch.float64, device="cuda")
+    U = U0.clone()
+    log("fp64: %d warmup + %d timed RK steps, dt=%.4e" % (args.warmup, args.steps, dt))
+    t64, wall64 = time_rk(op, U, work, dt, args.steps, args.warmup)
+    d = op.diagnostics(U)
+    if d.get("nonfinite"):
+        raise RuntimeError("the solution became non-finite")
+    value = ndof * 5 * args.steps / t64
+    log("fp64: %.3e DoF/s per operator evaluation (%.3f ms/step), e_k=%.6f" % (value, 1e3 * t64 / args.steps, d["e_k"]))
+
+    L = torch.empty_like(U0)
+    t_op = time_operator(op, U0, L, args.op_calls)
+    log("fp64 operator kernel: %.1f us per launch, %.3e DoF/s" % (1e6 * t_op, ndof / t_op))
+
+    flop = FLOP_PER_DOF.get((k, nq))
+    roof = {"bound": "alu", "achieved": None, "peak": PEAK_FP64_VALU / 1e12, "unit": "TFLOP/s", "frac": None,
+            "traffic": None}
+    if flop is not None:
+        ach = flop * ndof / t_op
+        roof.update(achieved=round(ach / 1e12, 3), frac=round(ach / PEAK_FP64_VALU, 4))
+    hbm_frac = BYTES_PER_DOF * ndof / t_op / PEAK_HBM
+
+    out = {"metric": METRIC, "value": value, "unit": "DoF/s", "n_gpus": 1, "steps": args.steps,
+           "warmup": args.warmup, "ms_per_step": 1e3 * t64 / args.steps, "higher_is_better": True,
+           "scaling": "weak", "vs_baseline": None, "dtype": "f64", "data": "synthetic",
+           "config": {"workload": "taylor_green_%dcubed_k%d_nq%d" % (ne, k, nq), "cells": ne ** 3, "degree": k,
+                      "n_q": nq, "basis": "LGL", "n_dof": ndof, "mach": 0.1, "reynolds": 1600,
+                      "time_integrator": "2N low-storage RK, 5 stages, order 4", "dt": dt},
+           "roofline": roof,
+           "operator_only": {"dofs_per_s": ndof / t_op, "us_per_launch": 1e6 * t_op,
+                             "hbm_frac_16B_per_dof": round(hbm_frac, 5)}}
+
+    if not args.no_fp32:
+        op32 = taylor_green(k, ne, n_q=nq, precision="fp32")
+        U32 = U0.clone()
+        t32, _ = time_rk(op32, U32, work, dt, args.steps, args.warmup)
+        t_op32 = time_operator(op32, U0, L, args.op_calls)
+        L64 = op.apply(U0)
+        L32 = op32.apply(U0)
+        r64 = op.diagnostics(U0, L64)["rate"]
+        r32 = op.diagnostics(U0, L32)["rate"]
+        res = float(torch.linalg.norm(L32 - L64) / torch.linalg.norm(L64))
+        out["fp32"] = {"value": ndof * 5 * args.steps / t32, "speedup_vs_fp64": t64 / t32,
+                       "operator_dofs_per_s": ndof / t_op32, "operator_speedup_vs_fp64": t_op / t_op32,
+                       "residual_rel_err": res, "dissipation_rate_rel_err": abs(r32 - r64) / abs(r64)}
+        log("fp32: %.3e DoF/s (x%.2f), operator x%.2f, |L32-L64|/|L64| = %.2e"
+            % (out["fp32"]["value"], t64 / t32, t_op / t_op32, res))
+        del op32
+
+    if not args.no_cpu_baseline:
+        log("cpu baseline: oracle on %d sample cells" % args.cpu_sample_cells)
+        out["cpu_baseline"] = cpu_baseline(ne, k, nq, args.cpu_sample_cells)
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -51,10 +51,12 @@ def uniform(x, fl, rho=1.0, u=(0.3, -0.2, 0.1), p=None):
                                        torch.full(shape, p, dtype=torch.float64), fl)
 
 
-def l2_project(op, func):
-    """U_h = M^{-1} (phi_i, U0) with the right-hand side on the n_q-point rule."""
-    cells = np.arange(op.mesh.n_cells)
+def l2_project(op, func, cells=None):
+    """U_h = M^{-1} (phi_i, U0) with the right-hand side on the n_q-point rule.
+
+    With `cells`, only those cells are projected (shape (5, len(cells), N))."""
+    cells = np.arange(op.mesh.n_cells) if cells is None else np.asarray(cells, dtype=np.int64)
     x, _, detJ = op._geometry(cells, op.cell_pts)
     vals = func(x.numpy())                                   # (E, P, 5)
     rhs = torch.einsum("pi,epc->cei", op.Phi, vals * (detJ * torch.as_tensor(op.cell_w))[..., None])
-    return op.apply_inverse_mass(rhs)
+    return op.apply_inverse_mass(rhs, cells)

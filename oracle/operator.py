@@ -93,7 +93,7 @@ class DGOperator:
         self.mass_pts, self.mass_w = meshmod.cell_points(xm, wm)
         Pm, _ = meshmod.tensor_basis(self.nodes, self.mass_pts)
         self.Phi_m = _t(Pm)
-        self.tau_cell = self._penalty_per_cell()
+        self._tau = np.full(mesh.n_cells, np.nan)
 
     # -- geometry ----------------------------------------------------------
     def _geometry(self, cells, pts):
@@ -124,13 +124,24 @@ class DGOperator:
         norm = torch.linalg.norm(nn, dim=-1)
         return nn / norm[..., None], detJ * norm * w
 
-    def _penalty_per_cell(self):
+    @property
+    def tau_cell(self):
+        return self.tau_of(np.arange(self.mesh.n_cells))
+
+    def tau_of(self, cells):
+        """Penalty of the given cells, computed on first use."""
+        cells = np.asarray(cells, dtype=np.int64)
+        missing = np.unique(cells[np.isnan(self._tau[cells])])
+        if len(missing):
+            self._penalty(missing)
+        return self._tau[cells]
+
+    def _penalty(self, todo):
         """tau_IP,e = nu (k+1)^2 (A(interior)/2 + A(boundary)) / V(e)  (eq. TauIP_Element)."""
-        E = self.mesh.n_cells
-        tau = np.zeros(E)
+        tau = self._tau
         w = _t(self.cell_w)
-        for c0 in range(0, E, 2048):
-            cells = np.arange(c0, min(E, c0 + 2048))
+        for c0 in range(0, len(todo), 2048):
+            cells = todo[c0:c0 + 2048]
             _, _, detJ = self._geometry(cells, self.cell_pts)
             V = (detJ * w).sum(-1)
             A = torch.zeros(len(cells), dtype=torch.float64)
@@ -142,7 +153,6 @@ class DGOperator:
                     boundary = torch.as_tensor(self.mesh.nb[cells, d, s] < 0)
                     A = A + torch.where(boundary, 1.0, 0.5) * dA.sum(-1)
             tau[cells] = (self.fl.nu * (self.k + 1) ** 2 * A / V).numpy()
-        return tau
 
     # -- evaluation at points ---------------------------------------------
     def _values(self, Ue, P, dP, Jinv):
@@ -230,7 +240,7 @@ class DGOperator:
         nbr_safe = np.where(wall, cells, nbr)
         _, Jinv_n, _ = self._geometry(nbr_safe, pts_n)
         Up, Gp = self._values(U[:, nbr_safe, :], Pn, dPn, Jinv_n)
-        tau = self.tau_cell[cells]
+        tau = self.tau_of(cells)
         if wall.any():
             if self.wall_T is None:
                 raise ValueError("wall faces need wall_T")
@@ -238,7 +248,7 @@ class DGOperator:
             wmask = torch.as_tensor(wall)
             Up = torch.where(wmask[:, None, None], Uw, Up)
             Gp = torch.where(wmask[:, None, None, None], Gw, Gp)
-        tau = _t(np.where(wall, tau, np.maximum(tau, self.tau_cell[nbr_safe])))
+        tau = _t(np.where(wall, tau, np.maximum(tau, self.tau_of(nbr_safe))))
 
         jump = Um - Up
         val = torch.zeros_like(Um)

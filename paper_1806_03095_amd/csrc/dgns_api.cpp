@@ -151,7 +151,8 @@ int dispatch_minv(const dgns_ctx* c, const double* R, double* L) {
 
 bool aligned8(const void* p) { return ((uintptr_t)p & 7u) == 0; }
 
-bool overlap(const double* a, const double* b, int64_t n) { return a < b + n && b < a + n; }
+// [a, a + na) and [b, b + nb) share an element
+bool overlap(const double* a, int64_t na, const double* b, int64_t nb) { return a < b + nb && b < a + na; }
 
 }  // namespace
 
@@ -257,7 +258,7 @@ int dgns_set_stream(dgns_ctx* c, void* stream) {
 int dgns_apply_residual(dgns_ctx* c, const double* U, double* R, unsigned term_mask) {
     if (!c || !U || !R) return fail(DGNS_EINVAL, "null argument");
     if (!aligned8(U) || !aligned8(R)) return fail(DGNS_EINVAL, "vectors must be 8-byte aligned");
-    if (overlap(U, R, c->ndof)) return fail(DGNS_EINVAL, "U and R overlap");
+    if (overlap(U, c->ndof, R, c->ndof)) return fail(DGNS_EINVAL, "U and R overlap");
     if (term_mask & ~DGNS_TERM_ALL) return fail(DGNS_EINVAL, "unknown term bits");
     return dispatch_operator(c, make_args(c, U, R, term_mask, 0));
 }
@@ -265,7 +266,7 @@ int dgns_apply_residual(dgns_ctx* c, const double* U, double* R, unsigned term_m
 int dgns_apply_inverse_mass(dgns_ctx* c, const double* R, double* L) {
     if (!c || !R || !L) return fail(DGNS_EINVAL, "null argument");
     if (!aligned8(R) || !aligned8(L)) return fail(DGNS_EINVAL, "vectors must be 8-byte aligned");
-    if (R != L && overlap(R, L, c->ndof)) return fail(DGNS_EINVAL, "R and L partially overlap");
+    if (R != L && overlap(R, c->ndof, L, c->ndof)) return fail(DGNS_EINVAL, "R and L partially overlap");
     return dispatch_minv(c, R, L);
 }
 
@@ -273,7 +274,7 @@ int dgns_apply_operator(dgns_ctx* c, const double* U, double* L, double t) {
     (void)t;
     if (!c || !U || !L) return fail(DGNS_EINVAL, "null argument");
     if (!aligned8(U) || !aligned8(L)) return fail(DGNS_EINVAL, "vectors must be 8-byte aligned");
-    if (overlap(U, L, c->ndof)) return fail(DGNS_EINVAL, "U and L overlap");
+    if (overlap(U, c->ndof, L, c->ndof)) return fail(DGNS_EINVAL, "U and L overlap");
     return dispatch_operator(c, make_args(c, U, L, DGNS_TERM_ALL, 1));
 }
 
@@ -288,7 +289,7 @@ int dgns_rk_step(dgns_ctx* c, double* U, double* work, double t, double dt) {
     (void)t;
     if (!c || !U || !work) return fail(DGNS_EINVAL, "null argument");
     if (!aligned8(U) || !aligned8(work)) return fail(DGNS_EINVAL, "vectors must be 8-byte aligned");
-    if (overlap(U, work, 2 * c->ndof) || overlap(work, U, c->ndof)) return fail(DGNS_EINVAL, "U and work overlap");
+    if (overlap(U, c->ndof, work, 2 * c->ndof)) return fail(DGNS_EINVAL, "U and work overlap");
     if (!std::isfinite(dt)) return fail(DGNS_EINVAL, "dt is not finite");
     double* dU = work;
     double* L = work + c->ndof;
