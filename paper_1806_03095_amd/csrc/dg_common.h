@@ -14,7 +14,7 @@ namespace dgns {
 
 constexpr int kMaxN = 8;    // nodes per direction, k <= 7
 constexpr int kMaxQ = 12;   // quadrature points per direction
-constexpr int kBlock = 256; // threads per workgroup of the cell kernels
+constexpr int kBlock = 128; // threads per workgroup of the cell kernels
 
 // 1D tables of one (k, n_q, basis) combination, float64 master copy.
 struct Tables1D {
@@ -93,14 +93,33 @@ __host__ __device__ inline Phys<Real> make_phys(const OpArgs& a) {
     return p;
 }
 
-// Viscous flux F_v(U, G)[c][j] for a conserved state U and a conserved-variable
-// gradient G[c][j] = dU_c/dx_j; linear in G.  Row 0 is identically zero.
+// Primitive quantities of a conserved state, computed once per point: 1/rho,
+// velocity u = m/rho, |u|^2, pressure p = (gamma-1)(rho E - rho |u|^2/2), E = rho E/rho.
 template <typename Real>
-__device__ __forceinline__ void viscous_flux(const Real U[5], const Real G[5][3], const Phys<Real>& ph,
+struct Prim {
+    Real rinv, u[3], uu, p, E;
+};
+
+template <typename Real>
+__device__ __forceinline__ Prim<Real> primitives(const Real U[5], const Phys<Real>& ph) {
+    Prim<Real> s;
+    s.rinv = Real(1) / U[0];
+    s.u[0] = U[1] * s.rinv;
+    s.u[1] = U[2] * s.rinv;
+    s.u[2] = U[3] * s.rinv;
+    s.uu = s.u[0] * s.u[0] + s.u[1] * s.u[1] + s.u[2] * s.u[2];
+    s.p = ph.gm1 * (U[4] - Real(0.5) * U[0] * s.uu);
+    s.E = U[4] * s.rinv;
+    return s;
+}
+
+// Viscous flux F_v(U, G)[c][j] for a conserved state U (primitives s) and a
+// conserved-variable gradient G[c][j] = dU_c/dx_j; linear in G.  Row 0 is zero.
+template <typename Real>
+__device__ __forceinline__ void viscous_flux(const Prim<Real>& s, const Real G[5][3], const Phys<Real>& ph,
                                              Real F[5][3]) {
-    const Real rinv = Real(1) / U[0];
-    const Real u0 = U[1] * rinv, u1 = U[2] * rinv, u2 = U[3] * rinv;
-    const Real E = U[4] * rinv;
+    const Real rinv = s.rinv;
+    const Real u0 = s.u[0], u1 = s.u[1], u2 = s.u[2];
     Real gu[3][3];
 #pragma unroll
     for (int j = 0; j < 3; ++j) {
@@ -121,7 +140,7 @@ __device__ __forceinline__ void viscous_flux(const Real U[5], const Real G[5][3]
 #pragma unroll
     for (int j = 0; j < 3; ++j) {
         // dT/dx_j = ((d(rho E)/dx_j - E drho/dx_j)/rho - u . du/dx_j) / c_v
-        const Real gE = (G[4][j] - E * G[0][j]) * rinv;
+        const Real gE = (G[4][j] - s.E * G[0][j]) * rinv;
         const Real gT = gE - (u0 * gu[0][j] + u1 * gu[1][j] + u2 * gu[2][j]);
         F[0][j] = Real(0);
         F[1][j] = tau[0][j];
@@ -131,52 +150,95 @@ __device__ __forceinline__ void viscous_flux(const Real U[5], const Real G[5][3]
     }
 }
 
+// F_v(U, G) . n, the viscous flux in direction n (five values, the first zero).
 template <typename Real>
-__device__ __forceinline__ Real pressure(const Real U[5], const Phys<Real>& ph) {
-    const Real rinv = Real(1) / U[0];
-    return ph.gm1 * (U[4] - Real(0.5) * (U[1] * U[1] + U[2] * U[2] + U[3] * U[3]) * rinv);
+__device__ __forceinline__ void viscous_flux_normal(const Prim<Real>& s, const Real G[5][3], const Real n[3],
+                                                    const Phys<Real>& ph, Real Fn[5]) {
+    const Real rinv = s.rinv;
+    Real gu[3][3];
+#pragma unroll
+    for (int a = 0; a < 3; ++a)
+#pragma unroll
+        for (int j = 0; j < 3; ++j) gu[a][j] = (G[1 + a][j] - s.u[a] * G[0][j]) * rinv;
+    const Real div = gu[0][0] + gu[1][1] + gu[2][2];
+    Real tn[3];
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+        // (grad u + grad u^T) n - 2/3 div n
+        const Real gun = gu[a][0] * n[0] + gu[a][1] * n[1] + gu[a][2] * n[2];
+        const Real gtn = gu[0][a] * n[0] + gu[1][a] * n[1] + gu[2][a] * n[2];
+        tn[a] = ph.mu * (gun + gtn - Real(2.0 / 3.0) * div * n[a]);
+    }
+    Real gTn = 0;
+#pragma unroll
+    for (int j = 0; j < 3; ++j) {
+        const Real gT = (G[4][j] - s.E * G[0][j]) * rinv - (s.u[0] * gu[0][j] + s.u[1] * gu[1][j] + s.u[2] * gu[2][j]);
+        gTn += gT * n[j];
+    }
+    Fn[0] = Real(0);
+    Fn[1] = tn[0];
+    Fn[2] = tn[1];
+    Fn[3] = tn[2];
+    Fn[4] = s.u[0] * tn[0] + s.u[1] * tn[1] + s.u[2] * tn[2] + ph.lam * ph.inv_cv * gTn;
+}
+
+// F_v(U, j (x) n) for a rank-one gradient (the symmetry term of the interior
+// penalty method, with j = U^- - U^+): du_a/dx_k = w_a n_k, w_a = (j_{1+a} - u_a j_0)/rho,
+// dT/dx_k = t n_k with t = ((j_4 - E j_0)/rho - u . w)/c_v.
+template <typename Real>
+__device__ __forceinline__ void viscous_flux_rank1(const Prim<Real>& s, const Real jmp[5], const Real n[3],
+                                                   const Phys<Real>& ph, Real F[5][3]) {
+    Real w[3];
+#pragma unroll
+    for (int a = 0; a < 3; ++a) w[a] = (jmp[1 + a] - s.u[a] * jmp[0]) * s.rinv;
+    const Real div = w[0] * n[0] + w[1] * n[1] + w[2] * n[2];
+    const Real t = ((jmp[4] - s.E * jmp[0]) * s.rinv - (s.u[0] * w[0] + s.u[1] * w[1] + s.u[2] * w[2])) * ph.inv_cv;
+    const Real un = s.u[0] * n[0] + s.u[1] * n[1] + s.u[2] * n[2];
+    const Real uw = s.u[0] * w[0] + s.u[1] * w[1] + s.u[2] * w[2];
+    const Real mu = ph.mu, dd = Real(2.0 / 3.0) * div;
+#pragma unroll
+    for (int j = 0; j < 3; ++j) {
+        F[0][j] = Real(0);
+#pragma unroll
+        for (int a = 0; a < 3; ++a) F[1 + a][j] = mu * (w[a] * n[j] + w[j] * n[a] - (a == j ? dd : Real(0)));
+        // (tau u)_j = mu (w_j (u.n) + n_j (u.w) - 2/3 div u_j)
+        F[4][j] = mu * (w[j] * un + n[j] * uw - dd * s.u[j]) + ph.lam * t * n[j];
+    }
 }
 
 // Convective flux F_c(U)[c][j].
 template <typename Real>
-__device__ __forceinline__ void convective_flux(const Real U[5], const Phys<Real>& ph, Real F[5][3]) {
-    const Real rinv = Real(1) / U[0];
-    const Real u[3] = {U[1] * rinv, U[2] * rinv, U[3] * rinv};
-    const Real p = ph.gm1 * (U[4] - Real(0.5) * (U[1] * u[0] + U[2] * u[1] + U[3] * u[2]));
+__device__ __forceinline__ void convective_flux(const Real U[5], const Prim<Real>& s, Real F[5][3]) {
 #pragma unroll
     for (int j = 0; j < 3; ++j) {
         F[0][j] = U[1 + j];
-        F[1][j] = U[1] * u[j] + (j == 0 ? p : Real(0));
-        F[2][j] = U[2] * u[j] + (j == 1 ? p : Real(0));
-        F[3][j] = U[3] * u[j] + (j == 2 ? p : Real(0));
-        F[4][j] = (U[4] + p) * u[j];
+        F[1][j] = U[1] * s.u[j] + (j == 0 ? s.p : Real(0));
+        F[2][j] = U[2] * s.u[j] + (j == 1 ? s.p : Real(0));
+        F[3][j] = U[3] * s.u[j] + (j == 2 ? s.p : Real(0));
+        F[4][j] = (U[4] + s.p) * s.u[j];
     }
 }
 
 // F_c(U) . n and the LLF wave speed |u| + c, c = sqrt(|gamma p / rho|).
 template <typename Real>
-__device__ __forceinline__ Real convective_normal(const Real U[5], const Real n[3], const Phys<Real>& ph,
-                                                  Real Fn[5]) {
-    const Real rinv = Real(1) / U[0];
-    const Real u0 = U[1] * rinv, u1 = U[2] * rinv, u2 = U[3] * rinv;
-    const Real uu = u0 * u0 + u1 * u1 + u2 * u2;
-    const Real p = ph.gm1 * (U[4] - Real(0.5) * U[0] * uu);
-    const Real un = u0 * n[0] + u1 * n[1] + u2 * n[2];
+__device__ __forceinline__ Real convective_normal(const Real U[5], const Prim<Real>& s, const Real n[3],
+                                                  const Phys<Real>& ph, Real Fn[5]) {
+    const Real un = s.u[0] * n[0] + s.u[1] * n[1] + s.u[2] * n[2];
     Fn[0] = U[0] * un;
-    Fn[1] = U[1] * un + p * n[0];
-    Fn[2] = U[2] * un + p * n[1];
-    Fn[3] = U[3] * un + p * n[2];
-    Fn[4] = (U[4] + p) * un;
-    return sqrt(uu) + sqrt(fabs(ph.gamma * p * rinv));
+    Fn[1] = U[1] * un + s.p * n[0];
+    Fn[2] = U[2] * un + s.p * n[1];
+    Fn[3] = U[3] * un + s.p * n[2];
+    Fn[4] = (U[4] + s.p) * un;
+    return sqrt(s.uu) + sqrt(fabs(ph.gamma * s.p * s.rinv));
 }
 
 // Exterior state at an isothermal no-slip wall: rho+ = rho-, u+ = -u-,
 // T+ = 2 T_wall - T-, E+ = c_v T+ + |u|^2/2 (gradients are copied by the caller).
 template <typename Real>
-__device__ __forceinline__ void wall_mirror(const Real Um[5], const Phys<Real>& ph, Real Up[5]) {
+__device__ __forceinline__ void wall_mirror(const Real Um[5], const Prim<Real>& s, const Phys<Real>& ph, Real Up[5]) {
     const Real rho = Um[0];
-    const Real ke = Real(0.5) * (Um[1] * Um[1] + Um[2] * Um[2] + Um[3] * Um[3]) / rho;
-    const Real T = ph.gm1 * (Um[4] - ke) / (rho * ph.R);
+    const Real ke = Real(0.5) * rho * s.uu;
+    const Real T = s.p * s.rinv / ph.R;
     const Real Tp = Real(2) * ph.wall_T - T;
     Up[0] = rho;
     Up[1] = -Um[1];

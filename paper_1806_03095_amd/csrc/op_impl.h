@@ -18,10 +18,15 @@
 // only its own test-function contributions, so that every cell's output is written
 // exactly once (no atomics, bit-reproducible).
 //
-// LDS layout per workgroup (Real units): sU[5][N^3] own coefficients, sR[5][N^3]
-// accumulated residual, sW = the work area of the current phase (see sizes below).
-// The quadrature points are processed in chunks of P planes along xi_2 to bound
-// the work area for large n_q.
+// Work organisation: a workgroup of B threads; every phase is a cooperative loop
+// over independent items (lines of a sweep, quadrature points) separated by
+// barriers.  The cell's quadrature points are processed in chunks of P planes
+// along xi_2; the faces in two groups (the three faces xi_d = 0, then the three
+// faces xi_d = 1), each phase covering all three faces of a group.  The sweep
+// along the second tangential direction of a face is fused into the pointwise
+// flux phase (each face point contracts its own line), so no n_q^2 intermediate
+// is stored.  LDS holds sU[5][N^3] (own coefficients), sR[5][N^3] (residual) and
+// a work area sized for the largest phase.
 
 #pragma once
 
@@ -32,30 +37,52 @@ namespace dgns {
 template <int A, int B>
 struct CMax { static constexpr int v = A > B ? A : B; };
 
-template <int N, int Q, int P>
-struct OpSizes {
-    static constexpr int N2 = N * N, N3 = N2 * N, Q2 = Q * Q, Q3 = Q2 * Q;
-    static constexpr int Z = 10 * Q * N2;                 // z-sweeps: value, derivative
-    static constexpr int Y = 15 * P * Q * N;              // y-sweeps (3 kinds), later x-transposed
-    static constexpr int F = 15 * P * Q2;                 // reference fluxes, later y-transposed
-    static constexpr int CELL = Z + Y + F;
-    static constexpr int R1 = CMax<CMax<5 * N3, 30 * Q * N>::v, CMax<20 * Q2, 10 * N2>::v>::v;
-    static constexpr int R2 = CMax<CMax<20 * N2, 40 * Q2>::v, 15 * Q * N>::v;
-    static constexpr int FACE = R1 + R2;
-    static constexpr int MASS = 10 * N3;
-    static constexpr int WORK = CMax<CMax<CELL, FACE>::v, MASS>::v;
+template <int N, int Q>
+struct FaceSizes {
+    static constexpr int N2 = N * N, Q2 = Q * Q;
+    // group of three faces; region 1 and region 2 alternate between phases
+    static constexpr int TR = 3 * 2 * 2 * 5 * N2;      // traces [f][side][v/n][c][N^2]
+    static constexpr int SW = 3 * 2 * 3 * 5 * N * Q;   // t0 sweep [f][side][3][c][N][Q]
+    static constexpr int OUT = 3 * 4 * 5 * Q2;         // point outputs [f][4][c][Q^2]
+    static constexpr int T1 = 3 * 3 * 5 * N * Q;       // t1-transposed [f][3][c][N][Q]
+    static constexpr int W = 3 * 2 * 5 * N2;           // lifted [f][2][c][N^2]
+    static constexpr int R1 = CMax<SW, T1>::v;
+    static constexpr int R2 = CMax<CMax<TR, OUT>::v, W>::v;
+    static constexpr int TOTAL = R1 + R2;
 };
 
-// Applies an N x N matrix M (row-major in M[r][c]) along axis `ax` of the five
-// arrays src[5][N^3] -> dst[5][N^3]; transposed uses M^T.  Cooperative over the
-// workgroup; the caller synchronises.
+template <int N, int Q, int P>
+struct CellSizes {
+    static constexpr int N2 = N * N, Q2 = Q * Q;
+    static constexpr int Z = 10 * Q * N2;   // z-sweeps: value, derivative
+    static constexpr int Y = 15 * P * Q * N;  // y-sweeps (3 kinds), later x-transposed
+    static constexpr int F = 15 * P * Q2;     // reference fluxes, later y-transposed
+    static constexpr int TOTAL = Z + Y + F;
+};
+
+// Planes per chunk: as many as fit in the face-phase work area (at least one).
+template <int N, int Q>
+struct ChooseP {
+    static constexpr int fit(int p) {
+        return p <= 1 ? 1 : (CellSizes<N, Q, 1>::TOTAL + (p - 1) * (15 * Q * N + 15 * Q * Q) <= FaceSizes<N, Q>::TOTAL ? p : fit(p - 1));
+    }
+    static constexpr int v = fit(Q);
+};
+
+template <int N, int Q>
+struct OpSizes {
+    static constexpr int P = ChooseP<N, Q>::v;
+    static constexpr int WORK = CMax<CMax<CellSizes<N, Q, P>::TOTAL, FaceSizes<N, Q>::TOTAL>::v, 10 * N * N * N>::v;
+};
+
+// Applies an N x N matrix M along axis `ax` of the five arrays src[5][N^3] ->
+// dst[5][N^3]; TRANS uses M^T.  Cooperative over the workgroup; the caller syncs.
 template <int N, typename Real, bool TRANS>
 __device__ __forceinline__ void sweep_nn(const Real (&M)[N][N], const Real* src, Real* dst, int ax) {
     constexpr int N2 = N * N, N3 = N2 * N;
     const int stride = ax == 0 ? 1 : (ax == 1 ? N : N2);
     for (int it = threadIdx.x; it < 5 * N2; it += blockDim.x) {
         const int c = it / N2, rest = it % N2;
-        // rest enumerates the two other coordinates
         int base;
         if (ax == 0) base = rest * N;                                  // (a1, a2)
         else if (ax == 1) base = (rest % N) + (rest / N) * N2;         // (a0, a2)
@@ -106,301 +133,304 @@ __device__ __forceinline__ void inverse_mass_lds(const MTab<N, Real>& mt, Real* 
     __syncthreads();
 }
 
-// Face terms of one direction d, both sides s = 0, 1, of the cell e (element-centric).
-template <int d, int N, int Q, typename Real, bool GEN, typename Sz>
-__device__ __forceinline__ void face_terms(const OpArgs& a, const KTab<N, Q, Real>& tb, const Phys<Real>& ph,
-                                           bool conv, bool visc, int64_t e, int i0, int i1, int i2,
-                                           const Real (&Ji)[9], Real detJ, const Real* sU, Real* sR, Real* sW) {
-    constexpr int N2 = N * N, N3 = N2 * N, Q2 = Q * Q;
-    Real* r1 = sW;
-    Real* r2 = sW + Sz::R1;
-    constexpr int t0 = d == 0 ? 1 : 0;
-    constexpr int t1 = d == 2 ? 1 : 2;
-    constexpr int sd = d == 0 ? 1 : (d == 1 ? N : N2);
-    constexpr int s0 = t0 == 0 ? 1 : (t0 == 1 ? N : N2);
-    constexpr int s1 = t1 == 0 ? 1 : (t1 == 1 ? N : N2);
-    const int tid = threadIdx.x;
-    const int64_t cstride = a.ncell * N3;
-    const int id = d == 0 ? i0 : (d == 1 ? i1 : i2);
-    const int it0 = t0 == 0 ? i0 : (t0 == 1 ? i1 : i2);
-    const int it1 = t1 == 0 ? i0 : (t1 == 1 ? i1 : i2);
-    const int nd = a.n[d];
-    for (int s = 0; s < 2; ++s) {
-                // neighbour across face xi_d = s
-                int jd = id + (s ? 1 : -1);
-                bool wall = false;
-                if (jd < 0 || jd >= nd) {
-                    if (a.periodic[d]) jd = (jd + nd) % nd;
-                    else wall = true;
-                }
-                const int j0 = d == 0 ? jd : i0, j1 = d == 1 ? jd : i1, j2 = d == 2 ? jd : i2;
-                const int64_t enb = wall ? e : j0 + (int64_t)a.n[0] * (j1 + (int64_t)a.n[1] * j2);
-                const int64_t fid = (id + s) + (int64_t)(nd + 1) * (it0 + (int64_t)a.n[t0] * it1);
-                const Real tau = (Real)a.tau_face[d][fid];
+__device__ __forceinline__ int axis_stride(int ax, int N) { return ax == 0 ? 1 : (ax == 1 ? N : N * N); }
 
-                // neighbour coefficients -> r1
-                if (!wall) {
-                    for (int i = tid; i < 5 * N3; i += blockDim.x) {
-                        const int c = i / N3, j = i % N3;
-                        r1[i] = (Real)a.U[c * cstride + enb * N3 + j];
-                    }
-                }
-                __syncthreads();
+// Neighbour, face id and penalty of the six faces, computed once per workgroup.
+struct FaceInfo {
+    int64_t enb[6];   // neighbour cell (own cell for walls), index d + 3 s
+    int64_t fid[6];
+    int wall[6];
+};
 
-                // traces: value and normal derivative of both sides at the face nodes
-                // r2 layout [side][kind v/n][c][b][a]
-                for (int it = tid; it < 5 * N2; it += blockDim.x) {
-                    const int c = it / N2, ab = it % N2, ia = ab % N, ib = ab / N;
-                    const int base = ia * s0 + ib * s1;
-                    Real tv = 0, tn = 0, uv = 0, un = 0;
+// Value and physical gradient of one side at face point (q0, q1): the sweep along
+// t1 of the t0-swept traces A[3][c][N][Q] (value, t0-derivative, normal derivative).
+template <int N, int Q, typename Real>
+__device__ __forceinline__ void load_face_point(const KTab<N, Q, Real>& tb, const Real* A, int d, int q0, int q1,
+                                                const Real (&J)[9], Real U[5], Real G[5][3]) {
 #pragma unroll
-                    for (int m = 0; m < N; ++m) {
-                        const Real x = sU[c * N3 + base + m * sd];
-                        tv += tb.fv[s][m] * x;
-                        tn += tb.fd[s][m] * x;
-                    }
-                    if (!wall) {
+    for (int c = 0; c < 5; ++c) {
+        Real v = 0, g0 = 0, g1 = 0, gn = 0;
 #pragma unroll
-                        for (int m = 0; m < N; ++m) {
-                            const Real x = r1[c * N3 + base + m * sd];
-                            uv += tb.fv[1 - s][m] * x;
-                            un += tb.fd[1 - s][m] * x;
-                        }
-                    }
-                    r2[((0 * 2 + 0) * 5 + c) * N2 + ab] = tv;
-                    r2[((0 * 2 + 1) * 5 + c) * N2 + ab] = tn;
-                    r2[((1 * 2 + 0) * 5 + c) * N2 + ab] = uv;
-                    r2[((1 * 2 + 1) * 5 + c) * N2 + ab] = un;
-                }
-                __syncthreads();
-
-                // sweep along t0: A0 = S tv, A1 = D tv, An = S tn   r1 layout [side][kind3][c][b][r0]
-                for (int it = tid; it < 2 * 5 * N; it += blockDim.x) {
-                    const int ib = it % N, c = (it / N) % 5, side = it / (5 * N);
-                    if (side == 1 && wall) continue;
-                    Real tv[N], tn[N];
+        for (int ib = 0; ib < N; ++ib) {
+            const Real a0 = A[(0 * 5 + c) * N * Q + ib * Q + q0];
+            const Real a1 = A[(1 * 5 + c) * N * Q + ib * Q + q0];
+            const Real an = A[(2 * 5 + c) * N * Q + ib * Q + q0];
+            v += tb.S[q1][ib] * a0;
+            g0 += tb.S[q1][ib] * a1;
+            g1 += tb.D[q1][ib] * a0;
+            gn += tb.S[q1][ib] * an;
+        }
+        // reference gradient in the cell's axes: (t0, t1, d) -> (0, 1, 2)
+        const Real gr0 = d == 0 ? gn : g0;
+        const Real gr1 = d == 1 ? gn : (d == 0 ? g0 : g1);
+        const Real gr2 = d == 2 ? gn : g1;
 #pragma unroll
-                    for (int ia = 0; ia < N; ++ia) {
-                        tv[ia] = r2[((side * 2 + 0) * 5 + c) * N2 + ib * N + ia];
-                        tn[ia] = r2[((side * 2 + 1) * 5 + c) * N2 + ib * N + ia];
-                    }
-#pragma unroll
-                    for (int q0 = 0; q0 < Q; ++q0) {
-                        Real a0 = 0, a1 = 0, an = 0;
-#pragma unroll
-                        for (int ia = 0; ia < N; ++ia) {
-                            a0 += tb.S[q0][ia] * tv[ia];
-                            a1 += tb.D[q0][ia] * tv[ia];
-                            an += tb.S[q0][ia] * tn[ia];
-                        }
-                        r1[((side * 3 + 0) * 5 + c) * N * Q + ib * Q + q0] = a0;
-                        r1[((side * 3 + 1) * 5 + c) * N * Q + ib * Q + q0] = a1;
-                        r1[((side * 3 + 2) * 5 + c) * N * Q + ib * Q + q0] = an;
-                    }
-                }
-                __syncthreads();
-
-                // sweep along t1: V, D_t0, D_t1, D_n at the face points   r2 layout [side][kind4][c][q1][q0]
-                for (int it = tid; it < 2 * 5 * Q; it += blockDim.x) {
-                    const int q0 = it % Q, c = (it / Q) % 5, side = it / (5 * Q);
-                    if (side == 1 && wall) continue;
-                    Real a0[N], a1[N], an[N];
-#pragma unroll
-                    for (int ib = 0; ib < N; ++ib) {
-                        a0[ib] = r1[((side * 3 + 0) * 5 + c) * N * Q + ib * Q + q0];
-                        a1[ib] = r1[((side * 3 + 1) * 5 + c) * N * Q + ib * Q + q0];
-                        an[ib] = r1[((side * 3 + 2) * 5 + c) * N * Q + ib * Q + q0];
-                    }
-#pragma unroll
-                    for (int q1 = 0; q1 < Q; ++q1) {
-                        Real v = 0, g0 = 0, g1 = 0, gn = 0;
-#pragma unroll
-                        for (int ib = 0; ib < N; ++ib) {
-                            v += tb.S[q1][ib] * a0[ib];
-                            g0 += tb.S[q1][ib] * a1[ib];
-                            g1 += tb.D[q1][ib] * a0[ib];
-                            gn += tb.S[q1][ib] * an[ib];
-                        }
-                        r2[((side * 4 + 0) * 5 + c) * Q2 + q1 * Q + q0] = v;
-                        r2[((side * 4 + 1) * 5 + c) * Q2 + q1 * Q + q0] = g0;
-                        r2[((side * 4 + 2) * 5 + c) * Q2 + q1 * Q + q0] = g1;
-                        r2[((side * 4 + 3) * 5 + c) * Q2 + q1 * Q + q0] = gn;
-                    }
-                }
-                __syncthreads();
-
-                // pointwise numerical fluxes   r1 layout [kind4: val, g_t0, g_t1, g_n][c][q1][q0]
-                for (int it = tid; it < Q2; it += blockDim.x) {
-                    const int q0 = it % Q, q1 = it / Q;
-                    Real Jm[9], Jp[9], nrm[3], dAw;
-                    if constexpr (GEN) {
-                        const double* fd = a.face_data[d] + fid * 22 * Q2 + it;
-                        const Real sgn = s ? Real(1) : Real(-1);
-#pragma unroll
-                        for (int j = 0; j < 3; ++j) nrm[j] = sgn * (Real)fd[j * Q2];
-                        dAw = (Real)fd[3 * Q2];
-                        const int own = s ? 4 : 13, oth = s ? 13 : 4;
-#pragma unroll
-                        for (int m = 0; m < 9; ++m) {
-                            Jm[m] = (Real)fd[(own + m) * Q2];
-                            Jp[m] = (Real)fd[(oth + m) * Q2];
-                        }
-                    } else {
-#pragma unroll
-                        for (int m = 0; m < 9; ++m) Jm[m] = Ji[m];
-                        const double* cm = a.cell_metric + enb * 10;
-#pragma unroll
-                        for (int m = 0; m < 9; ++m) Jp[m] = (Real)cm[m];
-                        const Real sgn = s ? Real(1) : Real(-1);
-                        const Real l = sqrt(Ji[d * 3] * Ji[d * 3] + Ji[d * 3 + 1] * Ji[d * 3 + 1] + Ji[d * 3 + 2] * Ji[d * 3 + 2]);
-#pragma unroll
-                        for (int j = 0; j < 3; ++j) nrm[j] = sgn * Ji[d * 3 + j] / l;
-                        dAw = detJ * l * tb.w[q0] * tb.w[q1];
-                    }
-                    Real Um[5], Up[5], Gm[5][3], Gp[5][3];
-#pragma unroll
-                    for (int c = 0; c < 5; ++c) {
-                        Real gr[3];
-                        Um[c] = r2[((0 * 4 + 0) * 5 + c) * Q2 + it];
-                        gr[t0] = r2[((0 * 4 + 1) * 5 + c) * Q2 + it];
-                        gr[t1] = r2[((0 * 4 + 2) * 5 + c) * Q2 + it];
-                        gr[d] = r2[((0 * 4 + 3) * 5 + c) * Q2 + it];
-#pragma unroll
-                        for (int j = 0; j < 3; ++j) Gm[c][j] = Jm[j] * gr[0] + Jm[3 + j] * gr[1] + Jm[6 + j] * gr[2];
-                    }
-                    if (wall) {
-                        wall_mirror(Um, ph, Up);
-#pragma unroll
-                        for (int c = 0; c < 5; ++c)
-#pragma unroll
-                            for (int j = 0; j < 3; ++j) Gp[c][j] = Gm[c][j];
-                    } else {
-#pragma unroll
-                        for (int c = 0; c < 5; ++c) {
-                            Real gr[3];
-                            Up[c] = r2[((1 * 4 + 0) * 5 + c) * Q2 + it];
-                            gr[t0] = r2[((1 * 4 + 1) * 5 + c) * Q2 + it];
-                            gr[t1] = r2[((1 * 4 + 2) * 5 + c) * Q2 + it];
-                            gr[d] = r2[((1 * 4 + 3) * 5 + c) * Q2 + it];
-#pragma unroll
-                            for (int j = 0; j < 3; ++j) Gp[c][j] = Jp[j] * gr[0] + Jp[3 + j] * gr[1] + Jp[6 + j] * gr[2];
-                        }
-                    }
-                    Real val[5], jump[5];
-                    Real gphys[5][3];
-#pragma unroll
-                    for (int c = 0; c < 5; ++c) {
-                        val[c] = 0;
-                        jump[c] = Um[c] - Up[c];
-#pragma unroll
-                        for (int j = 0; j < 3; ++j) gphys[c][j] = 0;
-                    }
-                    if (conv) {
-                        Real Fm[5], Fp[5];
-                        const Real lm = convective_normal(Um, nrm, ph, Fm);
-                        const Real lp = convective_normal(Up, nrm, ph, Fp);
-                        const Real lam = lm > lp ? lm : lp;
-#pragma unroll
-                        for (int c = 0; c < 5; ++c) val[c] -= Real(0.5) * (Fm[c] + Fp[c]) + Real(0.5) * lam * jump[c];
-                    }
-                    if (visc) {
-                        Real Vm[5][3], Vp[5][3], Dl[5][3], Sy[5][3];
-                        viscous_flux(Um, Gm, ph, Vm);
-                        viscous_flux(Up, Gp, ph, Vp);
-#pragma unroll
-                        for (int c = 0; c < 5; ++c) {
-                            val[c] += Real(0.5) * ((Vm[c][0] + Vp[c][0]) * nrm[0] + (Vm[c][1] + Vp[c][1]) * nrm[1] +
-                                                   (Vm[c][2] + Vp[c][2]) * nrm[2]) -
-                                      tau * jump[c];
-#pragma unroll
-                            for (int j = 0; j < 3; ++j) Dl[c][j] = jump[c] * nrm[j];
-                        }
-                        viscous_flux(Um, Dl, ph, Sy);
-#pragma unroll
-                        for (int c = 0; c < 5; ++c)
-#pragma unroll
-                            for (int j = 0; j < 3; ++j) gphys[c][j] = Real(0.5) * Sy[c][j];
-                    }
-#pragma unroll
-                    for (int c = 0; c < 5; ++c) {
-                        Real gref[3];
-#pragma unroll
-                        for (int dd = 0; dd < 3; ++dd)
-                            gref[dd] = (Jm[dd * 3] * gphys[c][0] + Jm[dd * 3 + 1] * gphys[c][1] + Jm[dd * 3 + 2] * gphys[c][2]) * dAw;
-                        r1[(0 * 5 + c) * Q2 + it] = val[c] * dAw;
-                        r1[(1 * 5 + c) * Q2 + it] = gref[t0];
-                        r1[(2 * 5 + c) * Q2 + it] = gref[t1];
-                        r1[(3 * 5 + c) * Q2 + it] = gref[d];
-                    }
-                }
-                __syncthreads();
-
-                // transposed along t1: P0 = S^T val + D^T g_t1, P1 = S^T g_t0, Pn = S^T g_n   r2 [kind3][c][b][q0]
-                for (int it = tid; it < 5 * Q * N; it += blockDim.x) {
-                    const int q0 = it % Q, ib = (it / Q) % N, c = it / (Q * N);
-                    Real p0 = 0, p1 = 0, pn = 0;
-#pragma unroll
-                    for (int q1 = 0; q1 < Q; ++q1) {
-                        const int pt = q1 * Q + q0;
-                        p0 += tb.S[q1][ib] * r1[(0 * 5 + c) * Q2 + pt] + tb.D[q1][ib] * r1[(2 * 5 + c) * Q2 + pt];
-                        p1 += tb.S[q1][ib] * r1[(1 * 5 + c) * Q2 + pt];
-                        pn += tb.S[q1][ib] * r1[(3 * 5 + c) * Q2 + pt];
-                    }
-                    r2[(0 * 5 + c) * N * Q + ib * Q + q0] = p0;
-                    r2[(1 * 5 + c) * N * Q + ib * Q + q0] = p1;
-                    r2[(2 * 5 + c) * N * Q + ib * Q + q0] = pn;
-                }
-                __syncthreads();
-
-                // transposed along t0: W0 = S^T P0 + D^T P1, W1 = S^T Pn   r1 [kind2][c][b][a]
-                for (int it = tid; it < 5 * N2; it += blockDim.x) {
-                    const int ia = it % N, ib = (it / N) % N, c = it / N2;
-                    Real w0 = 0, w1 = 0;
-#pragma unroll
-                    for (int q0 = 0; q0 < Q; ++q0) {
-                        w0 += tb.S[q0][ia] * r2[(0 * 5 + c) * N * Q + ib * Q + q0] +
-                              tb.D[q0][ia] * r2[(1 * 5 + c) * N * Q + ib * Q + q0];
-                        w1 += tb.S[q0][ia] * r2[(2 * 5 + c) * N * Q + ib * Q + q0];
-                    }
-                    r1[(0 * 5 + c) * N2 + ib * N + ia] = w0;
-                    r1[(1 * 5 + c) * N2 + ib * N + ia] = w1;
-                }
-                __syncthreads();
-
-                // R[c](a, b, m) += W0(a, b) l_m(s) + W1(a, b) l'_m(s)
-                for (int it = tid; it < 5 * N3; it += blockDim.x) {
-                    const int c = it / N3, r = it % N3;
-                    const int x0 = r % N, x1 = (r / N) % N, x2 = r / N2;
-                    const int ia = t0 == 0 ? x0 : x1;
-                    const int ib = t1 == 1 ? x1 : x2;
-                    const int m = d == 0 ? x0 : (d == 1 ? x1 : x2);
-                    sR[it] += r1[(0 * 5 + c) * N2 + ib * N + ia] * tb.fv[s][m] +
-                              r1[(1 * 5 + c) * N2 + ib * N + ia] * tb.fd[s][m];
-                }
-                __syncthreads();
+        for (int j = 0; j < 3; ++j) G[c][j] = J[j] * gr0 + J[3 + j] * gr1 + J[6 + j] * gr2;
+        U[c] = v;
     }
 }
 
-template <int N, int Q, typename Real, bool GEN, int P>
+// The three faces xi_d = s (d = 0, 1, 2) of the cell: traces, fluxes, test
+// integration, accumulated into sR.
+template <int N, int Q, typename Real, bool GEN>
+__device__ __forceinline__ void face_group(const OpArgs& a, const KTab<N, Q, Real>& tb, const Phys<Real>& ph, bool conv,
+                                           bool visc, int s, int64_t e, const FaceInfo& fi, const Real* sTau,
+                                           const Real (&Ji)[9], Real detJ, const Real* sU, Real* sR, Real* sW) {
+    using FS = FaceSizes<N, Q>;
+    constexpr int N2 = N * N, N3 = N2 * N, Q2 = Q * Q;
+    Real* r1 = sW;
+    Real* r2 = sW + FS::R1;
+    const int tid = threadIdx.x, nth = blockDim.x;
+    const int64_t cstride = a.ncell * N3;
+
+    // traces: value and normal derivative of both sides at the face nodes
+    for (int it = tid; it < 3 * 5 * N2; it += nth) {
+        const int d = it / (5 * N2), c = (it / N2) % 5, ab = it % N2, ia = ab % N, ib = ab / N;
+        const int t0 = d == 0 ? 1 : 0, t1 = d == 2 ? 1 : 2;
+        const int base = ia * axis_stride(t0, N) + ib * axis_stride(t1, N), sd = axis_stride(d, N);
+        Real tv = 0, tn = 0, uv = 0, un = 0;
+#pragma unroll
+        for (int m = 0; m < N; ++m) {
+            const Real x = sU[c * N3 + base + m * sd];
+            tv += tb.fv[s][m] * x;
+            tn += tb.fd[s][m] * x;
+        }
+        if (!fi.wall[d + 3 * s]) {
+            const double* un_line = a.U + c * cstride + fi.enb[d + 3 * s] * N3 + base;
+#pragma unroll
+            for (int m = 0; m < N; ++m) {
+                const Real x = (Real)un_line[m * sd];
+                uv += tb.fv[1 - s][m] * x;
+                un += tb.fd[1 - s][m] * x;
+            }
+        }
+        Real* tr = r2 + d * (2 * 2 * 5 * N2) + c * N2 + ab;
+        tr[(0 * 2 + 0) * 5 * N2] = tv;
+        tr[(0 * 2 + 1) * 5 * N2] = tn;
+        tr[(1 * 2 + 0) * 5 * N2] = uv;
+        tr[(1 * 2 + 1) * 5 * N2] = un;
+    }
+    __syncthreads();
+
+    // sweep along t0: A0 = S tv, A1 = D tv, An = S tn     r1 [f][side][3][c][b][q0]
+    for (int it = tid; it < 3 * 2 * 5 * N; it += nth) {
+        const int ib = it % N, c = (it / N) % 5, side = (it / (5 * N)) % 2, d = it / (10 * N);
+        if (side == 1 && fi.wall[d + 3 * s]) continue;
+        const Real* tr = r2 + d * (2 * 2 * 5 * N2) + side * (2 * 5 * N2) + c * N2 + ib * N;
+        Real tv[N], tn[N];
+#pragma unroll
+        for (int ia = 0; ia < N; ++ia) {
+            tv[ia] = tr[ia];
+            tn[ia] = tr[5 * N2 + ia];
+        }
+        Real* o = r1 + ((d * 2 + side) * 3 * 5 + c) * N * Q + ib * Q;
+#pragma unroll
+        for (int q0 = 0; q0 < Q; ++q0) {
+            Real a0 = 0, a1 = 0, an = 0;
+#pragma unroll
+            for (int ia = 0; ia < N; ++ia) {
+                a0 += tb.S[q0][ia] * tv[ia];
+                a1 += tb.D[q0][ia] * tv[ia];
+                an += tb.S[q0][ia] * tn[ia];
+            }
+            o[q0] = a0;
+            o[5 * N * Q + q0] = a1;
+            o[2 * 5 * N * Q + q0] = an;
+        }
+    }
+    __syncthreads();
+
+    // pointwise: t1 contraction of the own line, numerical fluxes, reference-space test coefficients
+    //   r2 [f][kind: val, g_t0, g_t1, g_n][c][q1][q0]
+    for (int it = tid; it < 3 * Q2; it += nth) {
+        const int d = it / Q2, pt = it % Q2, q0 = pt % Q, q1 = pt / Q;
+        const int fslot = d + 3 * s;
+        const bool wall = fi.wall[fslot] != 0;
+        Real Jm[9], Jp[9], nrm[3], dAw;
+        if constexpr (GEN) {
+            const double* fd = a.face_data[d] + fi.fid[fslot] * 22 * Q2 + pt;
+            const Real sgn = s ? Real(1) : Real(-1);
+#pragma unroll
+            for (int j = 0; j < 3; ++j) nrm[j] = sgn * (Real)fd[j * Q2];
+            dAw = (Real)fd[3 * Q2];
+            const int own = s ? 4 : 13, oth = s ? 13 : 4;
+#pragma unroll
+            for (int m = 0; m < 9; ++m) {
+                Jm[m] = (Real)fd[(own + m) * Q2];
+                Jp[m] = (Real)fd[(oth + m) * Q2];
+            }
+        } else {
+#pragma unroll
+            for (int m = 0; m < 9; ++m) Jm[m] = Ji[m];
+            const double* cm = a.cell_metric + fi.enb[fslot] * 10;
+#pragma unroll
+            for (int m = 0; m < 9; ++m) Jp[m] = (Real)cm[m];
+            const Real sgn = s ? Real(1) : Real(-1);
+            const Real j0 = d == 0 ? Ji[0] : (d == 1 ? Ji[3] : Ji[6]);
+            const Real j1 = d == 0 ? Ji[1] : (d == 1 ? Ji[4] : Ji[7]);
+            const Real j2 = d == 0 ? Ji[2] : (d == 1 ? Ji[5] : Ji[8]);
+            const Real l = sqrt(j0 * j0 + j1 * j1 + j2 * j2);
+            nrm[0] = sgn * j0 / l;
+            nrm[1] = sgn * j1 / l;
+            nrm[2] = sgn * j2 / l;
+            dAw = detJ * l * tb.w[q0] * tb.w[q1];
+        }
+        // one side at a time, to keep a single gradient live: value, physical gradient,
+        // F_c.n, F_v.n and the wave speed of each side
+        Real Um[5], Up[5], Fcm[5], Fcp[5], Fvm[5], Fvp[5], lam_m = 0, lam_p = 0;
+        Prim<Real> sm, sp;
+        {
+            Real G[5][3];
+            load_face_point<N, Q, Real>(tb, r1 + (d * 2 + 0) * 3 * 5 * N * Q, d, q0, q1, Jm, Um, G);
+            sm = primitives(Um, ph);
+            if (conv) lam_m = convective_normal(Um, sm, nrm, ph, Fcm);
+            if (visc) viscous_flux_normal(sm, G, nrm, ph, Fvm);
+            if (wall) {
+                wall_mirror(Um, sm, ph, Up);
+            } else {
+                load_face_point<N, Q, Real>(tb, r1 + (d * 2 + 1) * 3 * 5 * N * Q, d, q0, q1, Jp, Up, G);
+            }
+            sp = primitives(Up, ph);
+            if (conv) lam_p = convective_normal(Up, sp, nrm, ph, Fcp);
+            if (visc) viscous_flux_normal(sp, G, nrm, ph, Fvp);   // at walls G is the interior gradient
+        }
+        const Real tau = sTau[fslot];
+        Real val[5], jump[5];
+#pragma unroll
+        for (int c = 0; c < 5; ++c) {
+            val[c] = 0;
+            jump[c] = Um[c] - Up[c];
+        }
+        Real gphys[5][3];
+        if (conv) {
+            const Real lam = lam_m > lam_p ? lam_m : lam_p;
+#pragma unroll
+            for (int c = 0; c < 5; ++c) val[c] -= Real(0.5) * (Fcm[c] + Fcp[c]) + Real(0.5) * lam * jump[c];
+        }
+        if (visc) {
+#pragma unroll
+            for (int c = 0; c < 5; ++c) val[c] += Real(0.5) * (Fvm[c] + Fvp[c]) - tau * jump[c];
+            viscous_flux_rank1(sm, jump, nrm, ph, gphys);
+        } else {
+#pragma unroll
+            for (int c = 0; c < 5; ++c)
+#pragma unroll
+                for (int j = 0; j < 3; ++j) gphys[c][j] = 0;
+        }
+        const Real half_dAw = Real(0.5) * dAw;
+        Real* o = r2 + d * 4 * 5 * Q2 + pt;
+#pragma unroll
+        for (int c = 0; c < 5; ++c) {
+            Real gref[3];
+#pragma unroll
+            for (int dd = 0; dd < 3; ++dd)
+                gref[dd] = (Jm[dd * 3] * gphys[c][0] + Jm[dd * 3 + 1] * gphys[c][1] + Jm[dd * 3 + 2] * gphys[c][2]) *
+                           half_dAw;
+            const Real gt0 = d == 0 ? gref[1] : gref[0];
+            const Real gt1 = d == 2 ? gref[1] : gref[2];
+            const Real gn = d == 0 ? gref[0] : (d == 1 ? gref[1] : gref[2]);
+            o[(0 * 5 + c) * Q2] = val[c] * dAw;
+            o[(1 * 5 + c) * Q2] = gt0;
+            o[(2 * 5 + c) * Q2] = gt1;
+            o[(3 * 5 + c) * Q2] = gn;
+        }
+    }
+    __syncthreads();
+
+    // transposed along t1: P0 = S^T val + D^T g_t1, P1 = S^T g_t0, Pn = S^T g_n    r1 [f][3][c][b][q0]
+    for (int it = tid; it < 3 * 5 * N * Q; it += nth) {
+        const int q0 = it % Q, ib = (it / Q) % N, c = (it / (Q * N)) % 5, d = it / (5 * Q * N);
+        const Real* o = r2 + d * 4 * 5 * Q2 + c * Q2 + q0;
+        Real p0 = 0, p1 = 0, pn = 0;
+#pragma unroll
+        for (int q1 = 0; q1 < Q; ++q1) {
+            p0 += tb.S[q1][ib] * o[q1 * Q] + tb.D[q1][ib] * o[2 * 5 * Q2 + q1 * Q];
+            p1 += tb.S[q1][ib] * o[1 * 5 * Q2 + q1 * Q];
+            pn += tb.S[q1][ib] * o[3 * 5 * Q2 + q1 * Q];
+        }
+        Real* t = r1 + d * 3 * 5 * N * Q + c * N * Q + ib * Q + q0;
+        t[0] = p0;
+        t[5 * N * Q] = p1;
+        t[2 * 5 * N * Q] = pn;
+    }
+    __syncthreads();
+
+    // transposed along t0: W0 = S^T P0 + D^T P1, W1 = S^T Pn    r2 [f][2][c][b][a]
+    for (int it = tid; it < 3 * 5 * N2; it += nth) {
+        const int ia = it % N, ib = (it / N) % N, c = (it / N2) % 5, d = it / (5 * N2);
+        const Real* t = r1 + d * 3 * 5 * N * Q + c * N * Q + ib * Q;
+        Real w0 = 0, w1 = 0;
+#pragma unroll
+        for (int q0 = 0; q0 < Q; ++q0) {
+            w0 += tb.S[q0][ia] * t[q0] + tb.D[q0][ia] * t[5 * N * Q + q0];
+            w1 += tb.S[q0][ia] * t[2 * 5 * N * Q + q0];
+        }
+        Real* w = r2 + d * 2 * 5 * N2 + c * N2 + ib * N + ia;
+        w[0] = w0;
+        w[5 * N2] = w1;
+    }
+    __syncthreads();
+
+    // R[c](a, b, m) += sum_f W0_f(a, b) l_m(s) + W1_f(a, b) l'_m(s)
+    for (int it = tid; it < 5 * N3; it += nth) {
+        const int c = it / N3, r = it % N3;
+        const int x0 = r % N, x1 = (r / N) % N, x2 = r / N2;
+        const Real* w = r2 + c * N2;
+        // face d = 0: (a, b, m) = (x1, x2, x0); d = 1: (x0, x2, x1); d = 2: (x0, x1, x2)
+        Real acc = w[0 * 2 * 5 * N2 + x2 * N + x1] * tb.fv[s][x0] + w[(0 * 2 + 1) * 5 * N2 + x2 * N + x1] * tb.fd[s][x0];
+        acc += w[1 * 2 * 5 * N2 + x2 * N + x0] * tb.fv[s][x1] + w[(1 * 2 + 1) * 5 * N2 + x2 * N + x0] * tb.fd[s][x1];
+        acc += w[2 * 2 * 5 * N2 + x1 * N + x0] * tb.fv[s][x2] + w[(2 * 2 + 1) * 5 * N2 + x1 * N + x0] * tb.fd[s][x2];
+        sR[it] += acc;
+    }
+    __syncthreads();
+}
+
+template <int N, int Q, typename Real, bool GEN>
 __global__ void __launch_bounds__(kBlock)
 dg_operator_kernel(OpArgs a, KTab<N, Q, Real> tb, MTab<N, Real> mt) {
-    using Sz = OpSizes<N, Q, P>;
-    constexpr int N2 = Sz::N2, N3 = Sz::N3, Q2 = Sz::Q2, Q3 = Sz::Q3;
+    using Sz = OpSizes<N, Q>;
+    constexpr int P = Sz::P;
+    constexpr int N2 = N * N, N3 = N2 * N, Q2 = Q * Q, Q3 = Q2 * Q;
+    constexpr int ZS = CellSizes<N, Q, P>::Z, YS = CellSizes<N, Q, P>::Y;
     __shared__ Real sU[5 * N3];
     __shared__ Real sR[5 * N3];
     __shared__ Real sW[Sz::WORK];
+    __shared__ FaceInfo fi;
+    __shared__ Real sTau[6];
 
     const int64_t e = blockIdx.x;
-    const int tid = threadIdx.x;
+    const int tid = threadIdx.x, nth = blockDim.x;
     const Phys<Real> ph = make_phys<Real>(a);
     const bool conv = (a.terms & 1u) != 0;
     const bool visc = (a.terms & 2u) != 0;
     const int64_t cstride = a.ncell * N3;
 
-    for (int i = tid; i < 5 * N3; i += blockDim.x) {
+    for (int i = tid; i < 5 * N3; i += nth) {
         const int c = i / N3, j = i % N3;
         sU[i] = (Real)a.U[c * cstride + e * N3 + j];
         sR[i] = Real(0);
+    }
+    for (int f = tid; f < 6; f += nth) {
+        const int i0 = (int)(e % a.n[0]), i1 = (int)((e / a.n[0]) % a.n[1]), i2 = (int)(e / ((int64_t)a.n[0] * a.n[1]));
+        const int d = f % 3, s = f / 3;
+        const int nd = d == 0 ? a.n[0] : (d == 1 ? a.n[1] : a.n[2]);
+        const int per = d == 0 ? a.periodic[0] : (d == 1 ? a.periodic[1] : a.periodic[2]);
+        const int id = d == 0 ? i0 : (d == 1 ? i1 : i2);
+        // tangential indices (t0 < t1) and the extent of t0
+        const int it0 = d == 0 ? i1 : i0, it1 = d == 2 ? i1 : i2;
+        const int nt0 = d == 0 ? a.n[1] : a.n[0];
+        int jd = id + (s ? 1 : -1);
+        int wall = 0;
+        if (jd < 0 || jd >= nd) {
+            if (per) jd = (jd + nd) % nd;
+            else wall = 1;
+        }
+        const int j0 = d == 0 ? jd : i0, j1 = d == 1 ? jd : i1, j2 = d == 2 ? jd : i2;
+        fi.enb[f] = wall ? e : j0 + (int64_t)a.n[0] * (j1 + (int64_t)a.n[1] * j2);
+        fi.fid[f] = (id + s) + (int64_t)(nd + 1) * (it0 + (int64_t)nt0 * it1);
+        fi.wall[f] = wall;
+        const double* tf = d == 0 ? a.tau_face[0] : (d == 1 ? a.tau_face[1] : a.tau_face[2]);
+        sTau[f] = (Real)tf[fi.fid[f]];
     }
 
     // cell-constant metric (affine)
@@ -410,16 +440,15 @@ dg_operator_kernel(OpArgs a, KTab<N, Q, Real> tb, MTab<N, Real> mt) {
         for (int m = 0; m < 9; ++m) Ji[m] = (Real)a.cell_metric[e * 10 + m];
         detJ = (Real)a.cell_metric[e * 10 + 9];
     }
-    const int i0 = (int)(e % a.n[0]), i1 = (int)((e / a.n[0]) % a.n[1]), i2 = (int)(e / ((int64_t)a.n[0] * a.n[1]));
     __syncthreads();
 
     if (conv || visc) {
         // ------------------------------------------------------------ cell term
         Real* sZ = sW;
-        Real* sY = sW + Sz::Z;       // later sB
-        Real* sF = sY + Sz::Y;       // later sE
+        Real* sY = sW + ZS;       // later sB
+        Real* sF = sY + YS;       // later sE
         // z-sweep: Z0 = S_z U, Z1 = D_z U     layout [kind][c][pz][a1][a0]
-        for (int it = tid; it < 5 * N2; it += blockDim.x) {
+        for (int it = tid; it < 5 * N2; it += nth) {
             const int c = it / N2, r = it % N2;
             Real v[N];
 #pragma unroll
@@ -440,8 +469,7 @@ dg_operator_kernel(OpArgs a, KTab<N, Q, Real> tb, MTab<N, Real> mt) {
 
         for (int pz0 = 0; pz0 < Q; pz0 += P) {
             // y-sweep for planes pz0..pz0+P-1: Y00 = S_y Z0, Y10 = D_y Z0, Y01 = S_y Z1
-            // layout sY[kind][c][pl][py][a0]
-            for (int it = tid; it < 5 * P * N; it += blockDim.x) {
+            for (int it = tid; it < 5 * P * N; it += nth) {
                 const int a0 = it % N, pl = (it / N) % P, c = it / (N * P);
                 const int pz = pz0 + pl;
                 if (pz >= Q) continue;
@@ -468,7 +496,7 @@ dg_operator_kernel(OpArgs a, KTab<N, Q, Real> tb, MTab<N, Real> mt) {
             __syncthreads();
 
             // x-sweep + pointwise physics, one thread per quadrature point
-            for (int it = tid; it < P * Q2; it += blockDim.x) {
+            for (int it = tid; it < P * Q2; it += nth) {
                 const int px = it % Q, py = (it / Q) % Q, pl = it / Q2;
                 const int pz = pz0 + pl;
                 if (pz >= Q) continue;
@@ -503,29 +531,24 @@ dg_operator_kernel(OpArgs a, KTab<N, Q, Real> tb, MTab<N, Real> mt) {
                     for (int m = 0; m < 9; ++m) J[m] = Ji[m];
                     jxw = detJ * tb.w[px] * tb.w[py] * tb.w[pz];
                 }
-                // physical gradient G[c][j] = sum_d Jinv[d][j] Gr[c][d]
-                Real G[5][3];
-#pragma unroll
-                for (int c = 0; c < 5; ++c)
-#pragma unroll
-                    for (int j = 0; j < 3; ++j)
-                        G[c][j] = J[0 * 3 + j] * Gr[c][0] + J[1 * 3 + j] * Gr[c][1] + J[2 * 3 + j] * Gr[c][2];
+                const Prim<Real> sq = primitives(Uq, ph);
                 Real F[5][3];
-#pragma unroll
-                for (int c = 0; c < 5; ++c)
-#pragma unroll
-                    for (int j = 0; j < 3; ++j) F[c][j] = 0;
                 if (conv) {
-                    Real Fc[5][3];
-                    convective_flux(Uq, ph, Fc);
+                    convective_flux(Uq, sq, F);
+                } else {
 #pragma unroll
                     for (int c = 0; c < 5; ++c)
 #pragma unroll
-                        for (int j = 0; j < 3; ++j) F[c][j] += Fc[c][j];
+                        for (int j = 0; j < 3; ++j) F[c][j] = 0;
                 }
                 if (visc) {
-                    Real Fv[5][3];
-                    viscous_flux(Uq, G, ph, Fv);
+                    Real G[5][3], Fv[5][3];
+#pragma unroll
+                    for (int c = 0; c < 5; ++c)
+#pragma unroll
+                        for (int j = 0; j < 3; ++j)
+                            G[c][j] = J[0 * 3 + j] * Gr[c][0] + J[1 * 3 + j] * Gr[c][1] + J[2 * 3 + j] * Gr[c][2];
+                    viscous_flux(sq, G, ph, Fv);
 #pragma unroll
                     for (int c = 0; c < 5; ++c)
 #pragma unroll
@@ -544,7 +567,7 @@ dg_operator_kernel(OpArgs a, KTab<N, Q, Real> tb, MTab<N, Real> mt) {
 
             // x-transposed: B1 = D_x^T F_0, B2 = S_x^T F_1, B3 = S_x^T F_2   layout [kind][c][pl][py][a0]
             Real* sB = sY;
-            for (int it = tid; it < 5 * P * Q * N; it += blockDim.x) {
+            for (int it = tid; it < 5 * P * Q * N; it += nth) {
                 const int a0 = it % N, py = (it / N) % Q, pl = (it / (N * Q)) % P, c = it / (N * Q * P);
                 if (pz0 + pl >= Q) continue;
                 Real b1 = 0, b2 = 0, b3 = 0;
@@ -562,7 +585,7 @@ dg_operator_kernel(OpArgs a, KTab<N, Q, Real> tb, MTab<N, Real> mt) {
 
             // y-transposed: E1 = S_y^T B1 + D_y^T B2, E2 = S_y^T B3   layout [kind][c][pl][a1][a0]
             Real* sE = sF;
-            for (int it = tid; it < 5 * P * N2; it += blockDim.x) {
+            for (int it = tid; it < 5 * P * N2; it += nth) {
                 const int a0 = it % N, a1 = (it / N) % N, pl = (it / N2) % P, c = it / (N2 * P);
                 if (pz0 + pl >= Q) continue;
                 Real e1 = 0, e2 = 0;
@@ -578,7 +601,7 @@ dg_operator_kernel(OpArgs a, KTab<N, Q, Real> tb, MTab<N, Real> mt) {
             __syncthreads();
 
             // z-transposed, accumulated over the chunk's planes: R += S_z^T E1 + D_z^T E2
-            for (int it = tid; it < 5 * N3; it += blockDim.x) {
+            for (int it = tid; it < 5 * N3; it += nth) {
                 const int c = it / N3, r = it % N3, a2 = r / N2, r2 = r % N2;
                 Real acc = 0;
 #pragma unroll
@@ -594,9 +617,8 @@ dg_operator_kernel(OpArgs a, KTab<N, Q, Real> tb, MTab<N, Real> mt) {
         }
 
         // ------------------------------------------------------------ face terms
-        face_terms<0, N, Q, Real, GEN, Sz>(a, tb, ph, conv, visc, e, i0, i1, i2, Ji, detJ, sU, sR, sW);
-        face_terms<1, N, Q, Real, GEN, Sz>(a, tb, ph, conv, visc, e, i0, i1, i2, Ji, detJ, sU, sR, sW);
-        face_terms<2, N, Q, Real, GEN, Sz>(a, tb, ph, conv, visc, e, i0, i1, i2, Ji, detJ, sU, sR, sW);
+        face_group<N, Q, Real, GEN>(a, tb, ph, conv, visc, 0, e, fi, sTau, Ji, detJ, sU, sR, sW);
+        face_group<N, Q, Real, GEN>(a, tb, ph, conv, visc, 1, e, fi, sTau, Ji, detJ, sU, sR, sW);
     }
 
     // ------------------------------------------------------------ body force (k+1 rule)
@@ -612,7 +634,7 @@ dg_operator_kernel(OpArgs a, KTab<N, Q, Real> tb, MTab<N, Real> mt) {
         __syncthreads();
         sweep_nn<N, Real, false>(mt.Sm, t1b, t0b, 2);
         __syncthreads();
-        for (int p = tid; p < N3; p += blockDim.x) {
+        for (int p = tid; p < N3; p += nth) {
             Real jxw;
             if constexpr (GEN) jxw = (Real)jxw_m[p];
             else jxw = detJ * mt.wm[p % N] * mt.wm[(p / N) % N] * mt.wm[p / N2];
@@ -632,13 +654,13 @@ dg_operator_kernel(OpArgs a, KTab<N, Q, Real> tb, MTab<N, Real> mt) {
         __syncthreads();
         sweep_nn<N, Real, true>(mt.Sm, t0b, t1b, 2);
         __syncthreads();
-        for (int i = tid; i < 5 * N3; i += blockDim.x) sR[i] += t1b[i];
+        for (int i = tid; i < 5 * N3; i += nth) sR[i] += t1b[i];
         __syncthreads();
     }
 
     if (a.fuse_minv) inverse_mass_lds<N, Real, GEN>(mt, sR, sW, detJ, jxw_m);
 
-    for (int i = tid; i < 5 * N3; i += blockDim.x) {
+    for (int i = tid; i < 5 * N3; i += nth) {
         const int c = i / N3, j = i % N3;
         a.out[c * cstride + e * N3 + j] = (double)sR[i];
     }
@@ -663,11 +685,9 @@ inverse_mass_kernel(const double* R, double* L, int64_t ncell, const double* cel
     for (int i = threadIdx.x; i < 5 * N3; i += blockDim.x) L[(i / N3) * cs + e * N3 + i % N3] = (double)sR[i];
 }
 
-// ------------------------------------------------------------------ dispatch
-template <int N, int Q, typename Real, bool GEN>
-inline int launch_op_t(const OpArgs& a, const Tables1D& t, hipStream_t st) {
-    KTab<N, Q, Real> kt;
-    MTab<N, Real> mt;
+// ------------------------------------------------------------------ launchers
+template <int N, int Q, typename Real>
+inline void fill_tables(const Tables1D& t, KTab<N, Q, Real>& kt, MTab<N, Real>& mt) {
     for (int p = 0; p < Q; ++p) {
         for (int i = 0; i < N; ++i) {
             kt.S[p][i] = (Real)t.S[p][i];
@@ -687,10 +707,15 @@ inline int launch_op_t(const OpArgs& a, const Tables1D& t, hipStream_t st) {
         }
         mt.wm[i] = (Real)t.wm[i];
     }
-    // all n_q planes at once while the workgroup stays within 64 KB of LDS, else one plane at a time
-    constexpr int P = (OpSizes<N, Q, Q>::WORK + 10 * N * N * N) * (int)sizeof(Real) <= 64 * 1024 ? Q : 1;
-    static_assert((OpSizes<N, Q, P>::WORK + 10 * N * N * N) * sizeof(Real) <= 160 * 1024, "LDS budget");
-    hipLaunchKernelGGL((dg_operator_kernel<N, Q, Real, GEN, P>), dim3((unsigned)a.ncell), dim3(kBlock), 0, st, a, kt, mt);
+}
+
+template <int N, int Q, typename Real, bool GEN>
+inline int launch_op_t(const OpArgs& a, const Tables1D& t, hipStream_t st) {
+    KTab<N, Q, Real> kt;
+    MTab<N, Real> mt;
+    fill_tables<N, Q, Real>(t, kt, mt);
+    static_assert((OpSizes<N, Q>::WORK + 10 * N * N * N) * sizeof(Real) <= 160 * 1024, "LDS budget");
+    hipLaunchKernelGGL((dg_operator_kernel<N, Q, Real, GEN>), dim3((unsigned)a.ncell), dim3(kBlock), 0, st, a, kt, mt);
     return hipGetLastError() == hipSuccess ? 0 : -1;
 }
 
