@@ -150,6 +150,32 @@ __device__ __forceinline__ void viscous_flux(const Prim<Real>& s, const Real G[5
     }
 }
 
+// F -= F_v(U, G): the viscous flux subtracted in place (rows 1..4).
+template <typename Real>
+__device__ __forceinline__ void subtract_viscous_flux(const Prim<Real>& s, const Real G[5][3], const Phys<Real>& ph,
+                                                      Real F[5][3]) {
+    const Real rinv = s.rinv;
+    Real gu[3][3];
+#pragma unroll
+    for (int a = 0; a < 3; ++a)
+#pragma unroll
+        for (int j = 0; j < 3; ++j) gu[a][j] = (G[1 + a][j] - s.u[a] * G[0][j]) * rinv;
+    const Real dd = Real(2.0 / 3.0) * (gu[0][0] + gu[1][1] + gu[2][2]);
+    const Real lam_cv = ph.lam * ph.inv_cv;
+#pragma unroll
+    for (int j = 0; j < 3; ++j) {
+        const Real gT = (G[4][j] - s.E * G[0][j]) * rinv - (s.u[0] * gu[0][j] + s.u[1] * gu[1][j] + s.u[2] * gu[2][j]);
+        Real tu = 0;
+#pragma unroll
+        for (int a = 0; a < 3; ++a) {
+            const Real t = ph.mu * (gu[a][j] + gu[j][a] - (a == j ? dd : Real(0)));   // tau_aj = tau_ja
+            F[1 + a][j] -= t;
+            tu += t * s.u[a];
+        }
+        F[4][j] -= tu + lam_cv * gT;
+    }
+}
+
 // F_v(U, G) . n, the viscous flux in direction n (five values, the first zero).
 template <typename Real>
 __device__ __forceinline__ void viscous_flux_normal(const Prim<Real>& s, const Real G[5][3], const Real n[3],

@@ -175,7 +175,8 @@ __device__ __forceinline__ void load_face_point(const KTab<N, Q, Real>& tb, cons
 template <int N, int Q, typename Real, bool GEN>
 __device__ __forceinline__ void face_group(const OpArgs& a, const KTab<N, Q, Real>& tb, const Phys<Real>& ph, bool conv,
                                            bool visc, int s, int64_t e, const FaceInfo& fi, const Real* sTau,
-                                           const Real (&Ji)[9], Real detJ, const Real* sU, Real* sR, Real* sW) {
+                                           const Real* sFn, const Real (&Ji)[9], Real detJ, const Real* sU, Real* sR,
+                                           Real* sW) {
     using FS = FaceSizes<N, Q>;
     constexpr int N2 = N * N, N3 = N2 * N, Q2 = Q * Q;
     Real* r1 = sW;
@@ -246,70 +247,86 @@ __device__ __forceinline__ void face_group(const OpArgs& a, const KTab<N, Q, Rea
         const int d = it / Q2, pt = it % Q2, q0 = pt % Q, q1 = pt / Q;
         const int fslot = d + 3 * s;
         const bool wall = fi.wall[fslot] != 0;
-        Real Jm[9], Jp[9], nrm[3], dAw;
+        Real Jm[9], nrm[3], dAw;
+        const double* fdp = nullptr;
         if constexpr (GEN) {
-            const double* fd = a.face_data[d] + fi.fid[fslot] * 22 * Q2 + pt;
+            fdp = a.face_data[d] + fi.fid[fslot] * 22 * Q2 + pt;
             const Real sgn = s ? Real(1) : Real(-1);
 #pragma unroll
-            for (int j = 0; j < 3; ++j) nrm[j] = sgn * (Real)fd[j * Q2];
-            dAw = (Real)fd[3 * Q2];
-            const int own = s ? 4 : 13, oth = s ? 13 : 4;
+            for (int j = 0; j < 3; ++j) nrm[j] = sgn * (Real)fdp[j * Q2];
+            dAw = (Real)fdp[3 * Q2];
+            const int own = s ? 4 : 13;
 #pragma unroll
-            for (int m = 0; m < 9; ++m) {
-                Jm[m] = (Real)fd[(own + m) * Q2];
-                Jp[m] = (Real)fd[(oth + m) * Q2];
-            }
+            for (int m = 0; m < 9; ++m) Jm[m] = (Real)fdp[(own + m) * Q2];
         } else {
 #pragma unroll
             for (int m = 0; m < 9; ++m) Jm[m] = Ji[m];
-            const double* cm = a.cell_metric + fi.enb[fslot] * 10;
-#pragma unroll
-            for (int m = 0; m < 9; ++m) Jp[m] = (Real)cm[m];
             const Real sgn = s ? Real(1) : Real(-1);
-            const Real j0 = d == 0 ? Ji[0] : (d == 1 ? Ji[3] : Ji[6]);
-            const Real j1 = d == 0 ? Ji[1] : (d == 1 ? Ji[4] : Ji[7]);
-            const Real j2 = d == 0 ? Ji[2] : (d == 1 ? Ji[5] : Ji[8]);
-            const Real l = sqrt(j0 * j0 + j1 * j1 + j2 * j2);
-            nrm[0] = sgn * j0 / l;
-            nrm[1] = sgn * j1 / l;
-            nrm[2] = sgn * j2 / l;
-            dAw = detJ * l * tb.w[q0] * tb.w[q1];
+            const Real* fn = sFn + 4 * d;     // unit normal of face xi_d = 1 and |row d of J^{-1}|
+            nrm[0] = sgn * fn[0];
+            nrm[1] = sgn * fn[1];
+            nrm[2] = sgn * fn[2];
+            dAw = detJ * fn[3] * tb.w[q0] * tb.w[q1];
         }
-        // one side at a time, to keep a single gradient live: value, physical gradient,
-        // F_c.n, F_v.n and the wave speed of each side
-        Real Um[5], Up[5], Fcm[5], Fcp[5], Fvm[5], Fvp[5], lam_m = 0, lam_p = 0;
-        Prim<Real> sm, sp;
+        // one side at a time, to keep a single gradient live: the side's value,
+        // physical gradient, F_c.n and F_v.n go straight into the point's coefficient
+        //   val = -1/2 (F_c^- + F_c^+).n + 1/2 (F_v^- + F_v^+).n - (Lambda/2 + tau)(U^- - U^+)
+        Real Um[5], Up[5], val[5], lam_m = 0, lam_p = 0;
+        Prim<Real> sm;
         {
-            Real G[5][3];
+            Real G[5][3], Fn[5];
             load_face_point<N, Q, Real>(tb, r1 + (d * 2 + 0) * 3 * 5 * N * Q, d, q0, q1, Jm, Um, G);
             sm = primitives(Um, ph);
-            if (conv) lam_m = convective_normal(Um, sm, nrm, ph, Fcm);
-            if (visc) viscous_flux_normal(sm, G, nrm, ph, Fvm);
+#pragma unroll
+            for (int c = 0; c < 5; ++c) val[c] = 0;
+            if (conv) {
+                lam_m = convective_normal(Um, sm, nrm, ph, Fn);
+#pragma unroll
+                for (int c = 0; c < 5; ++c) val[c] -= Real(0.5) * Fn[c];
+            }
+            if (visc) {
+                viscous_flux_normal(sm, G, nrm, ph, Fn);
+#pragma unroll
+                for (int c = 0; c < 5; ++c) val[c] += Real(0.5) * Fn[c];
+            }
             if (wall) {
-                wall_mirror(Um, sm, ph, Up);
+                wall_mirror(Um, sm, ph, Up);   // the exterior gradient is the interior one: G is kept
             } else {
+                Real Jp[9];
+                if constexpr (GEN) {
+                    const int oth = s ? 13 : 4;
+#pragma unroll
+                    for (int m = 0; m < 9; ++m) Jp[m] = (Real)fdp[(oth + m) * Q2];
+                } else {
+                    const double* cm = a.cell_metric + fi.enb[fslot] * 10;
+#pragma unroll
+                    for (int m = 0; m < 9; ++m) Jp[m] = (Real)cm[m];
+                }
                 load_face_point<N, Q, Real>(tb, r1 + (d * 2 + 1) * 3 * 5 * N * Q, d, q0, q1, Jp, Up, G);
             }
-            sp = primitives(Up, ph);
-            if (conv) lam_p = convective_normal(Up, sp, nrm, ph, Fcp);
-            if (visc) viscous_flux_normal(sp, G, nrm, ph, Fvp);   // at walls G is the interior gradient
-        }
-        const Real tau = sTau[fslot];
-        Real val[5], jump[5];
+            const Prim<Real> sp = primitives(Up, ph);
+            if (conv) {
+                lam_p = convective_normal(Up, sp, nrm, ph, Fn);
 #pragma unroll
-        for (int c = 0; c < 5; ++c) {
-            val[c] = 0;
-            jump[c] = Um[c] - Up[c];
+                for (int c = 0; c < 5; ++c) val[c] -= Real(0.5) * Fn[c];
+            }
+            if (visc) {
+                viscous_flux_normal(sp, G, nrm, ph, Fn);
+#pragma unroll
+                for (int c = 0; c < 5; ++c) val[c] += Real(0.5) * Fn[c];
+            }
+        }
+        Real jump[5];
+#pragma unroll
+        for (int c = 0; c < 5; ++c) jump[c] = Um[c] - Up[c];
+        {
+            const Real lam = lam_m > lam_p ? lam_m : lam_p;
+            const Real pen = (conv ? Real(0.5) * lam : Real(0)) + (visc ? sTau[fslot] : Real(0));
+#pragma unroll
+            for (int c = 0; c < 5; ++c) val[c] -= pen * jump[c];
         }
         Real gphys[5][3];
-        if (conv) {
-            const Real lam = lam_m > lam_p ? lam_m : lam_p;
-#pragma unroll
-            for (int c = 0; c < 5; ++c) val[c] -= Real(0.5) * (Fcm[c] + Fcp[c]) + Real(0.5) * lam * jump[c];
-        }
         if (visc) {
-#pragma unroll
-            for (int c = 0; c < 5; ++c) val[c] += Real(0.5) * (Fvm[c] + Fvp[c]) - tau * jump[c];
             viscous_flux_rank1(sm, jump, nrm, ph, gphys);
         } else {
 #pragma unroll
@@ -397,6 +414,7 @@ dg_operator_kernel(OpArgs a, KTab<N, Q, Real> tb, MTab<N, Real> mt) {
     __shared__ Real sW[Sz::WORK];
     __shared__ FaceInfo fi;
     __shared__ Real sTau[6];
+    __shared__ Real sFn[12];   // affine: per direction the unit normal and |row of J^{-1}|
 
     const int64_t e = blockIdx.x;
     const int tid = threadIdx.x, nth = blockDim.x;
@@ -431,6 +449,14 @@ dg_operator_kernel(OpArgs a, KTab<N, Q, Real> tb, MTab<N, Real> mt) {
         fi.wall[f] = wall;
         const double* tf = d == 0 ? a.tau_face[0] : (d == 1 ? a.tau_face[1] : a.tau_face[2]);
         sTau[f] = (Real)tf[fi.fid[f]];
+        if (!GEN && s == 0) {
+            const double* row = a.cell_metric + e * 10 + 3 * d;
+            const double l = sqrt(row[0] * row[0] + row[1] * row[1] + row[2] * row[2]);
+            sFn[4 * d + 0] = (Real)(row[0] / l);
+            sFn[4 * d + 1] = (Real)(row[1] / l);
+            sFn[4 * d + 2] = (Real)(row[2] / l);
+            sFn[4 * d + 3] = (Real)l;
+        }
     }
 
     // cell-constant metric (affine)
@@ -542,17 +568,14 @@ dg_operator_kernel(OpArgs a, KTab<N, Q, Real> tb, MTab<N, Real> mt) {
                         for (int j = 0; j < 3; ++j) F[c][j] = 0;
                 }
                 if (visc) {
-                    Real G[5][3], Fv[5][3];
+                    // physical gradient in place: Gr <- J^{-T} Gr
 #pragma unroll
-                    for (int c = 0; c < 5; ++c)
+                    for (int c = 0; c < 5; ++c) {
+                        const Real g0 = Gr[c][0], g1 = Gr[c][1], g2 = Gr[c][2];
 #pragma unroll
-                        for (int j = 0; j < 3; ++j)
-                            G[c][j] = J[0 * 3 + j] * Gr[c][0] + J[1 * 3 + j] * Gr[c][1] + J[2 * 3 + j] * Gr[c][2];
-                    viscous_flux(sq, G, ph, Fv);
-#pragma unroll
-                    for (int c = 0; c < 5; ++c)
-#pragma unroll
-                        for (int j = 0; j < 3; ++j) F[c][j] -= Fv[c][j];
+                        for (int j = 0; j < 3; ++j) Gr[c][j] = J[0 * 3 + j] * g0 + J[1 * 3 + j] * g1 + J[2 * 3 + j] * g2;
+                    }
+                    subtract_viscous_flux(sq, Gr, ph, F);
                 }
                 // reference flux: w|J| J^{-1} F
 #pragma unroll
@@ -617,8 +640,8 @@ dg_operator_kernel(OpArgs a, KTab<N, Q, Real> tb, MTab<N, Real> mt) {
         }
 
         // ------------------------------------------------------------ face terms
-        face_group<N, Q, Real, GEN>(a, tb, ph, conv, visc, 0, e, fi, sTau, Ji, detJ, sU, sR, sW);
-        face_group<N, Q, Real, GEN>(a, tb, ph, conv, visc, 1, e, fi, sTau, Ji, detJ, sU, sR, sW);
+        face_group<N, Q, Real, GEN>(a, tb, ph, conv, visc, 0, e, fi, sTau, sFn, Ji, detJ, sU, sR, sW);
+        face_group<N, Q, Real, GEN>(a, tb, ph, conv, visc, 1, e, fi, sTau, sFn, Ji, detJ, sU, sR, sW);
     }
 
     // ------------------------------------------------------------ body force (k+1 rule)
