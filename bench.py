@@ -113,6 +113,11 @@ def main():
     ap.add_argument("--cpu-sample-cells", type=int, default=4096)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-fp32", action="store_true")
+    ap.add_argument("--op-only", type=int, default=0, metavar="CALLS",
+                    help="profiling mode: only CALLS launches of the float64 operator kernel, no JSON")
+    ap.add_argument("--precision", default="fp64", choices=("fp64", "fp32"), help="precision of --op-only")
+    ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
+                    help="profiling mode: one device-to-device copy of MIB MiB (HBM counter calibration)")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py measures one GPU only: this build has no multi-GPU path (the halo-exchange "
@@ -122,7 +127,26 @@ def main():
     import torch
     from paper_1806_03095_amd import taylor_green
 
+    if args.copy_calibration:
+        n = args.copy_calibration * (1 << 20) // 8
+        a = torch.ones(n, dtype=torch.float64, device="cuda")
+        b = torch.empty_like(a)
+        torch.cuda.synchronize()
+        b.copy_(a)
+        torch.cuda.synchronize()
+        log("copied %d MiB (read %d B, write %d B)" % (args.copy_calibration, 8 * n, 8 * n))
+        return
+
     k, nq, ne = args.degree, args.nq, args.cells
+    if args.op_only:
+        op = taylor_green(k, ne, n_q=nq, precision=args.precision)
+        U0 = op.project_ic("taylor_green", [1.0, 1.0, 0.1, 1.0])
+        L = torch.empty_like(U0)
+        for _ in range(args.op_only):
+            op.apply(U0, L)
+        torch.cuda.synchronize()
+        log("%d operator launches (%s), %d DoFs each" % (args.op_only, args.precision, op.n_dof))
+        return
     log("workload: TGV %d^3 cells, k=%d, n_q=%d" % (ne, k, nq))
     op = taylor_green(k, ne, n_q=nq, precision="fp64")
     ndof = op.n_dof
