@@ -156,6 +156,35 @@ int dgns_diagnostics(dgns_ctx* ctx, const double* U, const double* L, double* ou
  * projection).  U: device output. */
 int dgns_project_ic(dgns_ctx* ctx, int ic, const double* ic_params, const double* noise, double* U);
 
+/* ---------------------------------------------------------------- adjoint
+ * Hand-written reverse-mode derivatives of the operator above (float64 contexts,
+ * degree <= 5).  They differentiate exactly what the forward entry points
+ * compute: the Lax-Friedrichs max() takes the derivative of the selected side
+ * (the interior one only when it is strictly larger). */
+
+/* Ubar = (dR/dU)^T Rbar for the residual of dgns_apply_residual with the same
+ * term_mask.  U, Rbar, Ubar: device, n_dof doubles; Ubar must not overlap U or Rbar. */
+int dgns_apply_residual_vjp(dgns_ctx* ctx, const double* U, const double* Rbar, double* Ubar, unsigned term_mask);
+
+/* Ubar = (dL/dU)^T Lbar for L = M^{-1}(-F_c - F_v + F_rhs)(U) (M is symmetric, so
+ * Ubar = (dR/dU)^T M^{-1} Lbar).  Uses a context-owned device scratch vector of
+ * n_dof doubles, allocated on the first call (DGNS_ENOMEM if that fails). */
+int dgns_apply_operator_vjp(dgns_ctx* ctx, const double* U, const double* Lbar, double* Ubar);
+
+/* Reverse of one dgns_rk_step from U_n: Ubar_n = (dU_{n+1}/dU_n)^T Ubar_np1.
+ * The five stage states are recomputed from U_n.  work: device scratch of at
+ * least 9*n_dof doubles owned by the caller.  Ubar_n may equal Ubar_np1 (in
+ * place) but must not otherwise overlap any argument. */
+int dgns_rk_step_vjp(dgns_ctx* ctx, const double* U_n, double t, double dt, const double* Ubar_np1,
+                     double* Ubar_n, double* work);
+
+/* K = int |u|^2/2 over the domain (n_q rule, u = (rho u)/rho), returned to the
+ * host (synchronises the stream); DGNS_ENONFINITE if not finite. */
+int dgns_kinetic_energy(dgns_ctx* ctx, const double* U, double* ke);
+
+/* Ubar = dK/dU for K of dgns_kinetic_energy.  Ubar must not overlap U. */
+int dgns_kinetic_energy_vjp(dgns_ctx* ctx, const double* U, double* Ubar);
+
 #ifdef __cplusplus
 }
 #endif

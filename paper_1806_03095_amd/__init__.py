@@ -8,3 +8,4 @@ behind the C ABI of include/dgns.h.  This package is the thin Python binding
 
 from .binding import (DgnsError, Operator, load_library, taylor_green, EXPORTS, LIB_PATH,  # noqa: F401
                       TERM_ALL, TERM_CONVECTIVE, TERM_VISCOUS, TERM_FORCE)
+from . import autograd  # noqa: E402,F401

@@ -44,7 +44,8 @@ class BoxMesh(ctypes.Structure):
 
 EXPORTS = ["dgns_last_error", "dgns_create", "dgns_destroy", "dgns_sizes", "dgns_set_stream",
            "dgns_apply_residual", "dgns_apply_inverse_mass", "dgns_apply_operator", "dgns_rk_step",
-           "dgns_compute_dt", "dgns_diagnostics", "dgns_project_ic"]
+           "dgns_compute_dt", "dgns_diagnostics", "dgns_project_ic", "dgns_apply_residual_vjp",
+           "dgns_apply_operator_vjp", "dgns_rk_step_vjp", "dgns_kinetic_energy", "dgns_kinetic_energy_vjp"]
 
 _lib = None
 
@@ -71,6 +72,11 @@ def load_library(path=LIB_PATH):
     lib.dgns_compute_dt.argtypes = [vp] + [ctypes.c_double] * 6 + [dp]
     lib.dgns_diagnostics.argtypes = [vp, vp, vp, dp]
     lib.dgns_project_ic.argtypes = [vp, ctypes.c_int, dp, vp, vp]
+    lib.dgns_apply_residual_vjp.argtypes = [vp, vp, vp, vp, ctypes.c_uint]
+    lib.dgns_apply_operator_vjp.argtypes = [vp, vp, vp, vp]
+    lib.dgns_rk_step_vjp.argtypes = [vp, vp, ctypes.c_double, ctypes.c_double, vp, vp, vp]
+    lib.dgns_kinetic_energy.argtypes = [vp, vp, dp]
+    lib.dgns_kinetic_energy_vjp.argtypes = [vp, vp, vp]
     for name in EXPORTS:
         if name != "dgns_last_error":
             getattr(lib, name).restype = ctypes.c_int
@@ -196,6 +202,53 @@ class Operator:
             return res
         _check(rc)
         return res
+
+    # -- adjoint -------------------------------------------------------------
+    def residual_vjp(self, U, Rbar, out=None, terms=TERM_ALL):
+        """Ubar = (dR/dU)^T Rbar for the residual restricted to `terms`."""
+        self._vec(U, "U")
+        self._vec(Rbar, "Rbar")
+        out = self.empty() if out is None else self._vec(out, "out")
+        self._bind()
+        _check(self.lib.dgns_apply_residual_vjp(self.h, _ptr(U), _ptr(Rbar), _ptr(out), terms))
+        return out
+
+    def operator_vjp(self, U, Lbar, out=None):
+        """Ubar = (dL/dU)^T Lbar."""
+        self._vec(U, "U")
+        self._vec(Lbar, "Lbar")
+        out = self.empty() if out is None else self._vec(out, "out")
+        self._bind()
+        _check(self.lib.dgns_apply_operator_vjp(self.h, _ptr(U), _ptr(Lbar), _ptr(out)))
+        return out
+
+    def rk_step_vjp(self, U_n, t, dt, Ubar_np1, out=None, work=None):
+        """Ubar_n = (dU_{n+1}/dU_n)^T Ubar_{n+1} for one rk_step from U_n (out may be Ubar_np1)."""
+        self._vec(U_n, "U_n")
+        self._vec(Ubar_np1, "Ubar_np1")
+        out = self.empty() if out is None else self._vec(out, "out")
+        if work is None:
+            work = torch.empty(9 * self.n_dof, dtype=torch.float64, device="cuda")
+        elif not (work.is_cuda and work.dtype == torch.float64 and work.is_contiguous() and work.numel() >= 9 * self.n_dof):
+            raise ValueError("work must be a contiguous float64 CUDA tensor of >= 9 n_dof entries")
+        self._bind()
+        _check(self.lib.dgns_rk_step_vjp(self.h, _ptr(U_n), t, dt, _ptr(Ubar_np1), _ptr(out), _ptr(work)))
+        return out
+
+    def kinetic_energy(self, U):
+        """int |u|^2/2 over the domain (host float)."""
+        self._vec(U, "U")
+        out = ctypes.c_double()
+        self._bind()
+        _check(self.lib.dgns_kinetic_energy(self.h, _ptr(U), ctypes.byref(out)))
+        return out.value
+
+    def kinetic_energy_vjp(self, U, out=None):
+        self._vec(U, "U")
+        out = self.empty() if out is None else self._vec(out, "out")
+        self._bind()
+        _check(self.lib.dgns_kinetic_energy_vjp(self.h, _ptr(U), _ptr(out)))
+        return out
 
     def project_ic(self, kind, params, noise=None, out=None):
         out = self.empty() if out is None else self._vec(out, "out")

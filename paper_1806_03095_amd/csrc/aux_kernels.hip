@@ -278,3 +278,80 @@ int launch_channel_perturb(double* U, const double* node_x, const double* noise,
 }
 
 }  // namespace dgns
+
+namespace dgns {
+
+// ------------------------------------------------------------------ adjoint helpers
+__global__ void __launch_bounds__(256) fill_kernel(double* __restrict__ y, int64_t n, double v) {
+    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += stride) y[i] = v;
+}
+
+int launch_fill(double* y, int64_t n, double v, hipStream_t st) {
+    int64_t blocks = (n + 255) / 256;
+    if (blocks > 256 * 64) blocks = 256 * 64;
+    if (blocks < 1) blocks = 1;
+    hipLaunchKernelGGL(fill_kernel, dim3((unsigned)blocks), dim3(256), 0, st, y, n, v);
+    return hipGetLastError() == hipSuccess ? 0 : -1;
+}
+
+__global__ void __launch_bounds__(256) axpby_kernel(double* __restrict__ y, const double* __restrict__ x, int64_t n,
+                                                    double a, double b) {
+    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += stride) y[i] = a * y[i] + b * x[i];
+}
+
+int launch_axpby(double* y, const double* x, int64_t n, double a, double b, hipStream_t st) {
+    int64_t blocks = (n + 255) / 256;
+    if (blocks > 256 * 64) blocks = 256 * 64;
+    if (blocks < 1) blocks = 1;
+    hipLaunchKernelGGL(axpby_kernel, dim3((unsigned)blocks), dim3(256), 0, st, y, x, n, a, b);
+    return hipGetLastError() == hipSuccess ? 0 : -1;
+}
+
+// Ubar_i = sum_q w|J| phi_i(x_q) (-|u|^2/2, u_1, u_2, u_3, 0): the gradient of
+// K = int |u|^2/2 (n_q rule, u = m/rho) with respect to the coefficients U_i.
+__global__ void __launch_bounds__(256) ke_vjp_kernel(OpArgs a, const Tables1D* __restrict__ tp, double* Ub, int gen) {
+    extern __shared__ double sg[];   // [4][Q^3]
+    const Tables1D& t = *tp;
+    const int N = t.n, Q = t.q, N3 = N * N * N, Q3 = Q * Q * Q;
+    const int64_t e = blockIdx.x;
+    const int64_t cs = a.ncell * N3;
+    for (int p = threadIdx.x; p < Q3; p += blockDim.x) {
+        const int p0 = p % Q, p1 = (p / Q) % Q, p2 = p / (Q * Q);
+        double U[4] = {0, 0, 0, 0};
+        for (int i = 0; i < N3; ++i) {
+            const int a0 = i % N, a1 = (i / N) % N, a2 = i / (N * N);
+            const double phi = t.S[p0][a0] * t.S[p1][a1] * t.S[p2][a2];
+            for (int c = 0; c < 4; ++c) U[c] += phi * a.U[c * cs + e * N3 + i];
+        }
+        const double jxw = gen ? a.cell_metric[(e * 10 + 9) * Q3 + p] : a.cell_metric[e * 10 + 9] * t.w[p0] * t.w[p1] * t.w[p2];
+        const double r = 1.0 / U[0];
+        const double u0 = U[1] * r, u1 = U[2] * r, u2 = U[3] * r;
+        sg[p] = -0.5 * (u0 * u0 + u1 * u1 + u2 * u2) * jxw;
+        sg[Q3 + p] = u0 * jxw;
+        sg[2 * Q3 + p] = u1 * jxw;
+        sg[3 * Q3 + p] = u2 * jxw;
+    }
+    __syncthreads();
+    for (int it = threadIdx.x; it < 5 * N3; it += blockDim.x) {
+        const int c = it / N3, i = it % N3;
+        double s = 0;
+        if (c < 4) {
+            const int a0 = i % N, a1 = (i / N) % N, a2 = i / (N * N);
+            for (int p = 0; p < Q3; ++p) {
+                const int p0 = p % Q, p1 = (p / Q) % Q, p2 = p / (Q * Q);
+                s += t.S[p0][a0] * t.S[p1][a1] * t.S[p2][a2] * sg[c * Q3 + p];
+            }
+        }
+        Ub[c * cs + e * N3 + i] = s;
+    }
+}
+
+int launch_kinetic_energy_vjp(const OpArgs& a, const Tables1D* t_dev, int q, double* Ubar, bool gen, hipStream_t st) {
+    const size_t shm = sizeof(double) * 4 * q * q * q;
+    hipLaunchKernelGGL(ke_vjp_kernel, dim3((unsigned)a.ncell), dim3(256), shm, st, a, t_dev, Ubar, gen ? 1 : 0);
+    return hipGetLastError() == hipSuccess ? 0 : -1;
+}
+
+}  // namespace dgns

@@ -29,6 +29,15 @@ int launch_operator_k7(const OpArgs& a, const Tables1D& t, bool fp32, bool gen, 
 int launch_inverse_mass_k7(const double* R, double* L, int64_t ncell, const double* cm, const double* mj,
                             const Tables1D& t, bool fp32, bool gen, hipStream_t st);
 
+// Adjoint of the residual, Ubar = (dR/dU)^T Rbar (float64; degrees 1..5).
+int launch_adjoint_k1(const OpArgs& a, const double* Rb, const Tables1D& t, bool gen, hipStream_t st);
+int launch_adjoint_k2(const OpArgs& a, const double* Rb, const Tables1D& t, bool gen, hipStream_t st);
+int launch_adjoint_k3(const OpArgs& a, const double* Rb, const Tables1D& t, bool gen, hipStream_t st);
+int launch_adjoint_k4(const OpArgs& a, const double* Rb, const Tables1D& t, bool gen, hipStream_t st);
+int launch_adjoint_k5(const OpArgs& a, const double* Rb, const Tables1D& t, bool gen, hipStream_t st);
+int launch_adjoint_k6(const OpArgs& a, const double* Rb, const Tables1D& t, bool gen, hipStream_t st);
+int launch_adjoint_k7(const OpArgs& a, const double* Rb, const Tables1D& t, bool gen, hipStream_t st);
+
 // (degree, n_q) pairs with compiled operator kernels
 constexpr int kSupported[][2] = {{1, 2}, {1, 3}, {2, 3}, {2, 4}, {3, 4}, {3, 5}, {3, 6}, {4, 5}, {4, 6}, {4, 7}, {5, 6}, {5, 8}, {6, 7}, {6, 10}, {7, 8}, {7, 11}};
 
@@ -42,6 +51,15 @@ int launch_diagnostics(const OpArgs& a, const Tables1D* t_dev, const double* L, 
 // L2 projection right-hand side of an analytic initial state, U_rhs = (phi_i, U0).
 int launch_ic_rhs(const OpArgs& a, const Tables1D& t, const Tables1D* t_dev, const double* geo_nodes, int ic,
                   const double* icp, double* out, bool gen, hipStream_t st);
+
+// y <- a y + b x (n doubles).
+int launch_axpby(double* y, const double* x, int64_t n, double a, double b, hipStream_t st);
+
+// Ubar = gradient of int |u|^2/2 (n_q rule) with respect to U.
+int launch_kinetic_energy_vjp(const OpArgs& a, const Tables1D* t_dev, int q, double* Ubar, bool gen, hipStream_t st);
+
+// y <- v (n doubles), a kernel rather than a memset so that it may be captured in graphs.
+int launch_fill(double* y, int64_t n, double v, hipStream_t st);
 
 // Channel perturbation at the nodes: u_a += amp * u1_lam(x2) * noise_a, T kept.
 int launch_channel_perturb(double* U, const double* node_x, const double* noise, int64_t ncell, int n3,

@@ -67,6 +67,7 @@ struct dgns_ctx {
     double* d_partial = nullptr;
     double* d_total = nullptr;
     Tables1D* d_tab = nullptr;
+    double* d_scratch = nullptr;   // n_dof doubles, allocated on the first operator VJP
 };
 
 namespace {
@@ -88,6 +89,7 @@ void free_ctx(dgns_ctx* c) {
     hipFree(c->d_partial);
     hipFree(c->d_total);
     hipFree(c->d_tab);
+    hipFree(c->d_scratch);
 }
 
 OpArgs make_args(const dgns_ctx* c, const double* U, double* out, unsigned terms, int fuse) {
@@ -146,6 +148,22 @@ int dispatch_minv(const dgns_ctx* c, const double* R, double* L) {
     }
     if (rc == 1) return fail(DGNS_EUNSUPPORTED, "no inverse-mass kernel for degree %d", c->k);
     if (rc != 0) return fail(DGNS_EHIP, "inverse-mass launch failed");
+    return 0;
+}
+
+int dispatch_adjoint(const dgns_ctx* c, const OpArgs& a, const double* Rb) {
+    if (c->fp32) return fail(DGNS_EUNSUPPORTED, "the adjoint is float64 only");
+    int rc = 1;
+    switch (c->k) {
+        case 1: rc = launch_adjoint_k1(a, Rb, c->tab, c->gen, c->stream); break;
+        case 2: rc = launch_adjoint_k2(a, Rb, c->tab, c->gen, c->stream); break;
+        case 3: rc = launch_adjoint_k3(a, Rb, c->tab, c->gen, c->stream); break;
+        case 4: rc = launch_adjoint_k4(a, Rb, c->tab, c->gen, c->stream); break;
+        case 5: rc = launch_adjoint_k5(a, Rb, c->tab, c->gen, c->stream); break;
+        default: break;
+    }
+    if (rc == 1) return fail(DGNS_EUNSUPPORTED, "no adjoint kernel for degree %d, n_q %d", c->k, c->q);
+    if (rc != 0) return fail(DGNS_EHIP, "adjoint launch failed: %s", hipGetErrorString(hipGetLastError()));
     return 0;
 }
 
@@ -331,6 +349,106 @@ int dgns_diagnostics(dgns_ctx* c, const double* U, const double* L, double* out8
     for (int i = 0; i < 8; ++i)
         if (i != 2 || L)
             if (!std::isfinite(out8[i])) return fail(DGNS_ENONFINITE, "diagnostic %d is not finite", i);
+    return DGNS_OK;
+}
+
+int dgns_apply_residual_vjp(dgns_ctx* c, const double* U, const double* Rbar, double* Ubar, unsigned term_mask) {
+    if (!c || !U || !Rbar || !Ubar) return fail(DGNS_EINVAL, "null argument");
+    if (!aligned8(U) || !aligned8(Rbar) || !aligned8(Ubar)) return fail(DGNS_EINVAL, "vectors must be 8-byte aligned");
+    if (overlap(Ubar, c->ndof, U, c->ndof) || overlap(Ubar, c->ndof, Rbar, c->ndof))
+        return fail(DGNS_EINVAL, "Ubar overlaps an input");
+    if (term_mask & ~DGNS_TERM_ALL) return fail(DGNS_EINVAL, "unknown term bits");
+    return dispatch_adjoint(c, make_args(c, U, Ubar, term_mask, 0), Rbar);
+}
+
+static int ensure_scratch(dgns_ctx* c) {
+    if (c->d_scratch) return 0;
+    if (hipMalloc((void**)&c->d_scratch, sizeof(double) * c->ndof) != hipSuccess) {
+        c->d_scratch = nullptr;
+        return fail(DGNS_ENOMEM, "operator VJP scratch (%lld doubles)", (long long)c->ndof);
+    }
+    return 0;
+}
+
+int dgns_apply_operator_vjp(dgns_ctx* c, const double* U, const double* Lbar, double* Ubar) {
+    if (!c || !U || !Lbar || !Ubar) return fail(DGNS_EINVAL, "null argument");
+    if (!aligned8(U) || !aligned8(Lbar) || !aligned8(Ubar)) return fail(DGNS_EINVAL, "vectors must be 8-byte aligned");
+    if (overlap(Ubar, c->ndof, U, c->ndof) || overlap(Ubar, c->ndof, Lbar, c->ndof))
+        return fail(DGNS_EINVAL, "Ubar overlaps an input");
+    int rc = ensure_scratch(c);
+    if (rc) return rc;
+    // L = M^{-1} R(U): Ubar = (dR/dU)^T M^{-T} Lbar, and M is symmetric
+    rc = dispatch_minv(c, Lbar, c->d_scratch);
+    if (rc) return rc;
+    return dispatch_adjoint(c, make_args(c, U, Ubar, DGNS_TERM_ALL, 0), c->d_scratch);
+}
+
+int dgns_rk_step_vjp(dgns_ctx* c, const double* U_n, double t, double dt, const double* Ubar_np1, double* Ubar_n,
+                     double* work) {
+    (void)t;
+    if (!c || !U_n || !Ubar_np1 || !Ubar_n || !work) return fail(DGNS_EINVAL, "null argument");
+    if (!aligned8(U_n) || !aligned8(Ubar_np1) || !aligned8(Ubar_n) || !aligned8(work))
+        return fail(DGNS_EINVAL, "vectors must be 8-byte aligned");
+    const int64_t n = c->ndof;
+    if (overlap(work, 9 * n, U_n, n) || overlap(work, 9 * n, Ubar_np1, n) || overlap(work, 9 * n, Ubar_n, n) ||
+        overlap(Ubar_n, n, U_n, n) || (Ubar_n != Ubar_np1 && overlap(Ubar_n, n, Ubar_np1, n)))
+        return fail(DGNS_EINVAL, "overlapping arguments");
+    if (!std::isfinite(dt)) return fail(DGNS_EINVAL, "dt is not finite");
+    double* X = work;               // stage inputs U_1..U_4 (U_0 = U_n)
+    double* dU = work + 4 * n;
+    double* L = work + 5 * n;
+    double* dUb = work + 6 * n;
+    double* Rb = work + 7 * n;
+    double* T = work + 8 * n;
+    // forward recomputation of the stage inputs
+    for (int i = 0; i < 4; ++i) {
+        const double* src = i == 0 ? U_n : X + (int64_t)(i - 1) * n;
+        double* Ui = X + (int64_t)i * n;
+        HIP_TRY(hipMemcpyAsync(Ui, src, sizeof(double) * n, hipMemcpyDeviceToDevice, c->stream));
+        int rc = dispatch_operator(c, make_args(c, src, L, DGNS_TERM_ALL, 1));
+        if (rc) return rc;
+        if (launch_rk_update(Ui, dU, L, n, kRkA[i], kRkB[i], dt, c->stream) != 0)
+            return fail(DGNS_EHIP, "rk update launch failed");
+    }
+    // reverse sweep over the five stages
+    if (Ubar_n != Ubar_np1)
+        HIP_TRY(hipMemcpyAsync(Ubar_n, Ubar_np1, sizeof(double) * n, hipMemcpyDeviceToDevice, c->stream));
+    if (launch_fill(dUb, n, 0.0, c->stream) != 0) return fail(DGNS_EHIP, "fill launch failed");
+    for (int i = 4; i >= 0; --i) {
+        const double* Xi = i == 0 ? U_n : X + (int64_t)(i - 1) * n;
+        // U_i = U_{i-1} + B_i dU_i  ->  dUbar_i += B_i Ubar_i
+        if (launch_axpby(dUb, Ubar_n, n, 1.0, kRkB[i], c->stream) != 0) return fail(DGNS_EHIP, "axpby launch failed");
+        // K_i = L(U_{i-1}), dU_i = A_i dU_{i-1} + dt K_i  ->  Ubar_{i-1} += dt (dL/dU)^T dUbar_i
+        int rc = dispatch_minv(c, dUb, Rb);
+        if (rc) return rc;
+        rc = dispatch_adjoint(c, make_args(c, Xi, T, DGNS_TERM_ALL, 0), Rb);
+        if (rc) return rc;
+        if (launch_axpby(Ubar_n, T, n, 1.0, dt, c->stream) != 0) return fail(DGNS_EHIP, "axpby launch failed");
+        //  dUbar_{i-1} = A_i dUbar_i
+        if (launch_axpby(dUb, dUb, n, kRkA[i], 0.0, c->stream) != 0) return fail(DGNS_EHIP, "axpby launch failed");
+    }
+    return DGNS_OK;
+}
+
+int dgns_kinetic_energy(dgns_ctx* c, const double* U, double* ke) {
+    if (!c || !U || !ke) return fail(DGNS_EINVAL, "null argument");
+    OpArgs a = make_args(c, U, nullptr, 0, 0);
+    if (launch_diagnostics(a, c->d_tab, nullptr, c->d_partial, c->d_total, c->gen, c->stream) != 0)
+        return fail(DGNS_EHIP, "diagnostics launch failed");
+    double tot[9];
+    HIP_TRY(hipMemcpyAsync(tot, c->d_total, sizeof tot, hipMemcpyDeviceToHost, c->stream));
+    HIP_TRY(hipStreamSynchronize(c->stream));
+    *ke = tot[0];
+    if (!std::isfinite(*ke)) return fail(DGNS_ENONFINITE, "kinetic energy is not finite");
+    return DGNS_OK;
+}
+
+int dgns_kinetic_energy_vjp(dgns_ctx* c, const double* U, double* Ubar) {
+    if (!c || !U || !Ubar) return fail(DGNS_EINVAL, "null argument");
+    if (overlap(U, c->ndof, Ubar, c->ndof)) return fail(DGNS_EINVAL, "U and Ubar overlap");
+    OpArgs a = make_args(c, U, nullptr, 0, 0);
+    if (launch_kinetic_energy_vjp(a, c->d_tab, c->q, Ubar, c->gen, c->stream) != 0)
+        return fail(DGNS_EHIP, "kinetic energy VJP launch failed");
     return DGNS_OK;
 }
 

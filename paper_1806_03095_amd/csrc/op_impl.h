@@ -170,6 +170,61 @@ __device__ __forceinline__ void load_face_point(const KTab<N, Q, Real>& tb, cons
     }
 }
 
+// Test integration of the face-point coefficients r2 [f][val, g_t0, g_t1, g_n][c][q1][q0]
+// of the three faces xi_d = s against the cell's basis functions, accumulated
+// into sR: value part through phi_i, gradient part through grad_xi phi_i.
+template <int N, int Q, typename Real>
+__device__ __forceinline__ void face_test_accumulate(const KTab<N, Q, Real>& tb, int s, Real* r1, Real* r2, Real* sR) {
+    constexpr int N2 = N * N, N3 = N2 * N, Q2 = Q * Q;
+    const int tid = threadIdx.x, nth = blockDim.x;
+    // transposed along t1: P0 = S^T val + D^T g_t1, P1 = S^T g_t0, Pn = S^T g_n    r1 [f][3][c][b][q0]
+    for (int it = tid; it < 3 * 5 * N * Q; it += nth) {
+        const int q0 = it % Q, ib = (it / Q) % N, c = (it / (Q * N)) % 5, d = it / (5 * Q * N);
+        const Real* o = r2 + d * 4 * 5 * Q2 + c * Q2 + q0;
+        Real p0 = 0, p1 = 0, pn = 0;
+#pragma unroll
+        for (int q1 = 0; q1 < Q; ++q1) {
+            p0 += tb.S[q1][ib] * o[q1 * Q] + tb.D[q1][ib] * o[2 * 5 * Q2 + q1 * Q];
+            p1 += tb.S[q1][ib] * o[1 * 5 * Q2 + q1 * Q];
+            pn += tb.S[q1][ib] * o[3 * 5 * Q2 + q1 * Q];
+        }
+        Real* t = r1 + d * 3 * 5 * N * Q + c * N * Q + ib * Q + q0;
+        t[0] = p0;
+        t[5 * N * Q] = p1;
+        t[2 * 5 * N * Q] = pn;
+    }
+    __syncthreads();
+
+    // transposed along t0: W0 = S^T P0 + D^T P1, W1 = S^T Pn    r2 [f][2][c][b][a]
+    for (int it = tid; it < 3 * 5 * N2; it += nth) {
+        const int ia = it % N, ib = (it / N) % N, c = (it / N2) % 5, d = it / (5 * N2);
+        const Real* t = r1 + d * 3 * 5 * N * Q + c * N * Q + ib * Q;
+        Real w0 = 0, w1 = 0;
+#pragma unroll
+        for (int q0 = 0; q0 < Q; ++q0) {
+            w0 += tb.S[q0][ia] * t[q0] + tb.D[q0][ia] * t[5 * N * Q + q0];
+            w1 += tb.S[q0][ia] * t[2 * 5 * N * Q + q0];
+        }
+        Real* w = r2 + d * 2 * 5 * N2 + c * N2 + ib * N + ia;
+        w[0] = w0;
+        w[5 * N2] = w1;
+    }
+    __syncthreads();
+
+    // R[c](a, b, m) += sum_f W0_f(a, b) l_m(s) + W1_f(a, b) l'_m(s)
+    for (int it = tid; it < 5 * N3; it += nth) {
+        const int c = it / N3, r = it % N3;
+        const int x0 = r % N, x1 = (r / N) % N, x2 = r / N2;
+        const Real* w = r2 + c * N2;
+        // face d = 0: (a, b, m) = (x1, x2, x0); d = 1: (x0, x2, x1); d = 2: (x0, x1, x2)
+        Real acc = w[0 * 2 * 5 * N2 + x2 * N + x1] * tb.fv[s][x0] + w[(0 * 2 + 1) * 5 * N2 + x2 * N + x1] * tb.fd[s][x0];
+        acc += w[1 * 2 * 5 * N2 + x2 * N + x0] * tb.fv[s][x1] + w[(1 * 2 + 1) * 5 * N2 + x2 * N + x0] * tb.fd[s][x1];
+        acc += w[2 * 2 * 5 * N2 + x1 * N + x0] * tb.fv[s][x2] + w[(2 * 2 + 1) * 5 * N2 + x1 * N + x0] * tb.fd[s][x2];
+        sR[it] += acc;
+    }
+    __syncthreads();
+}
+
 // The three faces xi_d = s (d = 0, 1, 2) of the cell: traces, fluxes, test
 // integration, accumulated into sR.
 template <int N, int Q, typename Real, bool GEN>
@@ -354,52 +409,7 @@ __device__ __forceinline__ void face_group(const OpArgs& a, const KTab<N, Q, Rea
     }
     __syncthreads();
 
-    // transposed along t1: P0 = S^T val + D^T g_t1, P1 = S^T g_t0, Pn = S^T g_n    r1 [f][3][c][b][q0]
-    for (int it = tid; it < 3 * 5 * N * Q; it += nth) {
-        const int q0 = it % Q, ib = (it / Q) % N, c = (it / (Q * N)) % 5, d = it / (5 * Q * N);
-        const Real* o = r2 + d * 4 * 5 * Q2 + c * Q2 + q0;
-        Real p0 = 0, p1 = 0, pn = 0;
-#pragma unroll
-        for (int q1 = 0; q1 < Q; ++q1) {
-            p0 += tb.S[q1][ib] * o[q1 * Q] + tb.D[q1][ib] * o[2 * 5 * Q2 + q1 * Q];
-            p1 += tb.S[q1][ib] * o[1 * 5 * Q2 + q1 * Q];
-            pn += tb.S[q1][ib] * o[3 * 5 * Q2 + q1 * Q];
-        }
-        Real* t = r1 + d * 3 * 5 * N * Q + c * N * Q + ib * Q + q0;
-        t[0] = p0;
-        t[5 * N * Q] = p1;
-        t[2 * 5 * N * Q] = pn;
-    }
-    __syncthreads();
-
-    // transposed along t0: W0 = S^T P0 + D^T P1, W1 = S^T Pn    r2 [f][2][c][b][a]
-    for (int it = tid; it < 3 * 5 * N2; it += nth) {
-        const int ia = it % N, ib = (it / N) % N, c = (it / N2) % 5, d = it / (5 * N2);
-        const Real* t = r1 + d * 3 * 5 * N * Q + c * N * Q + ib * Q;
-        Real w0 = 0, w1 = 0;
-#pragma unroll
-        for (int q0 = 0; q0 < Q; ++q0) {
-            w0 += tb.S[q0][ia] * t[q0] + tb.D[q0][ia] * t[5 * N * Q + q0];
-            w1 += tb.S[q0][ia] * t[2 * 5 * N * Q + q0];
-        }
-        Real* w = r2 + d * 2 * 5 * N2 + c * N2 + ib * N + ia;
-        w[0] = w0;
-        w[5 * N2] = w1;
-    }
-    __syncthreads();
-
-    // R[c](a, b, m) += sum_f W0_f(a, b) l_m(s) + W1_f(a, b) l'_m(s)
-    for (int it = tid; it < 5 * N3; it += nth) {
-        const int c = it / N3, r = it % N3;
-        const int x0 = r % N, x1 = (r / N) % N, x2 = r / N2;
-        const Real* w = r2 + c * N2;
-        // face d = 0: (a, b, m) = (x1, x2, x0); d = 1: (x0, x2, x1); d = 2: (x0, x1, x2)
-        Real acc = w[0 * 2 * 5 * N2 + x2 * N + x1] * tb.fv[s][x0] + w[(0 * 2 + 1) * 5 * N2 + x2 * N + x1] * tb.fd[s][x0];
-        acc += w[1 * 2 * 5 * N2 + x2 * N + x0] * tb.fv[s][x1] + w[(1 * 2 + 1) * 5 * N2 + x2 * N + x0] * tb.fd[s][x1];
-        acc += w[2 * 2 * 5 * N2 + x1 * N + x0] * tb.fv[s][x2] + w[(2 * 2 + 1) * 5 * N2 + x1 * N + x0] * tb.fd[s][x2];
-        sR[it] += acc;
-    }
-    __syncthreads();
+    face_test_accumulate<N, Q, Real>(tb, s, r1, r2, sR);
 }
 
 template <int N, int Q, typename Real, bool GEN>

@@ -1,5 +1,5 @@
-// Operator kernels of polynomial degree 2: the supported n_q values.
-#include "op_impl.h"
+// Operator (and adjoint) kernels of polynomial degree 2: the supported n_q values.
+#include "adj_impl.h"
 #include "dg_kernels.h"
 
 namespace dgns {
@@ -20,6 +20,14 @@ int launch_inverse_mass_k2(const double* R, double* L, int64_t ncell, const doub
                        : launch_minv_t<3, float, false>(R, L, ncell, cm, mj, t, st))
                 : (gen ? launch_minv_t<3, double, true>(R, L, ncell, cm, mj, t, st)
                        : launch_minv_t<3, double, false>(R, L, ncell, cm, mj, t, st));
+}
+
+int launch_adjoint_k2(const OpArgs& a, const double* Rb, const Tables1D& t, bool gen, hipStream_t st) {
+    switch (t.q) {
+        case 3: return gen ? launch_adjoint_t<3, 3, true>(a, Rb, t, st) : launch_adjoint_t<3, 3, false>(a, Rb, t, st);
+        case 4: return gen ? launch_adjoint_t<3, 4, true>(a, Rb, t, st) : launch_adjoint_t<3, 4, false>(a, Rb, t, st);
+        default: return 1;
+    }
 }
 
 }  // namespace dgns

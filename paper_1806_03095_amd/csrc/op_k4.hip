@@ -1,5 +1,5 @@
-// Operator kernels of polynomial degree 4: the supported n_q values.
-#include "op_impl.h"
+// Operator (and adjoint) kernels of polynomial degree 4: the supported n_q values.
+#include "adj_impl.h"
 #include "dg_kernels.h"
 
 namespace dgns {
@@ -22,6 +22,15 @@ int launch_inverse_mass_k4(const double* R, double* L, int64_t ncell, const doub
                        : launch_minv_t<5, float, false>(R, L, ncell, cm, mj, t, st))
                 : (gen ? launch_minv_t<5, double, true>(R, L, ncell, cm, mj, t, st)
                        : launch_minv_t<5, double, false>(R, L, ncell, cm, mj, t, st));
+}
+
+int launch_adjoint_k4(const OpArgs& a, const double* Rb, const Tables1D& t, bool gen, hipStream_t st) {
+    switch (t.q) {
+        case 5: return gen ? launch_adjoint_t<5, 5, true>(a, Rb, t, st) : launch_adjoint_t<5, 5, false>(a, Rb, t, st);
+        case 6: return gen ? launch_adjoint_t<5, 6, true>(a, Rb, t, st) : launch_adjoint_t<5, 6, false>(a, Rb, t, st);
+        case 7: return gen ? launch_adjoint_t<5, 7, true>(a, Rb, t, st) : launch_adjoint_t<5, 7, false>(a, Rb, t, st);
+        default: return 1;
+    }
 }
 
 }  // namespace dgns

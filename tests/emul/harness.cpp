@@ -3,18 +3,26 @@
 // see that file for how a workgroup is emulated.
 //
 // usage: harness <in.bin> <out.bin>
-//   in.bin : dgns_params, dgns_box_mesh, uint32 terms, int32 fuse_minv, then U (n_dof float64)
-//   out.bin: R or L (n_dof float64)
+//   in.bin : dgns_params, dgns_box_mesh, uint32 terms, int32 mode, then U (n_dof float64)
+//            and, for mode 2, Rbar (n_dof float64)
+//   mode   : 0 residual R, 1 operator L = M^{-1} R, 2 residual adjoint Ubar = (dR/dU)^T Rbar
+//   out.bin: R, L or Ubar (n_dof float64)
 #include <cstdio>
 #include <string>
 #include <vector>
 
-#include "op_impl.h"
+#include "adj_impl.h"
 #include "setup.h"
 
 using namespace dgns;
 
 namespace {
+
+template <int N, int Q>
+int run_adj(const OpArgs& a, const double* Rb, const Tables1D& t, int gen) {
+    if constexpr (N <= 6) return gen ? launch_adjoint_t<N, Q, true>(a, Rb, t, nullptr) : launch_adjoint_t<N, Q, false>(a, Rb, t, nullptr);
+    return -4;
+}
 
 template <int N, int Q>
 int run(const OpArgs& a, const Tables1D& t, int fp32, int gen) {
@@ -43,8 +51,12 @@ int main(int argc, char** argv) {
         return 5;
     }
     const int64_t ndof = 5 * hs.ncell * hs.n3;
-    std::vector<double> U(ndof), out(ndof, -12345.0);
+    std::vector<double> U(ndof), out(ndof, -12345.0), Rb;
     if ((int64_t)std::fread(U.data(), 8, ndof, f) != ndof) return 6;
+    if (fuse == 2) {
+        Rb.resize(ndof);
+        if ((int64_t)std::fread(Rb.data(), 8, ndof, f) != ndof) return 6;
+    }
     std::fclose(f);
     OpArgs a;
     std::memset(&a, 0, sizeof a);
@@ -66,11 +78,11 @@ int main(int argc, char** argv) {
     a.lam = prm.lambda;
     a.wall_T = prm.wall_T;
     a.terms = terms;
-    a.fuse_minv = fuse;
+    a.fuse_minv = fuse == 1 ? 1 : 0;
     const int k = prm.degree, q = prm.n_q, fp32 = prm.precision, gen = hs.gen ? 1 : 0;
     rc = -4;
 #define EMU_CASE(K, Q_) \
-    if (k == K && q == Q_) rc = run<K + 1, Q_>(a, hs.tab, fp32, gen);
+    if (k == K && q == Q_) rc = fuse == 2 ? run_adj<K + 1, Q_>(a, Rb.data(), hs.tab, gen) : run<K + 1, Q_>(a, hs.tab, fp32, gen);
     EMU_CASES
     if (rc != 0) {
         std::fprintf(stderr, "no emulated kernel for k=%d nq=%d\n", k, q);
