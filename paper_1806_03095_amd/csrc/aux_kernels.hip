@@ -309,7 +309,7 @@ int launch_axpby(double* y, const double* x, int64_t n, double a, double b, hipS
     return hipGetLastError() == hipSuccess ? 0 : -1;
 }
 
-// Ubar_i = sum_q w|J| phi_i(x_q) (-|u|^2/2, u_1, u_2, u_3, 0): the gradient of
+// Ubar_i = sum_q w|J| phi_i(x_q) (-|u|^2, u_1, u_2, u_3, 0)/rho: the gradient of
 // K = int |u|^2/2 (n_q rule, u = m/rho) with respect to the coefficients U_i.
 __global__ void __launch_bounds__(256) ke_vjp_kernel(OpArgs a, const Tables1D* __restrict__ tp, double* Ub, int gen) {
     extern __shared__ double sg[];   // [4][Q^3]
@@ -326,12 +326,14 @@ __global__ void __launch_bounds__(256) ke_vjp_kernel(OpArgs a, const Tables1D* _
             for (int c = 0; c < 4; ++c) U[c] += phi * a.U[c * cs + e * N3 + i];
         }
         const double jxw = gen ? a.cell_metric[(e * 10 + 9) * Q3 + p] : a.cell_metric[e * 10 + 9] * t.w[p0] * t.w[p1] * t.w[p2];
+        // |u|^2/2 = |m|^2/(2 rho^2):  d/dm = u/rho,  d/drho = -|u|^2/rho
         const double r = 1.0 / U[0];
         const double u0 = U[1] * r, u1 = U[2] * r, u2 = U[3] * r;
-        sg[p] = -0.5 * (u0 * u0 + u1 * u1 + u2 * u2) * jxw;
-        sg[Q3 + p] = u0 * jxw;
-        sg[2 * Q3 + p] = u1 * jxw;
-        sg[3 * Q3 + p] = u2 * jxw;
+        const double wr = jxw * r;
+        sg[p] = -(u0 * u0 + u1 * u1 + u2 * u2) * wr;
+        sg[Q3 + p] = u0 * wr;
+        sg[2 * Q3 + p] = u1 * wr;
+        sg[3 * Q3 + p] = u2 * wr;
     }
     __syncthreads();
     for (int it = threadIdx.x; it < 5 * N3; it += blockDim.x) {

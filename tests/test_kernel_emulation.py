@@ -63,3 +63,44 @@ def test_emulated_fp32_error_scale():
     L = ed.run(U.numpy(), 3, 6, (2, 2, 2), *PI3, precision=1, mu=fl.mu, lam=fl.lam, terms=7, fuse=1)
     errs = rel_err_fields(L, oop.apply(U))
     assert 1e-8 < max(errs) < 1e-4, errs     # float32 rounding, not float64
+
+
+def _oracle_vjp(oop, U, Rb, terms):
+    import torch
+    V = U.clone().requires_grad_(True)
+    (g,) = torch.autograd.grad(oop.residual(V, terms=terms), V, grad_outputs=Rb)
+    return g
+
+
+@pytest.mark.parametrize("n,k,nq,kind,amp,basis", [
+    ((3, 2, 2), 1, 2, 0, 0.0, "LGL"),
+    ((2, 2, 2), 2, 3, 2, 0.15, "GL"),
+    ((2, 1, 2), 3, 6, 0, 0.0, "LGL"),
+])
+def test_emulated_adjoint_per_term(n, k, nq, kind, amp, basis):
+    import torch
+    fl, oop, U = _tgv_case(n, k, nq, kind, amp, basis)
+    b = 0 if basis == "LGL" else 1
+    Rb = torch.as_tensor(np.random.default_rng(41).standard_normal(tuple(U.shape)))
+    for mask, t in ((1, "c"), (2, "v"), (3, "cv")):
+        Ub = ed.run(U.numpy(), k, nq, n, *PI3, kind=kind, amp=amp, basis=b, mu=fl.mu, lam=fl.lam, terms=mask,
+                    fuse=2, Rbar=Rb.numpy())
+        errs = rel_err_fields(Ub, _oracle_vjp(oop, U, Rb, t))
+        assert max(errs) < 1e-12, (t, errs)
+
+
+def test_emulated_adjoint_channel_walls_and_force():
+    import torch
+    fl = tgv_fluid(mu=1.0 / 180.0)
+    T0 = (18.3 / 0.1) ** 2 / (1.4 * 287.0)
+    lo, hi = (0, -1, 0), (2 * math.pi, 1, math.pi)
+    om = omesh.BoxMesh((2, 4, 1), lo, hi, 4, periodic=(True, False, True), kind=omesh.CHANNEL)
+    oop = ooperator.DGOperator(om, fl, 7, body_force=(1.0, 0.0, 0.0), wall_T=T0)
+    U = channel_input(oop)
+    Rb = torch.as_tensor(np.random.default_rng(43).standard_normal(tuple(U.shape)))
+    for mask, t in ((1, "c"), (2, "v"), (4, "f"), (7, "cvf")):
+        Ub = ed.run(U.numpy(), 4, 7, (2, 4, 1), lo, hi, periodic=(1, 0, 1), kind=1, mu=fl.mu, lam=fl.lam,
+                    force=(1.0, 0, 0), wall_T=T0, terms=mask, fuse=2, Rbar=Rb.numpy())
+        want = _oracle_vjp(oop, U, Rb, t)
+        errs = rel_err_fields(Ub[:2], want[:2]) if t == "f" else rel_err_fields(Ub, want)
+        assert max(errs) < 1e-12, (t, errs)
