@@ -73,6 +73,11 @@ template <int N, int Q>
 struct OpSizes {
     static constexpr int P = ChooseP<N, Q>::v;
     static constexpr int WORK = CMax<CMax<CellSizes<N, Q, P>::TOTAL, FaceSizes<N, Q>::TOTAL>::v, 10 * N * N * N>::v;
+    // whether the LDS copies of the 1D tables fit beside the work arrays
+    template <typename Real>
+    static constexpr bool lds_tables() {
+        return (WORK + 10 * N * N * N + 2 * Q * N + Q + 4 * N + 2 * N * N + N) * (int)sizeof(Real) + 1024 <= 160 * 1024;
+    }
 };
 
 // Applies an N x N matrix M along axis `ax` of the five arrays src[5][N^3] ->
@@ -104,8 +109,8 @@ __device__ __forceinline__ void sweep_nn(const Real (&M)[N][N], const Real* src,
 
 // In-LDS inverse mass: sR <- (Smi)^{x3} diag(1/(|J| w)) (Smi^T)^{x3} sR, work >= 5 N^3.
 template <int N, typename Real, bool GEN>
-__device__ __forceinline__ void inverse_mass_lds(const MTab<N, Real>& mt, Real* sR, Real* work, Real detJ,
-                                                 const double* jxw_m) {
+__device__ __forceinline__ void inverse_mass_lds(const MTab<N, Real>& mt, const Real* wm, Real* sR, Real* work,
+                                                 Real detJ, const double* jxw_m) {
     constexpr int N2 = N * N, N3 = N2 * N;
     sweep_nn<N, Real, true>(mt.Smi, sR, work, 0);
     __syncthreads();
@@ -120,7 +125,7 @@ __device__ __forceinline__ void inverse_mass_lds(const MTab<N, Real>& mt, Real* 
             jxw = (Real)jxw_m[p];
         } else {
             const int p0 = p % N, p1 = (p / N) % N, p2 = p / N2;
-            jxw = detJ * mt.wm[p0] * mt.wm[p1] * mt.wm[p2];
+            jxw = detJ * wm[p0] * wm[p1] * wm[p2];
         }
         work[it] = work[it] / jxw;
     }
@@ -134,6 +139,15 @@ __device__ __forceinline__ void inverse_mass_lds(const MTab<N, Real>& mt, Real* 
 }
 
 __device__ __forceinline__ int axis_stride(int ax, int N) { return ax == 0 ? 1 : (ax == 1 ? N : N * N); }
+
+// Workgroup copy of a table struct of Real values (kernel argument -> LDS).
+template <typename T, typename Real>
+__device__ __forceinline__ void copy_table(const T& src, T& dst) {
+    constexpr int n = (int)(sizeof(T) / sizeof(Real));
+    const Real* s = reinterpret_cast<const Real*>(&src);
+    Real* d = reinterpret_cast<Real*>(&dst);
+    for (int i = threadIdx.x; i < n; i += blockDim.x) d[i] = s[i];
+}
 
 // Neighbour, face id and penalty of the six faces, computed once per workgroup.
 struct FaceInfo {
@@ -228,7 +242,7 @@ __device__ __forceinline__ void face_test_accumulate(const KTab<N, Q, Real>& tb,
 // The three faces xi_d = s (d = 0, 1, 2) of the cell: traces, fluxes, test
 // integration, accumulated into sR.
 template <int N, int Q, typename Real, bool GEN>
-__device__ __forceinline__ void face_group(const OpArgs& a, const KTab<N, Q, Real>& tb, const Phys<Real>& ph, bool conv,
+__device__ __forceinline__ void face_group(const OpArgs& a, const KTab<N, Q, Real>& lt, const Phys<Real>& ph, bool conv,
                                            bool visc, int s, int64_t e, const FaceInfo& fi, const Real* sTau,
                                            const Real* sFn, const Real (&Ji)[9], Real detJ, const Real* sU, Real* sR,
                                            Real* sW) {
@@ -248,16 +262,16 @@ __device__ __forceinline__ void face_group(const OpArgs& a, const KTab<N, Q, Rea
 #pragma unroll
         for (int m = 0; m < N; ++m) {
             const Real x = sU[c * N3 + base + m * sd];
-            tv += tb.fv[s][m] * x;
-            tn += tb.fd[s][m] * x;
+            tv += lt.fv[s][m] * x;
+            tn += lt.fd[s][m] * x;
         }
         if (!fi.wall[d + 3 * s]) {
             const double* un_line = a.U + c * cstride + fi.enb[d + 3 * s] * N3 + base;
 #pragma unroll
             for (int m = 0; m < N; ++m) {
                 const Real x = (Real)un_line[m * sd];
-                uv += tb.fv[1 - s][m] * x;
-                un += tb.fd[1 - s][m] * x;
+                uv += lt.fv[1 - s][m] * x;
+                un += lt.fd[1 - s][m] * x;
             }
         }
         Real* tr = r2 + d * (2 * 2 * 5 * N2) + c * N2 + ab;
@@ -285,9 +299,9 @@ __device__ __forceinline__ void face_group(const OpArgs& a, const KTab<N, Q, Rea
             Real a0 = 0, a1 = 0, an = 0;
 #pragma unroll
             for (int ia = 0; ia < N; ++ia) {
-                a0 += tb.S[q0][ia] * tv[ia];
-                a1 += tb.D[q0][ia] * tv[ia];
-                an += tb.S[q0][ia] * tn[ia];
+                a0 += lt.S[q0][ia] * tv[ia];
+                a1 += lt.D[q0][ia] * tv[ia];
+                an += lt.S[q0][ia] * tn[ia];
             }
             o[q0] = a0;
             o[5 * N * Q + q0] = a1;
@@ -321,7 +335,7 @@ __device__ __forceinline__ void face_group(const OpArgs& a, const KTab<N, Q, Rea
             nrm[0] = sgn * fn[0];
             nrm[1] = sgn * fn[1];
             nrm[2] = sgn * fn[2];
-            dAw = detJ * fn[3] * tb.w[q0] * tb.w[q1];
+            dAw = detJ * fn[3] * lt.w[q0] * lt.w[q1];
         }
         // one side at a time, to keep a single gradient live: the side's value,
         // physical gradient, F_c.n and F_v.n go straight into the point's coefficient
@@ -330,7 +344,7 @@ __device__ __forceinline__ void face_group(const OpArgs& a, const KTab<N, Q, Rea
         Prim<Real> sm;
         {
             Real G[5][3], Fn[5];
-            load_face_point<N, Q, Real>(tb, r1 + (d * 2 + 0) * 3 * 5 * N * Q, d, q0, q1, Jm, Um, G);
+            load_face_point<N, Q, Real>(lt, r1 + (d * 2 + 0) * 3 * 5 * N * Q, d, q0, q1, Jm, Um, G);
             sm = primitives(Um, ph);
 #pragma unroll
             for (int c = 0; c < 5; ++c) val[c] = 0;
@@ -357,7 +371,7 @@ __device__ __forceinline__ void face_group(const OpArgs& a, const KTab<N, Q, Rea
 #pragma unroll
                     for (int m = 0; m < 9; ++m) Jp[m] = (Real)cm[m];
                 }
-                load_face_point<N, Q, Real>(tb, r1 + (d * 2 + 1) * 3 * 5 * N * Q, d, q0, q1, Jp, Up, G);
+                load_face_point<N, Q, Real>(lt, r1 + (d * 2 + 1) * 3 * 5 * N * Q, d, q0, q1, Jp, Up, G);
             }
             const Prim<Real> sp = primitives(Up, ph);
             if (conv) {
@@ -409,11 +423,11 @@ __device__ __forceinline__ void face_group(const OpArgs& a, const KTab<N, Q, Rea
     }
     __syncthreads();
 
-    face_test_accumulate<N, Q, Real>(tb, s, r1, r2, sR);
+    face_test_accumulate<N, Q, Real>(lt, s, r1, r2, sR);
 }
 
 template <int N, int Q, typename Real, bool GEN>
-__global__ void __launch_bounds__(kBlock)
+__global__ void __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(2)))
 dg_operator_kernel(OpArgs a, KTab<N, Q, Real> tb, MTab<N, Real> mt) {
     using Sz = OpSizes<N, Q>;
     constexpr int P = Sz::P;
@@ -425,6 +439,7 @@ dg_operator_kernel(OpArgs a, KTab<N, Q, Real> tb, MTab<N, Real> mt) {
     __shared__ FaceInfo fi;
     __shared__ Real sTau[6];
     __shared__ Real sFn[12];   // affine: per direction the unit normal and |row of J^{-1}|
+    __shared__ Real lwm[N];
 
     const int64_t e = blockIdx.x;
     const int tid = threadIdx.x, nth = blockDim.x;
@@ -438,6 +453,26 @@ dg_operator_kernel(OpArgs a, KTab<N, Q, Real> tb, MTab<N, Real> mt) {
         sU[i] = (Real)a.U[c * cstride + e * N3 + j];
         sR[i] = Real(0);
     }
+    // LDS copy of the 1D tables when it fits beside the work arrays (otherwise the
+    // kernel argument is read directly).  Reading every table entry from LDS keeps
+    // the tables out of the scalar registers: held there for the whole kernel they
+    // exceed the scalar register file and spill through vector lanes.
+    const KTab<N, Q, Real>* ltp;
+    const MTab<N, Real>* lmp;
+    if constexpr (Sz::template lds_tables<Real>()) {
+        __shared__ KTab<N, Q, Real> lt_lds;
+        copy_table<KTab<N, Q, Real>, Real>(tb, lt_lds);
+        ltp = &lt_lds;
+        __shared__ MTab<N, Real> lm_lds;
+        copy_table<MTab<N, Real>, Real>(mt, lm_lds);
+        lmp = &lm_lds;
+    } else {
+        ltp = &tb;
+        lmp = &mt;
+    }
+    const MTab<N, Real>& lm = *lmp;
+    const KTab<N, Q, Real>& lt = *ltp;
+    for (int i = tid; i < N; i += nth) lwm[i] = mt.wm[i];
     for (int f = tid; f < 6; f += nth) {
         const int i0 = (int)(e % a.n[0]), i1 = (int)((e / a.n[0]) % a.n[1]), i2 = (int)(e / ((int64_t)a.n[0] * a.n[1]));
         const int d = f % 3, s = f / 3;
@@ -494,8 +529,8 @@ dg_operator_kernel(OpArgs a, KTab<N, Q, Real> tb, MTab<N, Real> mt) {
                 Real z0 = 0, z1 = 0;
 #pragma unroll
                 for (int i = 0; i < N; ++i) {
-                    z0 += tb.S[pz][i] * v[i];
-                    z1 += tb.D[pz][i] * v[i];
+                    z0 += lt.S[pz][i] * v[i];
+                    z1 += lt.D[pz][i] * v[i];
                 }
                 sZ[(0 * 5 + c) * Q * N2 + pz * N2 + r] = z0;
                 sZ[(1 * 5 + c) * Q * N2 + pz * N2 + r] = z1;
@@ -520,9 +555,9 @@ dg_operator_kernel(OpArgs a, KTab<N, Q, Real> tb, MTab<N, Real> mt) {
                     Real y00 = 0, y10 = 0, y01 = 0;
 #pragma unroll
                     for (int i = 0; i < N; ++i) {
-                        y00 += tb.S[py][i] * z0[i];
-                        y10 += tb.D[py][i] * z0[i];
-                        y01 += tb.S[py][i] * z1[i];
+                        y00 += lt.S[py][i] * z0[i];
+                        y10 += lt.D[py][i] * z0[i];
+                        y01 += lt.S[py][i] * z1[i];
                     }
                     sY[((0 * 5 + c) * P + pl) * Q * N + py * N + a0] = y00;
                     sY[((1 * 5 + c) * P + pl) * Q * N + py * N + a0] = y10;
@@ -545,10 +580,10 @@ dg_operator_kernel(OpArgs a, KTab<N, Q, Real> tb, MTab<N, Real> mt) {
                         const Real y00 = sY[((0 * 5 + c) * P + pl) * Q * N + py * N + i];
                         const Real y10 = sY[((1 * 5 + c) * P + pl) * Q * N + py * N + i];
                         const Real y01 = sY[((2 * 5 + c) * P + pl) * Q * N + py * N + i];
-                        v += tb.S[px][i] * y00;
-                        dx += tb.D[px][i] * y00;
-                        dy += tb.S[px][i] * y10;
-                        dz += tb.S[px][i] * y01;
+                        v += lt.S[px][i] * y00;
+                        dx += lt.D[px][i] * y00;
+                        dy += lt.S[px][i] * y10;
+                        dz += lt.S[px][i] * y01;
                     }
                     Uq[c] = v;
                     Gr[c][0] = dx;
@@ -565,7 +600,7 @@ dg_operator_kernel(OpArgs a, KTab<N, Q, Real> tb, MTab<N, Real> mt) {
                 } else {
 #pragma unroll
                     for (int m = 0; m < 9; ++m) J[m] = Ji[m];
-                    jxw = detJ * tb.w[px] * tb.w[py] * tb.w[pz];
+                    jxw = detJ * lt.w[px] * lt.w[py] * lt.w[pz];
                 }
                 const Prim<Real> sq = primitives(Uq, ph);
                 Real F[5][3];
@@ -606,9 +641,9 @@ dg_operator_kernel(OpArgs a, KTab<N, Q, Real> tb, MTab<N, Real> mt) {
                 Real b1 = 0, b2 = 0, b3 = 0;
 #pragma unroll
                 for (int px = 0; px < Q; ++px) {
-                    b1 += tb.D[px][a0] * sF[((c * 3 + 0) * P + pl) * Q2 + py * Q + px];
-                    b2 += tb.S[px][a0] * sF[((c * 3 + 1) * P + pl) * Q2 + py * Q + px];
-                    b3 += tb.S[px][a0] * sF[((c * 3 + 2) * P + pl) * Q2 + py * Q + px];
+                    b1 += lt.D[px][a0] * sF[((c * 3 + 0) * P + pl) * Q2 + py * Q + px];
+                    b2 += lt.S[px][a0] * sF[((c * 3 + 1) * P + pl) * Q2 + py * Q + px];
+                    b3 += lt.S[px][a0] * sF[((c * 3 + 2) * P + pl) * Q2 + py * Q + px];
                 }
                 sB[((0 * 5 + c) * P + pl) * Q * N + py * N + a0] = b1;
                 sB[((1 * 5 + c) * P + pl) * Q * N + py * N + a0] = b2;
@@ -624,9 +659,9 @@ dg_operator_kernel(OpArgs a, KTab<N, Q, Real> tb, MTab<N, Real> mt) {
                 Real e1 = 0, e2 = 0;
 #pragma unroll
                 for (int py = 0; py < Q; ++py) {
-                    e1 += tb.S[py][a1] * sB[((0 * 5 + c) * P + pl) * Q * N + py * N + a0] +
-                          tb.D[py][a1] * sB[((1 * 5 + c) * P + pl) * Q * N + py * N + a0];
-                    e2 += tb.S[py][a1] * sB[((2 * 5 + c) * P + pl) * Q * N + py * N + a0];
+                    e1 += lt.S[py][a1] * sB[((0 * 5 + c) * P + pl) * Q * N + py * N + a0] +
+                          lt.D[py][a1] * sB[((1 * 5 + c) * P + pl) * Q * N + py * N + a0];
+                    e2 += lt.S[py][a1] * sB[((2 * 5 + c) * P + pl) * Q * N + py * N + a0];
                 }
                 sE[((0 * 5 + c) * P + pl) * N2 + a1 * N + a0] = e1;
                 sE[((1 * 5 + c) * P + pl) * N2 + a1 * N + a0] = e2;
@@ -641,8 +676,8 @@ dg_operator_kernel(OpArgs a, KTab<N, Q, Real> tb, MTab<N, Real> mt) {
                 for (int pl = 0; pl < P; ++pl) {
                     const int pz = pz0 + pl;
                     if (pz < Q)
-                        acc += tb.S[pz][a2] * sE[((0 * 5 + c) * P + pl) * N2 + r2] +
-                               tb.D[pz][a2] * sE[((1 * 5 + c) * P + pl) * N2 + r2];
+                        acc += lt.S[pz][a2] * sE[((0 * 5 + c) * P + pl) * N2 + r2] +
+                               lt.D[pz][a2] * sE[((1 * 5 + c) * P + pl) * N2 + r2];
                 }
                 sR[it] += acc;
             }
@@ -650,8 +685,8 @@ dg_operator_kernel(OpArgs a, KTab<N, Q, Real> tb, MTab<N, Real> mt) {
         }
 
         // ------------------------------------------------------------ face terms
-        face_group<N, Q, Real, GEN>(a, tb, ph, conv, visc, 0, e, fi, sTau, sFn, Ji, detJ, sU, sR, sW);
-        face_group<N, Q, Real, GEN>(a, tb, ph, conv, visc, 1, e, fi, sTau, sFn, Ji, detJ, sU, sR, sW);
+        face_group<N, Q, Real, GEN>(a, lt, ph, conv, visc, 0, e, fi, sTau, sFn, Ji, detJ, sU, sR, sW);
+        face_group<N, Q, Real, GEN>(a, lt, ph, conv, visc, 1, e, fi, sTau, sFn, Ji, detJ, sU, sR, sW);
     }
 
     // ------------------------------------------------------------ body force (k+1 rule)
@@ -661,16 +696,16 @@ dg_operator_kernel(OpArgs a, KTab<N, Q, Real> tb, MTab<N, Real> mt) {
         Real* t0b = sW;
         Real* t1b = sW + 5 * N3;
         // values at the mass points: (Sm)^{x3} U
-        sweep_nn<N, Real, false>(mt.Sm, sU, t0b, 0);
+        sweep_nn<N, Real, false>(lm.Sm, sU, t0b, 0);
         __syncthreads();
-        sweep_nn<N, Real, false>(mt.Sm, t0b, t1b, 1);
+        sweep_nn<N, Real, false>(lm.Sm, t0b, t1b, 1);
         __syncthreads();
-        sweep_nn<N, Real, false>(mt.Sm, t1b, t0b, 2);
+        sweep_nn<N, Real, false>(lm.Sm, t1b, t0b, 2);
         __syncthreads();
         for (int p = tid; p < N3; p += nth) {
             Real jxw;
             if constexpr (GEN) jxw = (Real)jxw_m[p];
-            else jxw = detJ * mt.wm[p % N] * mt.wm[(p / N) % N] * mt.wm[p / N2];
+            else jxw = detJ * lwm[p % N] * lwm[(p / N) % N] * lwm[p / N2];
             const Real rho = t0b[p];
             const Real f0 = (Real)a.force[0], f1 = (Real)a.force[1], f2 = (Real)a.force[2];
             const Real fu = (f0 * t0b[N3 + p] + f1 * t0b[2 * N3 + p] + f2 * t0b[3 * N3 + p]) / rho;
@@ -681,17 +716,17 @@ dg_operator_kernel(OpArgs a, KTab<N, Q, Real> tb, MTab<N, Real> mt) {
             t0b[4 * N3 + p] = fu * jxw;
         }
         __syncthreads();
-        sweep_nn<N, Real, true>(mt.Sm, t0b, t1b, 0);
+        sweep_nn<N, Real, true>(lm.Sm, t0b, t1b, 0);
         __syncthreads();
-        sweep_nn<N, Real, true>(mt.Sm, t1b, t0b, 1);
+        sweep_nn<N, Real, true>(lm.Sm, t1b, t0b, 1);
         __syncthreads();
-        sweep_nn<N, Real, true>(mt.Sm, t0b, t1b, 2);
+        sweep_nn<N, Real, true>(lm.Sm, t0b, t1b, 2);
         __syncthreads();
         for (int i = tid; i < 5 * N3; i += nth) sR[i] += t1b[i];
         __syncthreads();
     }
 
-    if (a.fuse_minv) inverse_mass_lds<N, Real, GEN>(mt, sR, sW, detJ, jxw_m);
+    if (a.fuse_minv) inverse_mass_lds<N, Real, GEN>(lm, lwm, sR, sW, detJ, jxw_m);
 
     for (int i = tid; i < 5 * N3; i += nth) {
         const int c = i / N3, j = i % N3;
@@ -708,13 +743,15 @@ inverse_mass_kernel(const double* R, double* L, int64_t ncell, const double* cel
     constexpr int N3 = N * N * N;
     __shared__ Real sR[5 * N3];
     __shared__ Real sW[5 * N3];
+    __shared__ Real lwm[N];
     const int64_t e = blockIdx.x;
     const int64_t cs = ncell * N3;
     for (int i = threadIdx.x; i < 5 * N3; i += blockDim.x) sR[i] = (Real)R[(i / N3) * cs + e * N3 + i % N3];
+    for (int i = threadIdx.x; i < N; i += blockDim.x) lwm[i] = mt.wm[i];
     Real detJ = 1;
     if constexpr (!GEN) detJ = (Real)cell_metric[e * 10 + 9];
     __syncthreads();
-    inverse_mass_lds<N, Real, GEN>(mt, sR, sW, detJ, GEN ? mass_jxw + e * N3 : nullptr);
+    inverse_mass_lds<N, Real, GEN>(mt, lwm, sR, sW, detJ, GEN ? mass_jxw + e * N3 : nullptr);
     for (int i = threadIdx.x; i < 5 * N3; i += blockDim.x) L[(i / N3) * cs + e * N3 + i % N3] = (double)sR[i];
 }
 
