@@ -37,18 +37,26 @@ namespace dgns {
 template <int A, int B>
 struct CMax { static constexpr int v = A > B ? A : B; };
 
-template <int N, int Q>
+template <int N, int Q, int B>
 struct FaceSizes {
     static constexpr int N2 = N * N, Q2 = Q * Q;
-    // group of three faces; region 1 and region 2 alternate between phases
+    // group of three faces
     static constexpr int TR = 3 * 2 * 2 * 5 * N2;      // traces [f][side][v/n][c][N^2]
     static constexpr int SW = 3 * 2 * 3 * 5 * N * Q;   // t0 sweep [f][side][3][c][N][Q]
     static constexpr int OUT = 3 * 4 * 5 * Q2;         // point outputs [f][4][c][Q^2]
     static constexpr int T1 = 3 * 3 * 5 * N * Q;       // t1-transposed [f][3][c][N][Q]
     static constexpr int W = 3 * 2 * 5 * N2;           // lifted [f][2][c][N^2]
+    // Two regions that alternate between phases: R1 = {SW, T1}, R2 = {TR, OUT, W}.
     static constexpr int R1 = CMax<SW, T1>::v;
     static constexpr int R2 = CMax<CMax<TR, OUT>::v, W>::v;
-    static constexpr int TOTAL = R1 + R2;
+    static constexpr int SPLIT_TOTAL = R1 + R2;
+    // With one face point per thread, OUT can overwrite SW (the point results wait
+    // in registers across a barrier): SW | TR, then OUT | T1, then W | T1.
+    static constexpr bool ALIAS = 3 * Q2 <= B;
+    static constexpr int TR_OFF = ALIAS ? SW : R1;
+    static constexpr int OUT_OFF = ALIAS ? 0 : R1;
+    static constexpr int T1_OFF = ALIAS ? OUT : 0;
+    static constexpr int TOTAL = ALIAS ? CMax<CMax<SW + TR, OUT + T1>::v, W>::v : SPLIT_TOTAL;
 };
 
 template <int N, int Q, int P>
@@ -60,24 +68,36 @@ struct CellSizes {
     static constexpr int TOTAL = Z + Y + F;
 };
 
-// Planes per chunk: as many as fit in the face-phase work area (at least one).
+// Planes per chunk: as many as fit in the split face-phase layout (at least one).
 template <int N, int Q>
 struct ChooseP {
     static constexpr int fit(int p) {
-        return p <= 1 ? 1 : (CellSizes<N, Q, 1>::TOTAL + (p - 1) * (15 * Q * N + 15 * Q * Q) <= FaceSizes<N, Q>::TOTAL ? p : fit(p - 1));
+        return p <= 1 ? 1 : (CellSizes<N, Q, 1>::TOTAL + (p - 1) * (15 * Q * N + 15 * Q * Q) <= FaceSizes<N, Q, 1>::SPLIT_TOTAL ? p : fit(p - 1));
     }
     static constexpr int v = fit(Q);
 };
 
-template <int N, int Q>
+template <int N, int Q, int B>
 struct OpSizes {
     static constexpr int P = ChooseP<N, Q>::v;
-    static constexpr int WORK = CMax<CMax<CellSizes<N, Q, P>::TOTAL, FaceSizes<N, Q>::TOTAL>::v, 10 * N * N * N>::v;
+    static constexpr int WORK = CMax<CMax<CellSizes<N, Q, P>::TOTAL, FaceSizes<N, Q, B>::TOTAL>::v, 10 * N * N * N>::v;
     // whether the LDS copies of the 1D tables fit beside the work arrays
     template <typename Real>
     static constexpr bool lds_tables() {
         return (WORK + 10 * N * N * N + 2 * Q * N + Q + 4 * N + 2 * N * N + N) * (int)sizeof(Real) + 1024 <= 160 * 1024;
     }
+};
+
+// Workgroup size of the operator kernel: 128 threads (two waves) per cell while
+// four workgroups fit in a compute unit's LDS, so that every SIMD holds two waves;
+// 256 threads for the larger (N, n_q) whose LDS footprint allows fewer workgroups
+// (unless the 1D tables do not fit in LDS: that kernel spills, and more waves of
+// it only add spill traffic).
+template <int N, int Q, typename Real>
+struct OpBlock {
+    static constexpr int lds128 =
+        (OpSizes<N, Q, 128>::WORK + 10 * N * N * N + 2 * Q * N + Q + 4 * N + 2 * N * N + N) * (int)sizeof(Real) + 1024;
+    static constexpr int threads = (lds128 <= 40 * 1024 || lds128 > 160 * 1024) ? 128 : 256;
 };
 
 // Applies an N x N matrix M along axis `ax` of the five arrays src[5][N^3] ->
@@ -184,6 +204,31 @@ __device__ __forceinline__ void load_face_point(const KTab<N, Q, Real>& tb, cons
     }
 }
 
+// As load_face_point, with the metric rows already permuted to the face's axes:
+// Jr = rows (t0, t1, d) of J^{-1}, so the physical gradient needs no per-lane
+// selection of reference components.
+template <int N, int Q, typename Real>
+__device__ __forceinline__ void load_face_point_rows(const KTab<N, Q, Real>& tb, const Real* A, int q0, int q1,
+                                                     const Real (&Jr)[9], Real U[5], Real G[5][3]) {
+#pragma unroll
+    for (int c = 0; c < 5; ++c) {
+        Real v = 0, g0 = 0, g1 = 0, gn = 0;
+#pragma unroll
+        for (int ib = 0; ib < N; ++ib) {
+            const Real a0 = A[(0 * 5 + c) * N * Q + ib * Q + q0];
+            const Real a1 = A[(1 * 5 + c) * N * Q + ib * Q + q0];
+            const Real an = A[(2 * 5 + c) * N * Q + ib * Q + q0];
+            v += tb.S[q1][ib] * a0;
+            g0 += tb.S[q1][ib] * a1;
+            g1 += tb.D[q1][ib] * a0;
+            gn += tb.S[q1][ib] * an;
+        }
+#pragma unroll
+        for (int j = 0; j < 3; ++j) G[c][j] = Jr[j] * g0 + Jr[3 + j] * g1 + Jr[6 + j] * gn;
+        U[c] = v;
+    }
+}
+
 // Test integration of the face-point coefficients r2 [f][val, g_t0, g_t1, g_n][c][q1][q0]
 // of the three faces xi_d = s against the cell's basis functions, accumulated
 // into sR: value part through phi_i, gradient part through grad_xi phi_i.
@@ -239,17 +284,141 @@ __device__ __forceinline__ void face_test_accumulate(const KTab<N, Q, Real>& tb,
     __syncthreads();
 }
 
+// One face point it = d * n_q^2 + q0 + n_q q1 of the group of faces xi_d = s: the
+// t1 contraction of both sides' t0-swept traces A (layout [f][side][3][c][N][Q]),
+// the numerical fluxes, and the reference-space test coefficients
+//   res[kind * 5 + c], kind = value, g_t0, g_t1, g_n.
+template <int N, int Q, typename Real, bool GEN, bool WALLS>
+__device__ __forceinline__ void face_point(const OpArgs& a, const KTab<N, Q, Real>& lt, const Phys<Real>& ph, bool conv,
+                                           bool visc, int s, const FaceInfo& fi, const Real* sTau, const Real* sFn,
+                                           const Real* sJr, Real detJ, const Real* r1, int it, Real (&res)[20]) {
+    constexpr int Q2 = Q * Q;
+    const int d = it / Q2, pt = it % Q2, q0 = pt % Q, q1 = pt / Q;
+    const int fslot = d + 3 * s;
+    const bool wall = WALLS && fi.wall[fslot] != 0;
+    // reference axes of the face: tangential t0 < t1, normal d; rows[r] is the
+    // row of J^{-1} that multiplies the derivative along the face's axis r
+    const int rows[3] = {d == 0 ? 1 : 0, d == 2 ? 1 : 2, d};
+    Real Jm[9], nrm[3], dAw;
+    const double* fdp = nullptr;
+    if constexpr (GEN) {
+        fdp = a.face_data[d] + fi.fid[fslot] * 22 * Q2 + pt;
+        const Real sgn = s ? Real(1) : Real(-1);
+#pragma unroll
+        for (int j = 0; j < 3; ++j) nrm[j] = sgn * (Real)fdp[j * Q2];
+        dAw = (Real)fdp[3 * Q2];
+        const int own = s ? 4 : 13;
+#pragma unroll
+        for (int r = 0; r < 3; ++r)
+#pragma unroll
+            for (int j = 0; j < 3; ++j) Jm[3 * r + j] = (Real)fdp[(own + 3 * rows[r] + j) * Q2];
+    } else {
+#pragma unroll
+        for (int m = 0; m < 9; ++m) Jm[m] = sJr[9 * d + m];
+        const Real sgn = s ? Real(1) : Real(-1);
+        const Real* fn = sFn + 4 * d;     // unit normal of face xi_d = 1 and |row d of J^{-1}|
+        nrm[0] = sgn * fn[0];
+        nrm[1] = sgn * fn[1];
+        nrm[2] = sgn * fn[2];
+        dAw = detJ * fn[3] * lt.w[q0] * lt.w[q1];
+    }
+    // one side at a time, to keep a single gradient live: the side's value,
+    // physical gradient, F_c.n and F_v.n go straight into the point's coefficient
+    //   val = -1/2 (F_c^- + F_c^+).n + 1/2 (F_v^- + F_v^+).n - (Lambda/2 + tau)(U^- - U^+)
+    Real Um[5], Up[5], val[5], lam_m = 0, lam_p = 0;
+    Prim<Real> sm;
+    {
+        Real G[5][3], Fn[5];
+        load_face_point_rows<N, Q, Real>(lt, r1 + (d * 2 + 0) * 3 * 5 * N * Q, q0, q1, Jm, Um, G);
+        sm = primitives(Um, ph);
+#pragma unroll
+        for (int c = 0; c < 5; ++c) val[c] = 0;
+        if (conv) {
+            lam_m = convective_normal(Um, sm, nrm, ph, Fn);
+#pragma unroll
+            for (int c = 0; c < 5; ++c) val[c] -= Real(0.5) * Fn[c];
+        }
+        if (visc) {
+            viscous_flux_normal(sm, G, nrm, ph, Fn);
+#pragma unroll
+            for (int c = 0; c < 5; ++c) val[c] += Real(0.5) * Fn[c];
+        }
+        if (wall) {
+            wall_mirror(Um, sm, ph, Up);   // the exterior gradient is the interior one: G is kept
+        } else {
+            Real Jp[9];
+            if constexpr (GEN) {
+                const int oth = s ? 13 : 4;
+#pragma unroll
+                for (int r = 0; r < 3; ++r)
+#pragma unroll
+                    for (int j = 0; j < 3; ++j) Jp[3 * r + j] = (Real)fdp[(oth + 3 * rows[r] + j) * Q2];
+            } else {
+                const double* cm = a.cell_metric + fi.enb[fslot] * 10;
+#pragma unroll
+                for (int r = 0; r < 3; ++r)
+#pragma unroll
+                    for (int j = 0; j < 3; ++j) Jp[3 * r + j] = (Real)cm[3 * rows[r] + j];
+            }
+            load_face_point_rows<N, Q, Real>(lt, r1 + (d * 2 + 1) * 3 * 5 * N * Q, q0, q1, Jp, Up, G);
+        }
+        const Prim<Real> sp = primitives(Up, ph);
+        if (conv) {
+            lam_p = convective_normal(Up, sp, nrm, ph, Fn);
+#pragma unroll
+            for (int c = 0; c < 5; ++c) val[c] -= Real(0.5) * Fn[c];
+        }
+        if (visc) {
+            viscous_flux_normal(sp, G, nrm, ph, Fn);
+#pragma unroll
+            for (int c = 0; c < 5; ++c) val[c] += Real(0.5) * Fn[c];
+        }
+    }
+    Real jump[5];
+#pragma unroll
+    for (int c = 0; c < 5; ++c) jump[c] = Um[c] - Up[c];
+    {
+        const Real lam = lam_m > lam_p ? lam_m : lam_p;
+        const Real pen = (conv ? Real(0.5) * lam : Real(0)) + (visc ? sTau[fslot] : Real(0));
+#pragma unroll
+        for (int c = 0; c < 5; ++c) val[c] -= pen * jump[c];
+    }
+    Real gphys[5][3];
+    if (visc) {
+        viscous_flux_rank1(sm, jump, nrm, ph, gphys);
+    } else {
+#pragma unroll
+        for (int c = 0; c < 5; ++c)
+#pragma unroll
+            for (int j = 0; j < 3; ++j) gphys[c][j] = 0;
+    }
+    const Real half_dAw = Real(0.5) * dAw;
+#pragma unroll
+    for (int c = 0; c < 5; ++c) {
+        // reference-space coefficients along the face axes (t0, t1, n): the rows of Jm
+        res[c] = val[c] * dAw;
+#pragma unroll
+        for (int r = 0; r < 3; ++r)
+            res[(1 + r) * 5 + c] =
+                (Jm[r * 3] * gphys[c][0] + Jm[r * 3 + 1] * gphys[c][1] + Jm[r * 3 + 2] * gphys[c][2]) * half_dAw;
+    }
+}
+
 // The three faces xi_d = s (d = 0, 1, 2) of the cell: traces, fluxes, test
 // integration, accumulated into sR.
-template <int N, int Q, typename Real, bool GEN>
+template <int N, int Q, typename Real, bool GEN, bool WALLS>
 __device__ __forceinline__ void face_group(const OpArgs& a, const KTab<N, Q, Real>& lt, const Phys<Real>& ph, bool conv,
                                            bool visc, int s, int64_t e, const FaceInfo& fi, const Real* sTau,
-                                           const Real* sFn, const Real (&Ji)[9], Real detJ, const Real* sU, Real* sR,
+                                           const Real* sFn, const Real* sJr, Real detJ, const Real* sU, Real* sR,
                                            Real* sW) {
-    using FS = FaceSizes<N, Q>;
+    using FS = FaceSizes<N, Q, OpBlock<N, Q, Real>::threads>;
     constexpr int N2 = N * N, N3 = N2 * N, Q2 = Q * Q;
-    Real* r1 = sW;
-    Real* r2 = sW + FS::R1;
+    // work regions: SW (swept traces, read by the point phase), TR (traces), OUT
+    // (point results), T1 (t1-transposed), W (lifted): see FaceSizes
+    Real* r1 = sW;                 // SW
+    Real* rtr = sW + FS::TR_OFF;   // TR
+    Real* r2 = sW + FS::OUT_OFF;   // OUT, later W
+    Real* rt1 = sW + FS::T1_OFF;   // T1
     const int tid = threadIdx.x, nth = blockDim.x;
     const int64_t cstride = a.ncell * N3;
 
@@ -265,7 +434,7 @@ __device__ __forceinline__ void face_group(const OpArgs& a, const KTab<N, Q, Rea
             tv += lt.fv[s][m] * x;
             tn += lt.fd[s][m] * x;
         }
-        if (!fi.wall[d + 3 * s]) {
+        if (!WALLS || !fi.wall[d + 3 * s]) {
             const double* un_line = a.U + c * cstride + fi.enb[d + 3 * s] * N3 + base;
 #pragma unroll
             for (int m = 0; m < N; ++m) {
@@ -274,7 +443,7 @@ __device__ __forceinline__ void face_group(const OpArgs& a, const KTab<N, Q, Rea
                 un += lt.fd[1 - s][m] * x;
             }
         }
-        Real* tr = r2 + d * (2 * 2 * 5 * N2) + c * N2 + ab;
+        Real* tr = rtr + d * (2 * 2 * 5 * N2) + c * N2 + ab;
         tr[(0 * 2 + 0) * 5 * N2] = tv;
         tr[(0 * 2 + 1) * 5 * N2] = tn;
         tr[(1 * 2 + 0) * 5 * N2] = uv;
@@ -285,8 +454,8 @@ __device__ __forceinline__ void face_group(const OpArgs& a, const KTab<N, Q, Rea
     // sweep along t0: A0 = S tv, A1 = D tv, An = S tn     r1 [f][side][3][c][b][q0]
     for (int it = tid; it < 3 * 2 * 5 * N; it += nth) {
         const int ib = it % N, c = (it / N) % 5, side = (it / (5 * N)) % 2, d = it / (10 * N);
-        if (side == 1 && fi.wall[d + 3 * s]) continue;
-        const Real* tr = r2 + d * (2 * 2 * 5 * N2) + side * (2 * 5 * N2) + c * N2 + ib * N;
+        if (WALLS && side == 1 && fi.wall[d + 3 * s]) continue;
+        const Real* tr = rtr + d * (2 * 2 * 5 * N2) + side * (2 * 5 * N2) + c * N2 + ib * N;
         Real tv[N], tn[N];
 #pragma unroll
         for (int ia = 0; ia < N; ++ia) {
@@ -310,126 +479,38 @@ __device__ __forceinline__ void face_group(const OpArgs& a, const KTab<N, Q, Rea
     }
     __syncthreads();
 
-    // pointwise: t1 contraction of the own line, numerical fluxes, reference-space test coefficients
-    //   r2 [f][kind: val, g_t0, g_t1, g_n][c][q1][q0]
-    for (int it = tid; it < 3 * Q2; it += nth) {
-        const int d = it / Q2, pt = it % Q2, q0 = pt % Q, q1 = pt / Q;
-        const int fslot = d + 3 * s;
-        const bool wall = fi.wall[fslot] != 0;
-        Real Jm[9], nrm[3], dAw;
-        const double* fdp = nullptr;
-        if constexpr (GEN) {
-            fdp = a.face_data[d] + fi.fid[fslot] * 22 * Q2 + pt;
-            const Real sgn = s ? Real(1) : Real(-1);
+    // pointwise: numerical fluxes and reference-space test coefficients at every
+    // face point, stored as OUT [f][kind: val, g_t0, g_t1, g_n][c][q1][q0].  When one
+    // pass of the workgroup covers all face points, the results wait in registers
+    // across a barrier and overwrite the swept traces (smaller LDS footprint).
+    if constexpr (FS::ALIAS) {
+        Real res[20];
+        const bool act = tid < 3 * Q2;
+        if (act) face_point<N, Q, Real, GEN, WALLS>(a, lt, ph, conv, visc, s, fi, sTau, sFn, sJr, detJ, r1, tid, res);
+        __syncthreads();
+        if (act) {
+            Real* o = r2 + (tid / Q2) * 4 * 5 * Q2 + tid % Q2;
 #pragma unroll
-            for (int j = 0; j < 3; ++j) nrm[j] = sgn * (Real)fdp[j * Q2];
-            dAw = (Real)fdp[3 * Q2];
-            const int own = s ? 4 : 13;
-#pragma unroll
-            for (int m = 0; m < 9; ++m) Jm[m] = (Real)fdp[(own + m) * Q2];
-        } else {
-#pragma unroll
-            for (int m = 0; m < 9; ++m) Jm[m] = Ji[m];
-            const Real sgn = s ? Real(1) : Real(-1);
-            const Real* fn = sFn + 4 * d;     // unit normal of face xi_d = 1 and |row d of J^{-1}|
-            nrm[0] = sgn * fn[0];
-            nrm[1] = sgn * fn[1];
-            nrm[2] = sgn * fn[2];
-            dAw = detJ * fn[3] * lt.w[q0] * lt.w[q1];
+            for (int m = 0; m < 20; ++m) o[m * Q2] = res[m];
         }
-        // one side at a time, to keep a single gradient live: the side's value,
-        // physical gradient, F_c.n and F_v.n go straight into the point's coefficient
-        //   val = -1/2 (F_c^- + F_c^+).n + 1/2 (F_v^- + F_v^+).n - (Lambda/2 + tau)(U^- - U^+)
-        Real Um[5], Up[5], val[5], lam_m = 0, lam_p = 0;
-        Prim<Real> sm;
-        {
-            Real G[5][3], Fn[5];
-            load_face_point<N, Q, Real>(lt, r1 + (d * 2 + 0) * 3 * 5 * N * Q, d, q0, q1, Jm, Um, G);
-            sm = primitives(Um, ph);
+    } else {
+        for (int it = tid; it < 3 * Q2; it += nth) {
+            Real res[20];
+            face_point<N, Q, Real, GEN, WALLS>(a, lt, ph, conv, visc, s, fi, sTau, sFn, sJr, detJ, r1, it, res);
+            Real* o = r2 + (it / Q2) * 4 * 5 * Q2 + it % Q2;
 #pragma unroll
-            for (int c = 0; c < 5; ++c) val[c] = 0;
-            if (conv) {
-                lam_m = convective_normal(Um, sm, nrm, ph, Fn);
-#pragma unroll
-                for (int c = 0; c < 5; ++c) val[c] -= Real(0.5) * Fn[c];
-            }
-            if (visc) {
-                viscous_flux_normal(sm, G, nrm, ph, Fn);
-#pragma unroll
-                for (int c = 0; c < 5; ++c) val[c] += Real(0.5) * Fn[c];
-            }
-            if (wall) {
-                wall_mirror(Um, sm, ph, Up);   // the exterior gradient is the interior one: G is kept
-            } else {
-                Real Jp[9];
-                if constexpr (GEN) {
-                    const int oth = s ? 13 : 4;
-#pragma unroll
-                    for (int m = 0; m < 9; ++m) Jp[m] = (Real)fdp[(oth + m) * Q2];
-                } else {
-                    const double* cm = a.cell_metric + fi.enb[fslot] * 10;
-#pragma unroll
-                    for (int m = 0; m < 9; ++m) Jp[m] = (Real)cm[m];
-                }
-                load_face_point<N, Q, Real>(lt, r1 + (d * 2 + 1) * 3 * 5 * N * Q, d, q0, q1, Jp, Up, G);
-            }
-            const Prim<Real> sp = primitives(Up, ph);
-            if (conv) {
-                lam_p = convective_normal(Up, sp, nrm, ph, Fn);
-#pragma unroll
-                for (int c = 0; c < 5; ++c) val[c] -= Real(0.5) * Fn[c];
-            }
-            if (visc) {
-                viscous_flux_normal(sp, G, nrm, ph, Fn);
-#pragma unroll
-                for (int c = 0; c < 5; ++c) val[c] += Real(0.5) * Fn[c];
-            }
-        }
-        Real jump[5];
-#pragma unroll
-        for (int c = 0; c < 5; ++c) jump[c] = Um[c] - Up[c];
-        {
-            const Real lam = lam_m > lam_p ? lam_m : lam_p;
-            const Real pen = (conv ? Real(0.5) * lam : Real(0)) + (visc ? sTau[fslot] : Real(0));
-#pragma unroll
-            for (int c = 0; c < 5; ++c) val[c] -= pen * jump[c];
-        }
-        Real gphys[5][3];
-        if (visc) {
-            viscous_flux_rank1(sm, jump, nrm, ph, gphys);
-        } else {
-#pragma unroll
-            for (int c = 0; c < 5; ++c)
-#pragma unroll
-                for (int j = 0; j < 3; ++j) gphys[c][j] = 0;
-        }
-        const Real half_dAw = Real(0.5) * dAw;
-        Real* o = r2 + d * 4 * 5 * Q2 + pt;
-#pragma unroll
-        for (int c = 0; c < 5; ++c) {
-            Real gref[3];
-#pragma unroll
-            for (int dd = 0; dd < 3; ++dd)
-                gref[dd] = (Jm[dd * 3] * gphys[c][0] + Jm[dd * 3 + 1] * gphys[c][1] + Jm[dd * 3 + 2] * gphys[c][2]) *
-                           half_dAw;
-            const Real gt0 = d == 0 ? gref[1] : gref[0];
-            const Real gt1 = d == 2 ? gref[1] : gref[2];
-            const Real gn = d == 0 ? gref[0] : (d == 1 ? gref[1] : gref[2]);
-            o[(0 * 5 + c) * Q2] = val[c] * dAw;
-            o[(1 * 5 + c) * Q2] = gt0;
-            o[(2 * 5 + c) * Q2] = gt1;
-            o[(3 * 5 + c) * Q2] = gn;
+            for (int m = 0; m < 20; ++m) o[m * Q2] = res[m];
         }
     }
     __syncthreads();
 
-    face_test_accumulate<N, Q, Real>(lt, s, r1, r2, sR);
+    face_test_accumulate<N, Q, Real>(lt, s, rt1, r2, sR);
 }
 
-template <int N, int Q, typename Real, bool GEN>
-__global__ void __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(2)))
+template <int N, int Q, typename Real, bool GEN, bool WALLS>
+__global__ void __launch_bounds__((OpBlock<N, Q, Real>::threads)) __attribute__((amdgpu_waves_per_eu(2)))
 dg_operator_kernel(OpArgs a, KTab<N, Q, Real> tb, MTab<N, Real> mt) {
-    using Sz = OpSizes<N, Q>;
+    using Sz = OpSizes<N, Q, OpBlock<N, Q, Real>::threads>;
     constexpr int P = Sz::P;
     constexpr int N2 = N * N, N3 = N2 * N, Q2 = Q * Q, Q3 = Q2 * Q;
     constexpr int ZS = CellSizes<N, Q, P>::Z, YS = CellSizes<N, Q, P>::Y;
@@ -439,6 +520,7 @@ dg_operator_kernel(OpArgs a, KTab<N, Q, Real> tb, MTab<N, Real> mt) {
     __shared__ FaceInfo fi;
     __shared__ Real sTau[6];
     __shared__ Real sFn[12];   // affine: per direction the unit normal and |row of J^{-1}|
+    __shared__ Real sJr[GEN ? 1 : 27];   // affine: per direction d the rows (t0, t1, d) of J^{-1}
     __shared__ Real lwm[N];
 
     const int64_t e = blockIdx.x;
@@ -501,6 +583,9 @@ dg_operator_kernel(OpArgs a, KTab<N, Q, Real> tb, MTab<N, Real> mt) {
             sFn[4 * d + 1] = (Real)(row[1] / l);
             sFn[4 * d + 2] = (Real)(row[2] / l);
             sFn[4 * d + 3] = (Real)l;
+            const int rows[3] = {d == 0 ? 1 : 0, d == 2 ? 1 : 2, d};
+            for (int r = 0; r < 3; ++r)
+                for (int j = 0; j < 3; ++j) sJr[9 * d + 3 * r + j] = (Real)a.cell_metric[e * 10 + 3 * rows[r] + j];
         }
     }
 
@@ -685,8 +770,8 @@ dg_operator_kernel(OpArgs a, KTab<N, Q, Real> tb, MTab<N, Real> mt) {
         }
 
         // ------------------------------------------------------------ face terms
-        face_group<N, Q, Real, GEN>(a, lt, ph, conv, visc, 0, e, fi, sTau, sFn, Ji, detJ, sU, sR, sW);
-        face_group<N, Q, Real, GEN>(a, lt, ph, conv, visc, 1, e, fi, sTau, sFn, Ji, detJ, sU, sR, sW);
+        face_group<N, Q, Real, GEN, WALLS>(a, lt, ph, conv, visc, 0, e, fi, sTau, sFn, sJr, detJ, sU, sR, sW);
+        face_group<N, Q, Real, GEN, WALLS>(a, lt, ph, conv, visc, 1, e, fi, sTau, sFn, sJr, detJ, sU, sR, sW);
     }
 
     // ------------------------------------------------------------ body force (k+1 rule)
@@ -784,8 +869,13 @@ inline int launch_op_t(const OpArgs& a, const Tables1D& t, hipStream_t st) {
     KTab<N, Q, Real> kt;
     MTab<N, Real> mt;
     fill_tables<N, Q, Real>(t, kt, mt);
-    static_assert((OpSizes<N, Q>::WORK + 10 * N * N * N) * sizeof(Real) <= 160 * 1024, "LDS budget");
-    hipLaunchKernelGGL((dg_operator_kernel<N, Q, Real, GEN>), dim3((unsigned)a.ncell), dim3(kBlock), 0, st, a, kt, mt);
+    constexpr int B = OpBlock<N, Q, Real>::threads;
+    static_assert((OpSizes<N, Q, B>::WORK + 10 * N * N * N) * sizeof(Real) <= 160 * 1024, "LDS budget");
+    const bool walls = !(a.periodic[0] && a.periodic[1] && a.periodic[2]);
+    if (walls)
+        hipLaunchKernelGGL((dg_operator_kernel<N, Q, Real, GEN, true>), dim3((unsigned)a.ncell), dim3(B), 0, st, a, kt, mt);
+    else
+        hipLaunchKernelGGL((dg_operator_kernel<N, Q, Real, GEN, false>), dim3((unsigned)a.ncell), dim3(B), 0, st, a, kt, mt);
     return hipGetLastError() == hipSuccess ? 0 : -1;
 }
 
