@@ -35,7 +35,7 @@ BYTES_PER_DOF = 16.0
 # HBM bytes per launch of the dominant kernel from two rocprofv3 --pmc runs
 # (FETCH_SIZE, WRITE_SIZE), scaled by what the counters read for a plain copy of
 # known size; valid only for the kernel source they were taken on.
-MEASURED_TRAFFIC = {"fingerprint": "70983d7d49c138d5", "workload": (32, 3, 6), "bytes": 356263365.0}
+MEASURED_TRAFFIC = {"fingerprint": "e5c515de13e578ff", "workload": (32, 3, 6), "bytes": 356186224.0}
 
 
 def kernel_fingerprint():
@@ -122,7 +122,7 @@ def main():
     ap.add_argument("--degree", type=int, default=3)
     ap.add_argument("--nq", type=int, default=6)
     ap.add_argument("--op-calls", type=int, default=200)
-    ap.add_argument("--cpu-sample-cells", type=int, default=4096)
+    ap.add_argument("--cpu-sample-cells", type=int, default=12288)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-fp32", action="store_true")
     ap.add_argument("--op-only", type=int, default=0, metavar="CALLS",

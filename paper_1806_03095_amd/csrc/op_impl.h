@@ -288,14 +288,14 @@ __device__ __forceinline__ void face_test_accumulate(const KTab<N, Q, Real>& tb,
 // t1 contraction of both sides' t0-swept traces A (layout [f][side][3][c][N][Q]),
 // the numerical fluxes, and the reference-space test coefficients
 //   res[kind * 5 + c], kind = value, g_t0, g_t1, g_n.
-template <int N, int Q, typename Real, bool GEN, bool WALLS>
+template <int N, int Q, typename Real, bool GEN>
 __device__ __forceinline__ void face_point(const OpArgs& a, const KTab<N, Q, Real>& lt, const Phys<Real>& ph, bool conv,
                                            bool visc, int s, const FaceInfo& fi, const Real* sTau, const Real* sFn,
                                            const Real* sJr, Real detJ, const Real* r1, int it, Real (&res)[20]) {
     constexpr int Q2 = Q * Q;
     const int d = it / Q2, pt = it % Q2, q0 = pt % Q, q1 = pt / Q;
     const int fslot = d + 3 * s;
-    const bool wall = WALLS && fi.wall[fslot] != 0;
+    const bool wall = fi.wall[fslot] != 0;
     // reference axes of the face: tangential t0 < t1, normal d; rows[r] is the
     // row of J^{-1} that multiplies the derivative along the face's axis r
     const int rows[3] = {d == 0 ? 1 : 0, d == 2 ? 1 : 2, d};
@@ -406,7 +406,7 @@ __device__ __forceinline__ void face_point(const OpArgs& a, const KTab<N, Q, Rea
 
 // The three faces xi_d = s (d = 0, 1, 2) of the cell: traces, fluxes, test
 // integration, accumulated into sR.
-template <int N, int Q, typename Real, bool GEN, bool WALLS>
+template <int N, int Q, typename Real, bool GEN>
 __device__ __forceinline__ void face_group(const OpArgs& a, const KTab<N, Q, Real>& lt, const Phys<Real>& ph, bool conv,
                                            bool visc, int s, int64_t e, const FaceInfo& fi, const Real* sTau,
                                            const Real* sFn, const Real* sJr, Real detJ, const Real* sU, Real* sR,
@@ -434,7 +434,7 @@ __device__ __forceinline__ void face_group(const OpArgs& a, const KTab<N, Q, Rea
             tv += lt.fv[s][m] * x;
             tn += lt.fd[s][m] * x;
         }
-        if (!WALLS || !fi.wall[d + 3 * s]) {
+        if (!fi.wall[d + 3 * s]) {
             const double* un_line = a.U + c * cstride + fi.enb[d + 3 * s] * N3 + base;
 #pragma unroll
             for (int m = 0; m < N; ++m) {
@@ -454,7 +454,7 @@ __device__ __forceinline__ void face_group(const OpArgs& a, const KTab<N, Q, Rea
     // sweep along t0: A0 = S tv, A1 = D tv, An = S tn     r1 [f][side][3][c][b][q0]
     for (int it = tid; it < 3 * 2 * 5 * N; it += nth) {
         const int ib = it % N, c = (it / N) % 5, side = (it / (5 * N)) % 2, d = it / (10 * N);
-        if (WALLS && side == 1 && fi.wall[d + 3 * s]) continue;
+        if (side == 1 && fi.wall[d + 3 * s]) continue;
         const Real* tr = rtr + d * (2 * 2 * 5 * N2) + side * (2 * 5 * N2) + c * N2 + ib * N;
         Real tv[N], tn[N];
 #pragma unroll
@@ -486,7 +486,7 @@ __device__ __forceinline__ void face_group(const OpArgs& a, const KTab<N, Q, Rea
     if constexpr (FS::ALIAS) {
         Real res[20];
         const bool act = tid < 3 * Q2;
-        if (act) face_point<N, Q, Real, GEN, WALLS>(a, lt, ph, conv, visc, s, fi, sTau, sFn, sJr, detJ, r1, tid, res);
+        if (act) face_point<N, Q, Real, GEN>(a, lt, ph, conv, visc, s, fi, sTau, sFn, sJr, detJ, r1, tid, res);
         __syncthreads();
         if (act) {
             Real* o = r2 + (tid / Q2) * 4 * 5 * Q2 + tid % Q2;
@@ -496,7 +496,7 @@ __device__ __forceinline__ void face_group(const OpArgs& a, const KTab<N, Q, Rea
     } else {
         for (int it = tid; it < 3 * Q2; it += nth) {
             Real res[20];
-            face_point<N, Q, Real, GEN, WALLS>(a, lt, ph, conv, visc, s, fi, sTau, sFn, sJr, detJ, r1, it, res);
+            face_point<N, Q, Real, GEN>(a, lt, ph, conv, visc, s, fi, sTau, sFn, sJr, detJ, r1, it, res);
             Real* o = r2 + (it / Q2) * 4 * 5 * Q2 + it % Q2;
 #pragma unroll
             for (int m = 0; m < 20; ++m) o[m * Q2] = res[m];
@@ -507,7 +507,7 @@ __device__ __forceinline__ void face_group(const OpArgs& a, const KTab<N, Q, Rea
     face_test_accumulate<N, Q, Real>(lt, s, rt1, r2, sR);
 }
 
-template <int N, int Q, typename Real, bool GEN, bool WALLS>
+template <int N, int Q, typename Real, bool GEN>
 __global__ void __launch_bounds__((OpBlock<N, Q, Real>::threads)) __attribute__((amdgpu_waves_per_eu(2)))
 dg_operator_kernel(OpArgs a, KTab<N, Q, Real> tb, MTab<N, Real> mt) {
     using Sz = OpSizes<N, Q, OpBlock<N, Q, Real>::threads>;
@@ -770,8 +770,8 @@ dg_operator_kernel(OpArgs a, KTab<N, Q, Real> tb, MTab<N, Real> mt) {
         }
 
         // ------------------------------------------------------------ face terms
-        face_group<N, Q, Real, GEN, WALLS>(a, lt, ph, conv, visc, 0, e, fi, sTau, sFn, sJr, detJ, sU, sR, sW);
-        face_group<N, Q, Real, GEN, WALLS>(a, lt, ph, conv, visc, 1, e, fi, sTau, sFn, sJr, detJ, sU, sR, sW);
+        face_group<N, Q, Real, GEN>(a, lt, ph, conv, visc, 0, e, fi, sTau, sFn, sJr, detJ, sU, sR, sW);
+        face_group<N, Q, Real, GEN>(a, lt, ph, conv, visc, 1, e, fi, sTau, sFn, sJr, detJ, sU, sR, sW);
     }
 
     // ------------------------------------------------------------ body force (k+1 rule)
@@ -871,11 +871,7 @@ inline int launch_op_t(const OpArgs& a, const Tables1D& t, hipStream_t st) {
     fill_tables<N, Q, Real>(t, kt, mt);
     constexpr int B = OpBlock<N, Q, Real>::threads;
     static_assert((OpSizes<N, Q, B>::WORK + 10 * N * N * N) * sizeof(Real) <= 160 * 1024, "LDS budget");
-    const bool walls = !(a.periodic[0] && a.periodic[1] && a.periodic[2]);
-    if (walls)
-        hipLaunchKernelGGL((dg_operator_kernel<N, Q, Real, GEN, true>), dim3((unsigned)a.ncell), dim3(B), 0, st, a, kt, mt);
-    else
-        hipLaunchKernelGGL((dg_operator_kernel<N, Q, Real, GEN, false>), dim3((unsigned)a.ncell), dim3(B), 0, st, a, kt, mt);
+    hipLaunchKernelGGL((dg_operator_kernel<N, Q, Real, GEN>), dim3((unsigned)a.ncell), dim3(B), 0, st, a, kt, mt);
     return hipGetLastError() == hipSuccess ? 0 : -1;
 }
 
