@@ -83,6 +83,107 @@ def time_operator(op, U, L, calls):
     return e0.elapsed_time(e1) / 1e3 / calls
 
 
+def time_call(fn, calls):
+    """Average seconds per call of fn() (HIP events on the current stream)."""
+    import torch
+    for _ in range(3):
+        fn()
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(calls):
+        fn()
+    e1.record()
+    torch.cuda.synchronize()
+    return e0.elapsed_time(e1) / 1e3 / calls
+
+
+def copy_bandwidth(mib=1024, calls=20):
+    """Measured device-to-device copy rate in B/s (read + write bytes per second)."""
+    import torch
+    n = mib * (1 << 20) // 8
+    a = torch.ones(n, dtype=torch.float64, device="cuda")
+    b = torch.empty_like(a)
+    t = time_call(lambda: b.copy_(a), calls)
+    return 2 * 8 * n / t
+
+
+def operations(op, U, t_op, t_step, calls):
+    """The paper's six operations timed separately (per launch): F_c, F_v, F (all
+    terms, before M^{-1}), M^{-1}, the Runge-Kutta vector update, and L."""
+    import torch
+    ndof = op.n_dof
+    R = torch.empty_like(U)
+    out = {}
+    for name, mask in (("F_c", 1), ("F_v", 2), ("F", 7)):
+        t = time_call(lambda: op.residual(U, R, terms=mask), calls)
+        out[name] = {"us": 1e6 * t, "dofs_per_s": ndof / t}
+    t = time_call(lambda: op.inverse_mass(U, R), calls)
+    out["M_inv"] = {"us": 1e6 * t, "dofs_per_s": ndof / t, "hbm_frac": 16 * ndof / t / PEAK_HBM}
+    t_upd = max(t_step / 5.0 - t_op, 0.0)
+    out["rk_update"] = {"us": 1e6 * t_upd, "hbm_frac": (40 * ndof / t_upd / PEAK_HBM) if t_upd > 0 else None,
+                        "note": "per stage: RK step time / 5 minus one operator launch"}
+    out["L"] = {"us": 1e6 * t_op, "dofs_per_s": ndof / t_op}
+    return out
+
+
+def channel_throughput(calls):
+    """Operator throughput on the stretched channel of 16^3 cells, k=4, n_q=7 (per-point metric)."""
+    import torch
+    from paper_1806_03095_amd import Operator
+    mu, gamma, R, Pr = 1.0 / 180.0, 1.4, 287.0, 0.71
+    umax, mach = 18.3, 0.1
+    T0 = (umax / mach) ** 2 / (gamma * R)
+    res = {}
+    for prec in ("fp64", "fp32"):
+        op = Operator(4, 7, (16, 16, 16), (0.0, -1.0, 0.0), (2 * math.pi, 1.0, math.pi), periodic=(1, 0, 1),
+                      kind="channel", precision=prec, gamma=gamma, R=R, mu=mu,
+                      lam=mu * gamma * R / (gamma - 1) / Pr, body_force=(1.0, 0.0, 0.0), wall_T=T0)
+        U = op.project_ic("channel", [umax, mach, 2.0, 0.0])
+        L = torch.empty_like(U)
+        t = time_call(lambda: op.apply(U, L), calls)
+        res[prec] = {"us": 1e6 * t, "dofs_per_s": op.n_dof / t}
+        op.close()
+    res["workload"] = "channel_16cubed_k4_nq7_tanh1.8"
+    return res
+
+
+def precision_study(steps):
+    """Float32 vs float64 operator over `steps` RK steps from the same state, for
+    the Taylor-Green 16^3 k=7 n_q=11 and 24^3 k=5 n_q=8 workloads: relative
+    difference of the kinetic energy and of its dissipation rate -de_k/dt after the
+    run, and of L at the initial state."""
+    import torch
+    from paper_1806_03095_amd import taylor_green
+    out = []
+    for ne, k, nq in ((16, 7, 11), (24, 5, 8)):
+        ops = {p: taylor_green(k, ne, n_q=nq, precision=p) for p in ("fp64", "fp32")}
+        U0 = ops["fp64"].project_ic("taylor_green", [1.0, 1.0, 0.1, 1.0])
+        dt = ops["fp64"].compute_dt(0.4, 0.02, 1.5, 3.0, 1.0, 0.1)
+        L64, L32 = ops["fp64"].apply(U0), ops["fp32"].apply(U0)
+        row = {"workload": "taylor_green_%dcubed_k%d_nq%d" % (ne, k, nq), "n_dof": ops["fp64"].n_dof,
+               "steps": steps, "dt": dt,
+               "L0_rel_err": float(torch.linalg.norm(L32 - L64) / torch.linalg.norm(L64))}
+        res = {}
+        for p, op in ops.items():
+            U = U0.clone()
+            work = torch.empty(2 * op.n_dof, dtype=torch.float64, device="cuda")
+            t, _ = time_rk(op, U, work, dt, steps, 0)
+            d = ops["fp64"].diagnostics(U, ops["fp64"].apply(U))
+            res[p] = {"U": U, "e_k": d["e_k"], "rate": d["rate"], "ms_per_step": 1e3 * t / steps}
+            log("%s %s: %d steps, %.3f ms/step, e_k=%.8f, -de_k/dt=%.6e"
+                % (row["workload"], p, steps, 1e3 * t / steps, d["e_k"], d["rate"]))
+        a, b = res["fp32"], res["fp64"]
+        row.update(e_k_fp64=b["e_k"], e_k_fp32=a["e_k"], e_k_rel_err=abs(a["e_k"] - b["e_k"]) / abs(b["e_k"]),
+                   rate_fp64=b["rate"], rate_fp32=a["rate"], rate_rel_err=abs(a["rate"] - b["rate"]) / abs(b["rate"]),
+                   U_rel_err=float(torch.linalg.norm(a["U"] - b["U"]) / torch.linalg.norm(b["U"])),
+                   ms_per_step_fp64=b["ms_per_step"], ms_per_step_fp32=a["ms_per_step"],
+                   speedup=b["ms_per_step"] / a["ms_per_step"])
+        out.append(row)
+        del ops, res
+    return out
+
+
 def cpu_baseline(ne, k, nq, n_sample):
     """The oracle, as it stands, on a sample of cells of the same workload."""
     import numpy as np
@@ -130,6 +231,10 @@ def main():
     ap.add_argument("--precision", default="fp64", choices=("fp64", "fp32"), help="precision of --op-only")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
                     help="profiling mode: one device-to-device copy of MIB MiB (HBM counter calibration)")
+    ap.add_argument("--no-extras", action="store_true",
+                    help="skip the operation breakdown, copy bandwidth and channel figures")
+    ap.add_argument("--precision-study", type=int, default=0, metavar="STEPS",
+                    help="study mode: float32 vs float64 over STEPS RK steps (16^3 k=7, 24^3 k=5); one JSON line")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py measures one GPU only: this build has no multi-GPU path (the halo-exchange "
@@ -147,6 +252,10 @@ def main():
         b.copy_(a)
         torch.cuda.synchronize()
         log("copied %d MiB (read %d B, write %d B)" % (args.copy_calibration, 8 * n, 8 * n))
+        return
+
+    if args.precision_study:
+        print(json.dumps({"precision_study": precision_study(args.precision_study)}), flush=True)
         return
 
     k, nq, ne = args.degree, args.nq, args.cells
@@ -197,6 +306,15 @@ def main():
            "roofline": roof,
            "operator_only": {"dofs_per_s": ndof / t_op, "us_per_launch": 1e6 * t_op,
                              "hbm_frac_16B_per_dof": round(hbm_frac, 5)}}
+
+    if not args.no_extras:
+        out["operations"] = operations(op, U0, t_op, t64 / args.steps, max(args.op_calls // 4, 10))
+        bw = copy_bandwidth()
+        out["copy_bandwidth"] = {"bytes_per_s": bw, "frac_of_peak": bw / PEAK_HBM,
+                                 "operator_hbm_frac_of_copy": BYTES_PER_DOF * ndof / t_op / bw}
+        out["channel"] = channel_throughput(max(args.op_calls // 4, 10))
+        log("operations: " + ", ".join("%s %.1f us" % (n, v["us"]) for n, v in out["operations"].items()))
+        log("copy %.2f TB/s; channel fp64 %.3e DoF/s" % (bw / 1e12, out["channel"]["fp64"]["dofs_per_s"]))
 
     if not args.no_fp32:
         op32 = taylor_green(k, ne, n_q=nq, precision="fp32")

@@ -94,8 +94,8 @@ class DGOperator:
         Pm, _ = meshmod.tensor_basis(self.nodes, self.mass_pts)
         self.Phi_m = _t(Pm)
         self._tau = np.full(mesh.n_cells, np.nan)
-        if mesh.n_cells <= 4096:
-            # small meshes: all penalties up front, so that a residual evaluated
+        if mesh.n_cells <= 64:
+            # tiny meshes: all penalties up front, so that a residual evaluated
             # under a function transform (torch.func.jvp) never computes them
             self._penalty(np.arange(mesh.n_cells))
 

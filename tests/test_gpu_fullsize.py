@@ -1,0 +1,176 @@
+"""GPU parity at the full workload sizes, in the launch configuration bench.py times.
+
+The oracle cannot evaluate the whole 32^3 mesh in a test, so these tests compare
+the HIP operator with the oracle on a seeded sample of cells (each cell's output
+depends only on itself and its six face neighbours), and check properties that
+hold at any size (conservation under periodic boundaries) where a sample cannot
+be formed.  The state is built by the oracle on the sampled cells and their
+neighbours (L2 projection plus seeded noise) over a uniform background state
+elsewhere; both sides receive the same array.
+
+Workloads: Taylor-Green 32^3 cells k=3 n_q=6 (float64 and float32); stretched
+channel 16^3 cells k=4 n_q=7 with walls and body force; Taylor-Green 16^3 k=7
+n_q=11 and 24^3 k=5 n_q=8 (the precision-study sizes).
+"""
+import math
+
+import numpy as np
+import pytest
+import torch
+
+import synth
+from oracle import initial
+from tests.gpu_cases import announce, make_pair, rel_err_fields, tgv_fluid
+from tests.test_gpu_parity import _check_low_mach, tol_k
+
+pytestmark = pytest.mark.gpu
+
+
+def _sample_cells(n, count, seed):
+    """Corner and edge cells of the box (periodic wrap-around) plus seeded random ones."""
+    nx, ny, nz = n
+    corners = [0, nx - 1, nx * (ny - 1), nx * ny - 1, nx * ny * (nz - 1), nx * ny * nz - 1]
+    rng = synth.rng(seed)
+    rest = rng.choice(nx * ny * nz, size=count, replace=False)
+    return np.unique(np.concatenate([np.asarray(corners, dtype=np.int64), rest.astype(np.int64)]))
+
+
+def _patched_state(oop, cells, func, background, seed, noise):
+    """Uniform `background` everywhere; oracle projection of func plus noise on
+    `cells` and their face neighbours."""
+    m = oop.mesh
+    nbs = m.nb[cells].reshape(-1)
+    need = np.unique(np.concatenate([cells, nbs[nbs >= 0]]))
+    U = torch.empty(5, m.n_cells, oop.N, dtype=torch.float64)
+    U[:] = torch.as_tensor(background, dtype=torch.float64)[:, None, None]
+    P = initial.l2_project(oop, func, cells=need).numpy()
+    U[:, need, :] = torch.as_tensor(synth.relative_noise(P, seed, noise))
+    return U
+
+
+def _low_mach_tol(oop, k):
+    """Tolerances (normwise, per field) of the low-Mach comparison on this mesh.
+
+    The 1e-12 / 1e-11 bounds hold on the 4^3 Taylor-Green mesh (h = pi/2).  The
+    cancellation they allow for grows as 1/h: each quadrature term of a momentum row
+    is of order p0 |J| |grad phi| ~ p0 h^2 while the row's result is of order
+    |L| h^3, so the rounding error relative to the result scales with
+    p0 / (h |L|).  Both evaluations (oracle and kernel) carry it."""
+    s = max(1.0, (math.pi / 2) / oop.mesh.h_min())
+    return tol_k(k) * s, 10 * tol_k(k) * s
+
+
+def _tgv_func(oop, mach):
+    return lambda x: initial.taylor_green(x, oop.fl, mach=mach)
+
+
+def _rest_background(fl, mach):
+    p0 = 1.0 / (fl.gamma * mach ** 2)
+    return [1.0, 0.0, 0.0, 0.0, p0 / (fl.gamma - 1.0)]
+
+
+def _gpu_apply_sampled(gop, U, cells):
+    out = gop.apply(U.to("cuda").contiguous())
+    torch.cuda.synchronize()
+    return out[:, torch.as_tensor(cells, device="cuda"), :].cpu()
+
+
+def test_tgv_32cubed_k3_nq6_operator_sampled():
+    announce("tgv 32^3 k=3 nq=6 fp64 operator, 70 sampled cells")
+    n = (32, 32, 32)
+    oop, gop = make_pair(n, 3, 6)
+    cells = _sample_cells(n, 64, seed=11)
+    U = _patched_state(oop, cells, _tgv_func(oop, 0.1), _rest_background(oop.fl, 0.1), seed=12, noise=1e-3)
+    got = _gpu_apply_sampled(gop, U, cells)
+    want = oop.apply(U, cells=cells)
+    nt, ft = _low_mach_tol(oop, 3)
+    errs = _check_low_mach(got, want, "L 32^3 sample", norm_tol=nt, field_tol=ft)
+    print("per-field relative error on the sample:", errs, flush=True)
+    # the residual before M^{-1}, each term on its own
+    Ug = U.to("cuda").contiguous()
+    for terms, mask in (("c", 1), ("v", 2)):
+        R = gop.residual(Ug, terms=mask)
+        torch.cuda.synchronize()
+        Rs = R[:, torch.as_tensor(cells, device="cuda"), :].cpu()
+        _check_low_mach(Rs, oop.residual(U, cells=cells, terms=terms), "R_%s 32^3 sample" % terms, norm_tol=nt,
+                        field_tol=ft)
+
+
+def test_tgv_32cubed_fp32_error_sampled():
+    announce("tgv 32^3 k=3 nq=6 fp32 operator vs oracle, 70 sampled cells")
+    n = (32, 32, 32)
+    oop, gop = make_pair(n, 3, 6, precision="fp32")
+    cells = _sample_cells(n, 64, seed=11)
+    U = _patched_state(oop, cells, _tgv_func(oop, 0.1), _rest_background(oop.fl, 0.1), seed=12, noise=1e-3)
+    got = _gpu_apply_sampled(gop, U, cells)
+    errs = rel_err_fields(got, oop.apply(U, cells=cells))
+    print("fp32 per-field relative error on the sample:", errs, flush=True)
+    # float32 rounding (6e-8) of the background pressure p0 = 71 against momentum
+    # rates of order 1e-2..1 on this mesh: a few percent at most
+    assert max(errs) < 1e-1, errs
+
+
+def test_tgv_32cubed_rk_conserves_totals():
+    announce("tgv 32^3 k=3 nq=6: 5 RK steps conserve mass, momentum, energy")
+    from paper_1806_03095_amd import taylor_green
+    gop = taylor_green(3, 32, 6)
+    U = gop.project_ic("taylor_green", [1.0, 1.0, 0.1, 1.0])
+    work = torch.empty(2 * gop.n_dof, dtype=torch.float64, device="cuda")
+    d0 = gop.diagnostics(U)
+    dt = gop.compute_dt(0.35, 0.15, 1.5, 3.0, 1.0, 0.1)
+    ek = [d0["e_k"]]
+    for s in range(5):
+        gop.rk_step(U, work, s * dt, dt)
+        ek.append(gop.diagnostics(U)["e_k"])
+    d1 = gop.diagnostics(U)
+    scale = abs(d0["energy"])
+    assert abs(d1["mass"] - d0["mass"]) < 1e-13 * abs(d0["mass"])
+    assert abs(d1["energy"] - d0["energy"]) < 1e-13 * scale
+    for a, b in zip(d1["mom"], d0["mom"]):
+        assert abs(a - b) < 1e-13 * abs(d0["mass"])
+    # the kinetic energy decays monotonically (viscous dissipation)
+    assert all(b < a for a, b in zip(ek, ek[1:])), ek
+
+
+def test_channel_16cubed_k4_nq7_sampled():
+    announce("channel 16^3 k=4 nq=7 walls + body force, sampled cells incl. walls")
+    n = (16, 16, 16)
+    mu = 1.0 / 180.0
+    fl = tgv_fluid(mu=mu)
+    umax, mach = 18.3, 0.1
+    c = umax / mach
+    T0 = c * c / (fl.gamma * fl.R)
+    oop, gop = make_pair(n, 4, 7, lo=(0.0, -1.0, 0.0), hi=(2 * math.pi, 1.0, math.pi), periodic=(1, 0, 1),
+                         kind="channel", fluid=fl, force=(1.0, 0.0, 0.0), wall_T=T0)
+    # sampled cells: the seeded ones plus whole columns next to both walls
+    cells = _sample_cells(n, 40, seed=21)
+    walls = [i + 16 * (j + 16 * kk) for i in (0, 7) for j in (0, 15) for kk in (0, 9)]
+    cells = np.unique(np.concatenate([cells, np.asarray(walls, dtype=np.int64)]))
+    p0 = fl.R * T0
+    back = [1.0, 0.0, 0.0, 0.0, p0 / (fl.gamma - 1.0)]
+    U = _patched_state(oop, cells, lambda x: initial.channel_laminar(x, fl, umax=umax, mach=mach), back,
+                       seed=22, noise=1e-2)
+    got = _gpu_apply_sampled(gop, U, cells)
+    want = oop.apply(U, cells=cells)
+    nt, ft = _low_mach_tol(oop, 4)
+    errs = _check_low_mach(got, want, "L channel 16^3 sample", norm_tol=nt, field_tol=ft)
+    print("per-field relative error on the sample:", errs, flush=True)
+
+
+@pytest.mark.parametrize("n1,k,nq", [(16, 7, 11), (24, 5, 8)])
+def test_precision_study_sizes_sampled(n1, k, nq):
+    announce("tgv %d^3 k=%d nq=%d fp64 and fp32 operators, sampled cells" % (n1, k, nq))
+    n = (n1,) * 3
+    oop, g64 = make_pair(n, k, nq)
+    cells = _sample_cells(n, 24, seed=31)
+    U = _patched_state(oop, cells, _tgv_func(oop, 0.1), _rest_background(oop.fl, 0.1), seed=32, noise=1e-3)
+    want = oop.apply(U, cells=cells)
+    got = _gpu_apply_sampled(g64, U, cells)
+    nt, ft = _low_mach_tol(oop, k)
+    errs = _check_low_mach(got, want, "L fp64 sample", norm_tol=nt, field_tol=ft)
+    print("fp64 per-field relative error on the sample:", errs, flush=True)
+    del g64
+    _, g32 = make_pair(n, k, nq, precision="fp32")
+    e32 = rel_err_fields(_gpu_apply_sampled(g32, U, cells), want)
+    print("fp32 per-field relative error on the sample:", e32, flush=True)
+    assert max(e32) < 1e-1, e32

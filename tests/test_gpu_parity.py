@@ -55,6 +55,8 @@ def _check_low_mach(got, want, what, norm_tol=1e-12, field_tol=1e-11):
     g = torch.as_tensor(got).cpu()
     w = torch.as_tensor(want).cpu()
     norm = float(torch.linalg.norm(g - w) / torch.linalg.norm(w))
+    print("%s: normwise %.3e (bound %.1e), per field %s (bound %.1e)"
+          % (what, norm, norm_tol, ["%.2e" % v for v in rel_err_fields(g, w)], field_tol), flush=True)
     assert norm < norm_tol, (what, norm)
     return _check_fields(g, w, field_tol, what)
 
