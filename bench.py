@@ -35,6 +35,12 @@ BYTES_PER_DOF = 16.0
 # HBM bytes per launch of the dominant kernel from two rocprofv3 --pmc runs
 # (FETCH_SIZE, WRITE_SIZE), scaled by what the counters read for a plain copy of
 # known size; valid only for the kernel source they were taken on.
+# Courant numbers of the time step (eq. TimeStepRestrictions_Compressible, e = 1.5):
+# about 2/3 of the largest value for which 400 steps of the 5-stage scheme stay
+# finite on these Taylor-Green meshes (measured: 0.40-0.45 at k=3 and k=5,
+# 0.35-0.40 at k=7).
+CR = 0.3
+CR_STUDY = 0.25
 MEASURED_TRAFFIC = {"fingerprint": "e5c515de13e578ff", "workload": (32, 3, 6), "bytes": 356186224.0}
 
 
@@ -159,7 +165,7 @@ def precision_study(steps):
     for ne, k, nq in ((16, 7, 11), (24, 5, 8)):
         ops = {p: taylor_green(k, ne, n_q=nq, precision=p) for p in ("fp64", "fp32")}
         U0 = ops["fp64"].project_ic("taylor_green", [1.0, 1.0, 0.1, 1.0])
-        dt = ops["fp64"].compute_dt(0.4, 0.02, 1.5, 3.0, 1.0, 0.1)
+        dt = ops["fp64"].compute_dt(CR_STUDY, 0.02, 1.5, 3.0, 1.0, 0.1)
         L64, L32 = ops["fp64"].apply(U0), ops["fp32"].apply(U0)
         row = {"workload": "taylor_green_%dcubed_k%d_nq%d" % (ne, k, nq), "n_dof": ops["fp64"].n_dof,
                "steps": steps, "dt": dt,
@@ -272,7 +278,7 @@ def main():
     op = taylor_green(k, ne, n_q=nq, precision="fp64")
     ndof = op.n_dof
     U0 = op.project_ic("taylor_green", [1.0, 1.0, 0.1, 1.0])
-    dt = op.compute_dt(0.4, 0.02, 1.5, 3.0, 1.0, 0.1)
+    dt = op.compute_dt(CR, 0.02, 1.5, 3.0, 1.0, 0.1)
     work = torch.empty(2 * ndof, dtype=torch.float64, device="cuda")
     U = U0.clone()
     log("fp64: %d warmup + %d timed RK steps, dt=%.4e" % (args.warmup, args.steps, dt))
