@@ -41,6 +41,7 @@ inline const char* hipGetErrorString(hipError_t) { return "emulated"; }
 #define __host__
 #define __forceinline__ inline
 #define __launch_bounds__(x)
+#define amdgpu_waves_per_eu(...)   // AMDGPU register-allocation attribute: meaningless on the host
 #define __shared__ static
 #define __restrict__
 // Reusable barrier of the emulated workgroup's threads.
