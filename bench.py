@@ -154,6 +154,36 @@ def channel_throughput(calls):
     return res
 
 
+def adjoint_timing():
+    """The differentiation workload: gradient of the kinetic energy after 50 RK steps
+    with respect to the initial state (Taylor-Green 16^3 cells, k=3, n_q=6, float64),
+    checkpoints every 10 steps; forward and backward wall time, and the operator VJP
+    against the operator on the same mesh."""
+    import torch
+    from paper_1806_03095_amd import taylor_green
+    from paper_1806_03095_amd.autograd import kinetic_energy, rk_rollout
+    op = taylor_green(3, 16, n_q=6)
+    U0 = op.project_ic("taylor_green", [1.0, 1.0, 0.1, 1.0])
+    dt = op.compute_dt(CR, 0.02, 1.5, 3.0, 1.0, 0.1)
+    L = torch.empty_like(U0)
+    t_op = time_call(lambda: op.apply(U0, L), 20)
+    Ub = torch.empty_like(U0)
+    t_vjp = time_call(lambda: op.operator_vjp(U0, L, out=Ub), 20)
+    x = U0.clone().requires_grad_(True)
+    torch.cuda.synchronize()
+    w0 = time.perf_counter()
+    K = kinetic_energy(rk_rollout(x, op, 50, dt, ckpt_every=10), op)
+    torch.cuda.synchronize()
+    w1 = time.perf_counter()
+    (g,) = torch.autograd.grad(K, x)
+    torch.cuda.synchronize()
+    w2 = time.perf_counter()
+    return {"workload": "taylor_green_16cubed_k3_nq6_50steps_ckpt10", "n_dof": op.n_dof,
+            "forward_s": w1 - w0, "backward_s": w2 - w1, "backward_over_forward": (w2 - w1) / (w1 - w0),
+            "operator_us": 1e6 * t_op, "operator_vjp_us": 1e6 * t_vjp, "vjp_over_operator": t_vjp / t_op,
+            "grad_finite": bool(torch.isfinite(g).all())}
+
+
 def precision_study(steps):
     """Float32 vs float64 operator over `steps` RK steps from the same state, for
     the Taylor-Green 16^3 k=7 n_q=11 and 24^3 k=5 n_q=8 workloads: relative
@@ -319,6 +349,7 @@ def main():
         out["copy_bandwidth"] = {"bytes_per_s": bw, "frac_of_peak": bw / PEAK_HBM,
                                  "operator_hbm_frac_of_copy": BYTES_PER_DOF * ndof / t_op / bw}
         out["channel"] = channel_throughput(max(args.op_calls // 4, 10))
+        out["adjoint"] = adjoint_timing()
         log("operations: " + ", ".join("%s %.1f us" % (n, v["us"]) for n, v in out["operations"].items()))
         log("copy %.2f TB/s; channel fp64 %.3e DoF/s" % (bw / 1e12, out["channel"]["fp64"]["dofs_per_s"]))
 

@@ -58,7 +58,7 @@ struct AdjSizes {
 
 // Adjoint of the three faces xi_d = s.  sX = [U_e; Rbar_e] (10 fields), Rb = Rbar (global).
 template <int N, int Q, bool GEN>
-__device__ __forceinline__ void adj_face_group(const OpArgs& a, const double* Rb, const KTab<N, Q, double>& tb,
+__device__ __forceinline__ void adj_face_group(const OpArgs& a, const double* Rb, const KTab<N, Q, double>& lt,
                                                const Phys<double>& ph, bool conv, bool visc, int s, const FaceInfo& fi,
                                                const double* sTau, const double* sFn, const double (&Ji)[9], double detJ,
                                                const double* sX, double* sUb, double* sW) {
@@ -80,16 +80,16 @@ __device__ __forceinline__ void adj_face_group(const OpArgs& a, const double* Rb
 #pragma unroll
         for (int m = 0; m < N; ++m) {
             const Real x = sX[(src * 5 + c) * N3 + base + m * sd];
-            tv += tb.fv[s][m] * x;
-            tn += tb.fd[s][m] * x;
+            tv += lt.fv[s][m] * x;
+            tn += lt.fd[s][m] * x;
         }
         if (!fi.wall[d + 3 * s]) {
             const double* g = (src == 0 ? a.U : Rb) + c * cstride + fi.enb[d + 3 * s] * N3 + base;
 #pragma unroll
             for (int m = 0; m < N; ++m) {
                 const Real x = g[m * sd];
-                uv += tb.fv[1 - s][m] * x;
-                un += tb.fd[1 - s][m] * x;
+                uv += lt.fv[1 - s][m] * x;
+                un += lt.fd[1 - s][m] * x;
             }
         }
         Real* tr = r2 + (d * 8 + src * 4) * 5 * N2 + c * N2 + ab;
@@ -117,9 +117,9 @@ __device__ __forceinline__ void adj_face_group(const OpArgs& a, const double* Rb
             Real a0 = 0, a1 = 0, an = 0;
 #pragma unroll
             for (int ia = 0; ia < N; ++ia) {
-                a0 += tb.S[q0][ia] * tv[ia];
-                a1 += tb.D[q0][ia] * tv[ia];
-                an += tb.S[q0][ia] * tn[ia];
+                a0 += lt.S[q0][ia] * tv[ia];
+                a1 += lt.D[q0][ia] * tv[ia];
+                an += lt.S[q0][ia] * tn[ia];
             }
             o[q0] = a0;
             o[5 * N * Q + q0] = a1;
@@ -157,13 +157,13 @@ __device__ __forceinline__ void adj_face_group(const OpArgs& a, const double* Rb
             nrm[0] = sgn * fn[0];
             nrm[1] = sgn * fn[1];
             nrm[2] = sgn * fn[2];
-            dAw = detJ * fn[3] * tb.w[q0] * tb.w[q1];
+            dAw = detJ * fn[3] * lt.w[q0] * lt.w[q1];
         }
         const Real* A = r1 + d * 4 * 3 * 5 * N * Q;
         constexpr int SS = 3 * 5 * N * Q;
         Real Um[5], Gm[5][3], Up[5], Gp[5][3], rbm[5], gbm[5][3], rbp[5], gbp[5][3];
-        load_face_point<N, Q, Real>(tb, A + 0 * SS, d, q0, q1, Jm, Um, Gm);
-        load_face_point<N, Q, Real>(tb, A + 2 * SS, d, q0, q1, Jm, rbm, gbm);
+        load_face_point<N, Q, Real>(lt, A + 0 * SS, d, q0, q1, Jm, Um, Gm);
+        load_face_point<N, Q, Real>(lt, A + 2 * SS, d, q0, q1, Jm, rbm, gbm);
         const Prim<Real> sm = primitives(Um, ph);
         if (wall) {
             wall_mirror(Um, sm, ph, Up);
@@ -177,8 +177,8 @@ __device__ __forceinline__ void adj_face_group(const OpArgs& a, const double* Rb
                 }
             }
         } else {
-            load_face_point<N, Q, Real>(tb, A + 1 * SS, d, q0, q1, Jp, Up, Gp);
-            load_face_point<N, Q, Real>(tb, A + 3 * SS, d, q0, q1, Jp, rbp, gbp);
+            load_face_point<N, Q, Real>(lt, A + 1 * SS, d, q0, q1, Jp, Up, Gp);
+            load_face_point<N, Q, Real>(lt, A + 3 * SS, d, q0, q1, Jp, rbp, gbp);
         }
         const Prim<Real> sp = primitives(Up, ph);
         Real jump[5], vb[5];
@@ -263,7 +263,7 @@ __device__ __forceinline__ void adj_face_group(const OpArgs& a, const double* Rb
         }
     }
     __syncthreads();
-    face_test_accumulate<N, Q, Real>(tb, s, r1, r2, sUb);
+    face_test_accumulate<N, Q, Real>(lt, s, r1, r2, sUb);
 }
 
 template <int N, int Q, bool GEN>
@@ -294,6 +294,11 @@ dg_adjoint_kernel(OpArgs a, const double* Rb, KTab<N, Q, double> tb, MTab<N, dou
         sX[5 * N3 + i] = Rb[c * cstride + e * N3 + j];
         sUb[i] = 0;
     }
+    // LDS copies of the 1D tables (every lookup reads LDS; see the forward kernel)
+    __shared__ KTab<N, Q, double> lt;
+    __shared__ MTab<N, double> lm;
+    copy_table<KTab<N, Q, double>, double>(tb, lt);
+    copy_table<MTab<N, double>, double>(mt, lm);
     for (int f = tid; f < 6; f += nth) {
         const int i0 = (int)(e % a.n[0]), i1 = (int)((e / a.n[0]) % a.n[1]), i2 = (int)(e / ((int64_t)a.n[0] * a.n[1]));
         const int d = f % 3, s = f / 3;
@@ -346,8 +351,8 @@ dg_adjoint_kernel(OpArgs a, const double* Rb, KTab<N, Q, double> tb, MTab<N, dou
                 Real z0 = 0, z1 = 0;
 #pragma unroll
                 for (int i = 0; i < N; ++i) {
-                    z0 += tb.S[pz][i] * v[i];
-                    z1 += tb.D[pz][i] * v[i];
+                    z0 += lt.S[pz][i] * v[i];
+                    z1 += lt.D[pz][i] * v[i];
                 }
                 sZ[(0 * 10 + c) * Q * N2 + pz * N2 + r] = z0;
                 sZ[(1 * 10 + c) * Q * N2 + pz * N2 + r] = z1;
@@ -370,9 +375,9 @@ dg_adjoint_kernel(OpArgs a, const double* Rb, KTab<N, Q, double> tb, MTab<N, dou
                     Real y00 = 0, y10 = 0, y01 = 0;
 #pragma unroll
                     for (int i = 0; i < N; ++i) {
-                        y00 += tb.S[py][i] * z0[i];
-                        y10 += tb.D[py][i] * z0[i];
-                        y01 += tb.S[py][i] * z1[i];
+                        y00 += lt.S[py][i] * z0[i];
+                        y10 += lt.D[py][i] * z0[i];
+                        y01 += lt.S[py][i] * z1[i];
                     }
                     sY[((0 * 10 + c) * P + pl) * Q * N + py * N + a0] = y00;
                     sY[((1 * 10 + c) * P + pl) * Q * N + py * N + a0] = y10;
@@ -395,10 +400,10 @@ dg_adjoint_kernel(OpArgs a, const double* Rb, KTab<N, Q, double> tb, MTab<N, dou
                         const Real y00 = sY[((0 * 10 + c) * P + pl) * Q * N + py * N + i];
                         const Real y10 = sY[((1 * 10 + c) * P + pl) * Q * N + py * N + i];
                         const Real y01 = sY[((2 * 10 + c) * P + pl) * Q * N + py * N + i];
-                        v += tb.S[px][i] * y00;
-                        dx += tb.D[px][i] * y00;
-                        dy += tb.S[px][i] * y10;
-                        dz += tb.S[px][i] * y01;
+                        v += lt.S[px][i] * y00;
+                        dx += lt.D[px][i] * y00;
+                        dy += lt.S[px][i] * y10;
+                        dz += lt.S[px][i] * y01;
                     }
                     X[c] = v;
                     Gr[c][0] = dx;
@@ -415,7 +420,7 @@ dg_adjoint_kernel(OpArgs a, const double* Rb, KTab<N, Q, double> tb, MTab<N, dou
                 } else {
 #pragma unroll
                     for (int m = 0; m < 9; ++m) J[m] = Ji[m];
-                    jxw = detJ * tb.w[px] * tb.w[py] * tb.w[pz];
+                    jxw = detJ * lt.w[px] * lt.w[py] * lt.w[pz];
                 }
                 Real U[5], G[5][3], Fb[5][3];
 #pragma unroll
@@ -465,10 +470,10 @@ dg_adjoint_kernel(OpArgs a, const double* Rb, KTab<N, Q, double> tb, MTab<N, dou
                 Real b1 = 0, b2 = 0, b3 = 0;
 #pragma unroll
                 for (int px = 0; px < Q; ++px) {
-                    b1 += tb.S[px][a0] * sF[((0 * 5 + c) * P + pl) * Q2 + py * Q + px] +
-                          tb.D[px][a0] * sF[((1 * 5 + c) * P + pl) * Q2 + py * Q + px];
-                    b2 += tb.S[px][a0] * sF[((2 * 5 + c) * P + pl) * Q2 + py * Q + px];
-                    b3 += tb.S[px][a0] * sF[((3 * 5 + c) * P + pl) * Q2 + py * Q + px];
+                    b1 += lt.S[px][a0] * sF[((0 * 5 + c) * P + pl) * Q2 + py * Q + px] +
+                          lt.D[px][a0] * sF[((1 * 5 + c) * P + pl) * Q2 + py * Q + px];
+                    b2 += lt.S[px][a0] * sF[((2 * 5 + c) * P + pl) * Q2 + py * Q + px];
+                    b3 += lt.S[px][a0] * sF[((3 * 5 + c) * P + pl) * Q2 + py * Q + px];
                 }
                 sB[((0 * 5 + c) * P + pl) * Q * N + py * N + a0] = b1;
                 sB[((1 * 5 + c) * P + pl) * Q * N + py * N + a0] = b2;
@@ -482,9 +487,9 @@ dg_adjoint_kernel(OpArgs a, const double* Rb, KTab<N, Q, double> tb, MTab<N, dou
                 Real e1 = 0, e2 = 0;
 #pragma unroll
                 for (int py = 0; py < Q; ++py) {
-                    e1 += tb.S[py][a1] * sB[((0 * 5 + c) * P + pl) * Q * N + py * N + a0] +
-                          tb.D[py][a1] * sB[((1 * 5 + c) * P + pl) * Q * N + py * N + a0];
-                    e2 += tb.S[py][a1] * sB[((2 * 5 + c) * P + pl) * Q * N + py * N + a0];
+                    e1 += lt.S[py][a1] * sB[((0 * 5 + c) * P + pl) * Q * N + py * N + a0] +
+                          lt.D[py][a1] * sB[((1 * 5 + c) * P + pl) * Q * N + py * N + a0];
+                    e2 += lt.S[py][a1] * sB[((2 * 5 + c) * P + pl) * Q * N + py * N + a0];
                 }
                 sE[((0 * 5 + c) * P + pl) * N2 + a1 * N + a0] = e1;
                 sE[((1 * 5 + c) * P + pl) * N2 + a1 * N + a0] = e2;
@@ -497,16 +502,16 @@ dg_adjoint_kernel(OpArgs a, const double* Rb, KTab<N, Q, double> tb, MTab<N, dou
                 for (int pl = 0; pl < P; ++pl) {
                     const int pz = pz0 + pl;
                     if (pz < Q)
-                        acc += tb.S[pz][a2] * sE[((0 * 5 + c) * P + pl) * N2 + r2] +
-                               tb.D[pz][a2] * sE[((1 * 5 + c) * P + pl) * N2 + r2];
+                        acc += lt.S[pz][a2] * sE[((0 * 5 + c) * P + pl) * N2 + r2] +
+                               lt.D[pz][a2] * sE[((1 * 5 + c) * P + pl) * N2 + r2];
                 }
                 sUb[it] += acc;
             }
             __syncthreads();
         }
 
-        adj_face_group<N, Q, GEN>(a, Rb, tb, ph, conv, visc, 0, fi, sTau, sFn, Ji, detJ, sX, sUb, sW);
-        adj_face_group<N, Q, GEN>(a, Rb, tb, ph, conv, visc, 1, fi, sTau, sFn, Ji, detJ, sX, sUb, sW);
+        adj_face_group<N, Q, GEN>(a, Rb, lt, ph, conv, visc, 0, fi, sTau, sFn, Ji, detJ, sX, sUb, sW);
+        adj_face_group<N, Q, GEN>(a, Rb, lt, ph, conv, visc, 1, fi, sTau, sFn, Ji, detJ, sX, sUb, sW);
     }
 
     // body force: R_i += sum_m w|J| phi_i (0, f, f.u); only f.u depends on U
@@ -515,22 +520,22 @@ dg_adjoint_kernel(OpArgs a, const double* Rb, KTab<N, Q, double> tb, MTab<N, dou
         Real* t0b = sW;
         Real* t1b = sW + 5 * N3;
         // U and Rbar at the mass points (fields 0..4 of sX: U, fields 5..9: Rbar)
-        sweep_nn<N, Real, false>(mt.Sm, sX, t0b, 0);
+        sweep_nn<N, Real, false>(lm.Sm, sX, t0b, 0);
         __syncthreads();
-        sweep_nn<N, Real, false>(mt.Sm, t0b, t1b, 1);
+        sweep_nn<N, Real, false>(lm.Sm, t0b, t1b, 1);
         __syncthreads();
-        sweep_nn<N, Real, false>(mt.Sm, t1b, t0b, 2);
+        sweep_nn<N, Real, false>(lm.Sm, t1b, t0b, 2);
         __syncthreads();
         Real* rb = t1b;   // Rbar_4 at the mass points (only the energy row of F_rhs depends on U)
-        sweep_nn<N, Real, false>(mt.Sm, sX + 5 * N3, t1b + 5 * N3, 0);
+        sweep_nn<N, Real, false>(lm.Sm, sX + 5 * N3, t1b + 5 * N3, 0);
         __syncthreads();
-        sweep_nn<N, Real, false>(mt.Sm, t1b + 5 * N3, rb, 1);
+        sweep_nn<N, Real, false>(lm.Sm, t1b + 5 * N3, rb, 1);
         __syncthreads();
-        sweep_nn<N, Real, false>(mt.Sm, rb, t1b + 5 * N3, 2);
+        sweep_nn<N, Real, false>(lm.Sm, rb, t1b + 5 * N3, 2);
         __syncthreads();
         const double* jxw_m = GEN ? a.mass_jxw + e * N3 : nullptr;
         for (int p = tid; p < N3; p += nth) {
-            const Real jxw = GEN ? jxw_m[p] : detJ * mt.wm[p % N] * mt.wm[(p / N) % N] * mt.wm[p / N2];
+            const Real jxw = GEN ? jxw_m[p] : detJ * lm.wm[p % N] * lm.wm[(p / N) % N] * lm.wm[p / N2];
             const Real rho = t0b[p];
             const Real fu = (a.force[0] * t0b[N3 + p] + a.force[1] * t0b[2 * N3 + p] + a.force[2] * t0b[3 * N3 + p]) / rho;
             const Real g = jxw * t1b[5 * N3 + 4 * N3 + p];    // cotangent of f.u
@@ -541,11 +546,11 @@ dg_adjoint_kernel(OpArgs a, const double* Rb, KTab<N, Q, double> tb, MTab<N, dou
             t0b[4 * N3 + p] = 0;
         }
         __syncthreads();
-        sweep_nn<N, Real, true>(mt.Sm, t0b, t1b, 0);
+        sweep_nn<N, Real, true>(lm.Sm, t0b, t1b, 0);
         __syncthreads();
-        sweep_nn<N, Real, true>(mt.Sm, t1b, t0b, 1);
+        sweep_nn<N, Real, true>(lm.Sm, t1b, t0b, 1);
         __syncthreads();
-        sweep_nn<N, Real, true>(mt.Sm, t0b, t1b, 2);
+        sweep_nn<N, Real, true>(lm.Sm, t0b, t1b, 2);
         __syncthreads();
         for (int i = tid; i < 5 * N3; i += nth) sUb[i] += t1b[i];
         __syncthreads();
