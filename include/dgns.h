@@ -140,7 +140,7 @@ int dgns_rk_step(dgns_ctx* ctx, double* U, double* work, double t, double dt);
 int dgns_compute_dt(const dgns_ctx* ctx, double Cr, double D, double e, double f,
                     double umax, double mach, double* dt);
 
-/* Diagnostics of Sec. 5.2.2 computed on the device, returned to the host
+/* Diagnostics of Sec. 5.2.3 computed on the device, returned to the host
  * (synchronises the stream):
  *   out8[0] = e_k = 1/V int |u|^2/2,      out8[1] = eps = nu/V int grad u : grad u,
  *   out8[2] = -de_k/dt = -1/V int u.(L_m - u L_rho)/rho   (NaN if L is NULL),

@@ -17,7 +17,7 @@ Modules
     physics      pointwise fluxes and constitutive laws (Sec. 2.1)
     operator     the DG residual, inverse mass matrix and L(U) (Sec. 2.2.2, 2.2.3, 2.4)
     timeint      explicit low-storage Runge-Kutta and the time-step formula (Sec. 2.4)
-    diagnostics  kinetic energy, dissipation, conserved totals (Sec. 5.2.2)
+    diagnostics  kinetic energy, dissipation, conserved totals (Sec. 5.2.3)
     initial      Taylor-Green and channel initial states, L2 projection (Sec. 5.2.1, 5.3.1)
 
 The state-dependent parts use plain PyTorch CPU ops in float64 so that

@@ -2,7 +2,7 @@
 
 Oracle (test infrastructure only).
 
-Paper Sec. 5.2.2: computed as for the incompressible case,
+Paper Sec. 5.2.3: computed as for the incompressible case,
     e_k = 1/V int 1/2 u.u,   eps = nu/V int grad u : grad u,
     eps_num = -d e_k/dt - eps,
 with u = (rho u)/rho and the element-wise (broken) gradient of u.  The exact

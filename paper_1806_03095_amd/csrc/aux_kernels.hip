@@ -1,6 +1,6 @@
 // Memory-bound and setup kernels around the DG operator: the low-storage
 // Runge-Kutta stage update (paper Sec. 2.4), the kinetic-energy / dissipation
-// diagnostics (Sec. 5.2.2) and the L2 projection of the initial states of
+// diagnostics (Sec. 5.2.3) and the L2 projection of the initial states of
 // Sec. 5.2.1 (Taylor-Green) and Sec. 5.3.1 (channel).
 
 #include "dg_common.h"

@@ -152,7 +152,7 @@ def test_kinetic_energy_gradient_50_steps_against_fd():
     op = taylor_green(3, 16, n_q=6)
     U0 = op.project_ic("taylor_green", [1.0, 1.0, 0.1, 1.0])
     U0 = U0 * (1.0 + 1e-3 * _cuda(torch.as_tensor(synth.normal(tuple(U0.shape), 31))))
-    dt = op.compute_dt(0.4, 0.02, 1.5, 3.0, 1.0, 0.1)
+    dt = op.compute_dt(0.3, 0.02, 1.5, 3.0, 1.0, 0.1)   # about 2/3 of the stability limit
     x = U0.clone().requires_grad_(True)
     K = kinetic_energy(rk_rollout(x, op, 50, dt, ckpt_every=10), op)
     (g,) = torch.autograd.grad(K, x)

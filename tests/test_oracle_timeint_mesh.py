@@ -1,6 +1,6 @@
 """Pins of the time integrator, the time-step formula and the mesh generator.
 
-* Table 3 of the paper (Sec. 5.2.3): all 25 printed step counts follow from
+* Table 3 of the paper (Sec. 5.2.4): all 25 printed step counts follow from
   eq. TimeStepRestrictions_Compressible with Cr=0.5, e=1.5, M=0.1, |u|_max=1,
   t_f=20 and h_min = the cell edge 2 pi / 2^l.
 * Sec. 5.3.1: the channel mesh's printed maximum aspect ratios.
