@@ -82,100 +82,19 @@ __device__ inline double block_sum(double v, double* red) {
     return r;
 }
 
-__global__ void __launch_bounds__(256) diag_cell_kernel(OpArgs a, const Tables1D* __restrict__ tp, const double* L,
-                                                        double* partial, int gen) {
-    const Tables1D& t = *tp;
-    const int N = t.n, Q = t.q, N3 = N * N * N, Q3 = Q * Q * Q;
-    const int64_t e = blockIdx.x;
-    const int64_t cs = a.ncell * N3;
-    __shared__ double red[256];
-    double acc[kDiag];
-    for (int m = 0; m < kDiag; ++m) acc[m] = 0;
-    double Jc[9], detJ = 1;
-    if (!gen) {
-        for (int m = 0; m < 9; ++m) Jc[m] = a.cell_metric[e * 10 + m];
-        detJ = a.cell_metric[e * 10 + 9];
-    }
-    for (int p = threadIdx.x; p < Q3; p += blockDim.x) {
-        const int p0 = p % Q, p1 = (p / Q) % Q, p2 = p / (Q * Q);
-        double U[5] = {0, 0, 0, 0, 0}, Gr[5][3] = {}, Lv[4] = {0, 0, 0, 0};
-        for (int i = 0; i < N3; ++i) {
-            const int a0 = i % N, a1 = (i / N) % N, a2 = i / (N * N);
-            const double v0 = t.S[p0][a0], v1 = t.S[p1][a1], v2 = t.S[p2][a2];
-            const double phi = v0 * v1 * v2;
-            const double g0 = t.D[p0][a0] * v1 * v2, g1 = v0 * t.D[p1][a1] * v2, g2 = v0 * v1 * t.D[p2][a2];
-            for (int c = 0; c < 5; ++c) {
-                const double x = a.U[c * cs + e * N3 + i];
-                U[c] += phi * x;
-                Gr[c][0] += g0 * x;
-                Gr[c][1] += g1 * x;
-                Gr[c][2] += g2 * x;
-            }
-            if (L)
-                for (int c = 0; c < 4; ++c) Lv[c] += phi * L[c * cs + e * N3 + i];
-        }
-        double J[9], jxw;
-        if (gen) {
-            for (int m = 0; m < 9; ++m) J[m] = a.cell_metric[(e * 10 + m) * Q3 + p];
-            jxw = a.cell_metric[(e * 10 + 9) * Q3 + p];
-        } else {
-            for (int m = 0; m < 9; ++m) J[m] = Jc[m];
-            jxw = detJ * t.w[p0] * t.w[p1] * t.w[p2];
-        }
-        const double rinv = 1.0 / U[0];
-        const double u[3] = {U[1] * rinv, U[2] * rinv, U[3] * rinv};
-        double gg = 0;
-        for (int al = 0; al < 3; ++al)
-            for (int j = 0; j < 3; ++j) {
-                double gm = 0, gr = 0;
-                for (int d = 0; d < 3; ++d) {
-                    gm += J[d * 3 + j] * Gr[1 + al][d];
-                    gr += J[d * 3 + j] * Gr[0][d];
-                }
-                const double du = (gm - u[al] * gr) * rinv;
-                gg += du * du;
-            }
-        acc[0] += 0.5 * (u[0] * u[0] + u[1] * u[1] + u[2] * u[2]) * jxw;
-        acc[1] += gg * jxw;
-        if (L) {
-            double r = 0;
-            for (int al = 0; al < 3; ++al) r += u[al] * (Lv[1 + al] - u[al] * Lv[0]) * rinv;
-            acc[2] -= r * jxw;
-        }
-        acc[8] += jxw;
-    }
-    // conserved totals with the mass rule
-    for (int p = threadIdx.x; p < N3; p += blockDim.x) {
-        const int p0 = p % N, p1 = (p / N) % N, p2 = p / (N * N);
-        double U[5] = {0, 0, 0, 0, 0};
-        for (int i = 0; i < N3; ++i) {
-            const int a0 = i % N, a1 = (i / N) % N, a2 = i / (N * N);
-            const double phi = t.Sm[p0][a0] * t.Sm[p1][a1] * t.Sm[p2][a2];
-            for (int c = 0; c < 5; ++c) U[c] += phi * a.U[c * cs + e * N3 + i];
-        }
-        const double jxw = gen ? a.mass_jxw[e * N3 + p] : detJ * t.wm[p0] * t.wm[p1] * t.wm[p2];
-        for (int c = 0; c < 5; ++c) acc[3 + c] += U[c] * jxw;
-    }
-    for (int m = 0; m < kDiag; ++m) {
-        const double s = block_sum(acc[m], red);
-        if (threadIdx.x == 0) partial[e * kDiag + m] = s;
-    }
+// Totals of the per-cell partial sums: workgroup m sums quantity m over all cells in
+// a fixed order (deterministic).
+__global__ void __launch_bounds__(1024) diag_total_kernel(const double* partial, int64_t ncell, double* total) {
+    __shared__ double red[1024];
+    const int m = blockIdx.x;
+    double s = 0;
+    for (int64_t e = threadIdx.x; e < ncell; e += blockDim.x) s += partial[e * kDiag + m];
+    const double r = block_sum(s, red);
+    if (threadIdx.x == 0) total[m] = r;
 }
 
-__global__ void __launch_bounds__(256) diag_total_kernel(const double* partial, int64_t ncell, double* total) {
-    __shared__ double red[256];
-    for (int m = 0; m < kDiag; ++m) {
-        double s = 0;
-        for (int64_t e = threadIdx.x; e < ncell; e += blockDim.x) s += partial[e * kDiag + m];
-        const double r = block_sum(s, red);
-        if (threadIdx.x == 0) total[m] = r;
-    }
-}
-
-int launch_diagnostics(const OpArgs& a, const Tables1D* t_dev, const double* L, double* partial, double* total, bool gen,
-                       hipStream_t st) {
-    hipLaunchKernelGGL(diag_cell_kernel, dim3((unsigned)a.ncell), dim3(256), 0, st, a, t_dev, L, partial, gen ? 1 : 0);
-    hipLaunchKernelGGL(diag_total_kernel, dim3(1), dim3(256), 0, st, partial, a.ncell, total);
+int launch_diag_total(const double* partial, int64_t ncell, double* total, hipStream_t st) {
+    hipLaunchKernelGGL(diag_total_kernel, dim3(kDiag), dim3(1024), 0, st, partial, ncell, total);
     return hipGetLastError() == hipSuccess ? 0 : -1;
 }
 
@@ -311,49 +230,4 @@ int launch_axpby(double* y, const double* x, int64_t n, double a, double b, hipS
 
 // Ubar_i = sum_q w|J| phi_i(x_q) (-|u|^2, u_1, u_2, u_3, 0)/rho: the gradient of
 // K = int |u|^2/2 (n_q rule, u = m/rho) with respect to the coefficients U_i.
-__global__ void __launch_bounds__(256) ke_vjp_kernel(OpArgs a, const Tables1D* __restrict__ tp, double* Ub, int gen) {
-    extern __shared__ double sg[];   // [4][Q^3]
-    const Tables1D& t = *tp;
-    const int N = t.n, Q = t.q, N3 = N * N * N, Q3 = Q * Q * Q;
-    const int64_t e = blockIdx.x;
-    const int64_t cs = a.ncell * N3;
-    for (int p = threadIdx.x; p < Q3; p += blockDim.x) {
-        const int p0 = p % Q, p1 = (p / Q) % Q, p2 = p / (Q * Q);
-        double U[4] = {0, 0, 0, 0};
-        for (int i = 0; i < N3; ++i) {
-            const int a0 = i % N, a1 = (i / N) % N, a2 = i / (N * N);
-            const double phi = t.S[p0][a0] * t.S[p1][a1] * t.S[p2][a2];
-            for (int c = 0; c < 4; ++c) U[c] += phi * a.U[c * cs + e * N3 + i];
-        }
-        const double jxw = gen ? a.cell_metric[(e * 10 + 9) * Q3 + p] : a.cell_metric[e * 10 + 9] * t.w[p0] * t.w[p1] * t.w[p2];
-        // |u|^2/2 = |m|^2/(2 rho^2):  d/dm = u/rho,  d/drho = -|u|^2/rho
-        const double r = 1.0 / U[0];
-        const double u0 = U[1] * r, u1 = U[2] * r, u2 = U[3] * r;
-        const double wr = jxw * r;
-        sg[p] = -(u0 * u0 + u1 * u1 + u2 * u2) * wr;
-        sg[Q3 + p] = u0 * wr;
-        sg[2 * Q3 + p] = u1 * wr;
-        sg[3 * Q3 + p] = u2 * wr;
-    }
-    __syncthreads();
-    for (int it = threadIdx.x; it < 5 * N3; it += blockDim.x) {
-        const int c = it / N3, i = it % N3;
-        double s = 0;
-        if (c < 4) {
-            const int a0 = i % N, a1 = (i / N) % N, a2 = i / (N * N);
-            for (int p = 0; p < Q3; ++p) {
-                const int p0 = p % Q, p1 = (p / Q) % Q, p2 = p / (Q * Q);
-                s += t.S[p0][a0] * t.S[p1][a1] * t.S[p2][a2] * sg[c * Q3 + p];
-            }
-        }
-        Ub[c * cs + e * N3 + i] = s;
-    }
-}
-
-int launch_kinetic_energy_vjp(const OpArgs& a, const Tables1D* t_dev, int q, double* Ubar, bool gen, hipStream_t st) {
-    const size_t shm = sizeof(double) * 4 * q * q * q;
-    hipLaunchKernelGGL(ke_vjp_kernel, dim3((unsigned)a.ncell), dim3(256), shm, st, a, t_dev, Ubar, gen ? 1 : 0);
-    return hipGetLastError() == hipSuccess ? 0 : -1;
-}
-
 }  // namespace dgns

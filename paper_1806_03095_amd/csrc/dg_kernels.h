@@ -44,9 +44,17 @@ constexpr int kSupported[][2] = {{1, 2}, {1, 3}, {2, 3}, {2, 4}, {3, 4}, {3, 5},
 // LSRK stage update dU <- A dU + dt L; U <- U + B dU (A == 0: dU <- dt L).
 int launch_rk_update(double* U, double* dU, const double* L, int64_t n, double A, double B, double dt, hipStream_t st);
 
-// Per-cell diagnostic partial sums and their deterministic total.
-int launch_diagnostics(const OpArgs& a, const Tables1D* t_dev, const double* L, double* partial, double* total,
-                       bool gen, hipStream_t st);
+// Per-cell diagnostic partial sums (nine per cell, see diag_impl.h), float64.
+int launch_diagnostics_k1(const OpArgs& a, const Tables1D& t, const double* L, double* partial, bool gen, hipStream_t st);
+int launch_diagnostics_k2(const OpArgs& a, const Tables1D& t, const double* L, double* partial, bool gen, hipStream_t st);
+int launch_diagnostics_k3(const OpArgs& a, const Tables1D& t, const double* L, double* partial, bool gen, hipStream_t st);
+int launch_diagnostics_k4(const OpArgs& a, const Tables1D& t, const double* L, double* partial, bool gen, hipStream_t st);
+int launch_diagnostics_k5(const OpArgs& a, const Tables1D& t, const double* L, double* partial, bool gen, hipStream_t st);
+int launch_diagnostics_k6(const OpArgs& a, const Tables1D& t, const double* L, double* partial, bool gen, hipStream_t st);
+int launch_diagnostics_k7(const OpArgs& a, const Tables1D& t, const double* L, double* partial, bool gen, hipStream_t st);
+
+// Deterministic totals of the nine per-cell partial sums.
+int launch_diag_total(const double* partial, int64_t ncell, double* total, hipStream_t st);
 
 // L2 projection right-hand side of an analytic initial state, U_rhs = (phi_i, U0).
 int launch_ic_rhs(const OpArgs& a, const Tables1D& t, const Tables1D* t_dev, const double* geo_nodes, int ic,
@@ -55,8 +63,14 @@ int launch_ic_rhs(const OpArgs& a, const Tables1D& t, const Tables1D* t_dev, con
 // y <- a y + b x (n doubles).
 int launch_axpby(double* y, const double* x, int64_t n, double a, double b, hipStream_t st);
 
-// Ubar = gradient of int |u|^2/2 (n_q rule) with respect to U.
-int launch_kinetic_energy_vjp(const OpArgs& a, const Tables1D* t_dev, int q, double* Ubar, bool gen, hipStream_t st);
+// Ubar = gradient of int |u|^2/2 (n_q rule) with respect to U, float64.
+int launch_ke_vjp_k1(const OpArgs& a, const Tables1D& t, double* Ub, bool gen, hipStream_t st);
+int launch_ke_vjp_k2(const OpArgs& a, const Tables1D& t, double* Ub, bool gen, hipStream_t st);
+int launch_ke_vjp_k3(const OpArgs& a, const Tables1D& t, double* Ub, bool gen, hipStream_t st);
+int launch_ke_vjp_k4(const OpArgs& a, const Tables1D& t, double* Ub, bool gen, hipStream_t st);
+int launch_ke_vjp_k5(const OpArgs& a, const Tables1D& t, double* Ub, bool gen, hipStream_t st);
+int launch_ke_vjp_k6(const OpArgs& a, const Tables1D& t, double* Ub, bool gen, hipStream_t st);
+int launch_ke_vjp_k7(const OpArgs& a, const Tables1D& t, double* Ub, bool gen, hipStream_t st);
 
 // y <- v (n doubles), a kernel rather than a memset so that it may be captured in graphs.
 int launch_fill(double* y, int64_t n, double v, hipStream_t st);

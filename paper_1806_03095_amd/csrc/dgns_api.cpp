@@ -151,6 +151,40 @@ int dispatch_minv(const dgns_ctx* c, const double* R, double* L) {
     return 0;
 }
 
+// Per-cell diagnostic partial sums into c->d_partial, then their totals into c->d_total.
+int dispatch_diagnostics(const dgns_ctx* c, const OpArgs& a, const double* L) {
+    int rc = 1;
+    switch (c->k) {
+        case 1: rc = launch_diagnostics_k1(a, c->tab, L, c->d_partial, c->gen, c->stream); break;
+        case 2: rc = launch_diagnostics_k2(a, c->tab, L, c->d_partial, c->gen, c->stream); break;
+        case 3: rc = launch_diagnostics_k3(a, c->tab, L, c->d_partial, c->gen, c->stream); break;
+        case 4: rc = launch_diagnostics_k4(a, c->tab, L, c->d_partial, c->gen, c->stream); break;
+        case 5: rc = launch_diagnostics_k5(a, c->tab, L, c->d_partial, c->gen, c->stream); break;
+        case 6: rc = launch_diagnostics_k6(a, c->tab, L, c->d_partial, c->gen, c->stream); break;
+        case 7: rc = launch_diagnostics_k7(a, c->tab, L, c->d_partial, c->gen, c->stream); break;
+    }
+    if (rc == 0) rc = launch_diag_total(c->d_partial, c->ncell, c->d_total, c->stream);
+    if (rc == 1) return fail(DGNS_EUNSUPPORTED, "no diagnostics kernel for degree %d, n_q %d", c->k, c->q);
+    if (rc != 0) return fail(DGNS_EHIP, "diagnostics launch failed");
+    return 0;
+}
+
+int dispatch_ke_vjp(const dgns_ctx* c, const OpArgs& a, double* Ub) {
+    int rc = 1;
+    switch (c->k) {
+        case 1: rc = launch_ke_vjp_k1(a, c->tab, Ub, c->gen, c->stream); break;
+        case 2: rc = launch_ke_vjp_k2(a, c->tab, Ub, c->gen, c->stream); break;
+        case 3: rc = launch_ke_vjp_k3(a, c->tab, Ub, c->gen, c->stream); break;
+        case 4: rc = launch_ke_vjp_k4(a, c->tab, Ub, c->gen, c->stream); break;
+        case 5: rc = launch_ke_vjp_k5(a, c->tab, Ub, c->gen, c->stream); break;
+        case 6: rc = launch_ke_vjp_k6(a, c->tab, Ub, c->gen, c->stream); break;
+        case 7: rc = launch_ke_vjp_k7(a, c->tab, Ub, c->gen, c->stream); break;
+    }
+    if (rc == 1) return fail(DGNS_EUNSUPPORTED, "no kinetic-energy kernel for degree %d, n_q %d", c->k, c->q);
+    if (rc != 0) return fail(DGNS_EHIP, "kinetic energy VJP launch failed");
+    return 0;
+}
+
 int dispatch_adjoint(const dgns_ctx* c, const OpArgs& a, const double* Rb) {
     if (c->fp32) return fail(DGNS_EUNSUPPORTED, "the adjoint is float64 only");
     int rc = 1;
@@ -335,8 +369,8 @@ int dgns_compute_dt(const dgns_ctx* c, double Cr, double D, double e, double f, 
 int dgns_diagnostics(dgns_ctx* c, const double* U, const double* L, double* out8) {
     if (!c || !U || !out8) return fail(DGNS_EINVAL, "null argument");
     OpArgs a = make_args(c, U, nullptr, 0, 0);
-    if (launch_diagnostics(a, c->d_tab, L, c->d_partial, c->d_total, c->gen, c->stream) != 0)
-        return fail(DGNS_EHIP, "diagnostics launch failed");
+    int rc = dispatch_diagnostics(c, a, L);
+    if (rc) return rc;
     double tot[9];
     HIP_TRY(hipMemcpyAsync(tot, c->d_total, sizeof tot, hipMemcpyDeviceToHost, c->stream));
     HIP_TRY(hipStreamSynchronize(c->stream));
@@ -433,8 +467,8 @@ int dgns_rk_step_vjp(dgns_ctx* c, const double* U_n, double t, double dt, const 
 int dgns_kinetic_energy(dgns_ctx* c, const double* U, double* ke) {
     if (!c || !U || !ke) return fail(DGNS_EINVAL, "null argument");
     OpArgs a = make_args(c, U, nullptr, 0, 0);
-    if (launch_diagnostics(a, c->d_tab, nullptr, c->d_partial, c->d_total, c->gen, c->stream) != 0)
-        return fail(DGNS_EHIP, "diagnostics launch failed");
+    int rc = dispatch_diagnostics(c, a, nullptr);
+    if (rc) return rc;
     double tot[9];
     HIP_TRY(hipMemcpyAsync(tot, c->d_total, sizeof tot, hipMemcpyDeviceToHost, c->stream));
     HIP_TRY(hipStreamSynchronize(c->stream));
@@ -446,10 +480,7 @@ int dgns_kinetic_energy(dgns_ctx* c, const double* U, double* ke) {
 int dgns_kinetic_energy_vjp(dgns_ctx* c, const double* U, double* Ubar) {
     if (!c || !U || !Ubar) return fail(DGNS_EINVAL, "null argument");
     if (overlap(U, c->ndof, Ubar, c->ndof)) return fail(DGNS_EINVAL, "U and Ubar overlap");
-    OpArgs a = make_args(c, U, nullptr, 0, 0);
-    if (launch_kinetic_energy_vjp(a, c->d_tab, c->q, Ubar, c->gen, c->stream) != 0)
-        return fail(DGNS_EHIP, "kinetic energy VJP launch failed");
-    return DGNS_OK;
+    return dispatch_ke_vjp(c, make_args(c, U, nullptr, 0, 0), Ubar);
 }
 
 int dgns_project_ic(dgns_ctx* c, int ic, const double* icp, const double* noise, double* U) {

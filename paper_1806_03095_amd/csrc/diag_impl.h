@@ -1,0 +1,332 @@
+// Diagnostics of the Taylor-Green and channel runs (Sec. 5.2.3) and the gradient of
+// the kinetic energy, evaluated per cell with sum factorisation (Sec. 2.3), float64.
+//
+// diag_kernel, one workgroup per cell, writes the cell's nine partial sums
+//   [0] int |u|^2/2            [1] int grad u : grad u      [2] -int u.(L_m - u L_rho)/rho
+//   [3..7] int U_c (k+1 rule)  [8] cell volume (n_q rule)
+// with u = m/rho and the broken (cell-wise) gradient at the n_q^3 Gauss points.  The
+// values and reference gradients of rho and m (and the values of L_rho, L_m) come from
+// the same z / y / x sweeps as the operator's cell term, processed in chunks of P
+// planes; the totals use the mass-point interpolation of the inverse mass matrix.
+//
+// ke_vjp_kernel writes Ubar = dK/dU for K = int |u|^2/2: the point values
+// g = (-|u|^2/rho, u/rho) w|J| are tested against the basis functions by the
+// transposed sweeps.
+#pragma once
+
+#include "op_impl.h"
+
+namespace dgns {
+
+constexpr int kDiagSums = 9;
+
+template <int N, int Q>
+struct DiagSizes {
+    static constexpr int N2 = N * N, N3 = N2 * N, Q2 = Q * Q;
+    static constexpr int P = Q2 >= 128 ? 1 : (128 / Q2 < Q ? 128 / Q2 : Q);   // planes per chunk
+    static constexpr int Z = 12 * Q * N2;     // Z0 [8][Q][N^2] (rho, m, L_rho, L_m), Z1 [4][Q][N^2]
+    static constexpr int Y = 16 * P * Q * N;  // Y00 [8][P][Q][N], Y10 [4][P][Q][N], Y01 [4][P][Q][N]
+    static constexpr int WORK = CMax<Z + Y, 10 * N3>::v;
+};
+
+// Deterministic sum of M per-thread values over the workgroup (fixed tree order).
+template <int M>
+__device__ __forceinline__ void block_sums(double (&v)[M], double* red) {
+    const int tid = threadIdx.x, nth = blockDim.x;
+#pragma unroll
+    for (int m = 0; m < M; ++m) red[m * nth + tid] = v[m];
+    __syncthreads();
+    for (int s = nth / 2; s > 0; s >>= 1) {
+        if (tid < s)
+#pragma unroll
+            for (int m = 0; m < M; ++m) red[m * nth + tid] += red[m * nth + tid + s];
+        __syncthreads();
+    }
+#pragma unroll
+    for (int m = 0; m < M; ++m) v[m] = red[m * nth];
+    __syncthreads();
+}
+
+constexpr int kDiagBlock = 128;
+
+template <int N, int Q, bool GEN>
+__global__ void __launch_bounds__(kDiagBlock)
+diag_kernel(OpArgs a, const double* L, double* partial, KTab<N, Q, double> tb, MTab<N, double> mt) {
+    using DS = DiagSizes<N, Q>;
+    constexpr int N2 = N * N, N3 = N2 * N, Q2 = Q * Q, Q3 = Q2 * Q, P = DS::P;
+    __shared__ double sX[9 * N3];    // U (5 components), then L_rho, L_m (4)
+    __shared__ double sW[DS::WORK];
+    __shared__ double red[kDiagSums * kDiagBlock];
+    __shared__ KTab<N, Q, double> lt;
+    __shared__ MTab<N, double> lm;
+    const int64_t e = blockIdx.x;
+    const int tid = threadIdx.x, nth = blockDim.x;
+    const int64_t cs = a.ncell * N3;
+    for (int i = tid; i < 9 * N3; i += nth) {
+        const int c = i / N3, j = i % N3;
+        double v = 0;
+        if (c < 5) v = a.U[c * cs + e * N3 + j];
+        else if (L) v = L[(c - 5) * cs + e * N3 + j];
+        sX[i] = v;
+    }
+    copy_table<KTab<N, Q, double>, double>(tb, lt);
+    copy_table<MTab<N, double>, double>(mt, lm);
+    double Jc[9], detJ = 1;
+    if constexpr (!GEN) {
+#pragma unroll
+        for (int m = 0; m < 9; ++m) Jc[m] = a.cell_metric[e * 10 + m];
+        detJ = a.cell_metric[e * 10 + 9];
+    }
+    double acc[kDiagSums];
+#pragma unroll
+    for (int m = 0; m < kDiagSums; ++m) acc[m] = 0;
+    __syncthreads();
+
+    // the 8 interpolated components: rho, m (sX 0..3) and L_rho, L_m (sX 5..8)
+    double* Z = sW;
+    double* Yb = sW + DS::Z;
+    // z-sweep: Z0[c] = S_z X_c (c < 8), Z1[c] = D_z X_c (c < 4)      layout [c][pz][a1 a0]
+    for (int it = tid; it < 8 * N2; it += nth) {
+        const int c = it / N2, r = it % N2, src = c < 4 ? c : c + 1;
+        double v[N];
+#pragma unroll
+        for (int i = 0; i < N; ++i) v[i] = sX[src * N3 + i * N2 + r];
+#pragma unroll
+        for (int pz = 0; pz < Q; ++pz) {
+            double z0 = 0, z1 = 0;
+#pragma unroll
+            for (int i = 0; i < N; ++i) {
+                z0 += lt.S[pz][i] * v[i];
+                z1 += lt.D[pz][i] * v[i];
+            }
+            Z[(c * Q + pz) * N2 + r] = z0;
+            if (c < 4) Z[((8 + c) * Q + pz) * N2 + r] = z1;
+        }
+    }
+    __syncthreads();
+
+    for (int pz0 = 0; pz0 < Q; pz0 += P) {
+        // y-sweep of P planes: Y00 = S_y Z0 (8), Y10 = D_y Z0 (4), Y01 = S_y Z1 (4)   layout [kind c][pl][py][a0]
+        for (int it = tid; it < 8 * P * N; it += nth) {
+            const int a0 = it % N, pl = (it / N) % P, c = it / (N * P), pz = pz0 + pl;
+            if (pz >= Q) continue;
+            double z0[N], z1[N];
+#pragma unroll
+            for (int i = 0; i < N; ++i) {
+                z0[i] = Z[(c * Q + pz) * N2 + i * N + a0];
+                z1[i] = c < 4 ? Z[((8 + c) * Q + pz) * N2 + i * N + a0] : 0.0;
+            }
+#pragma unroll
+            for (int py = 0; py < Q; ++py) {
+                double y00 = 0, y10 = 0, y01 = 0;
+#pragma unroll
+                for (int i = 0; i < N; ++i) {
+                    y00 += lt.S[py][i] * z0[i];
+                    y10 += lt.D[py][i] * z0[i];
+                    y01 += lt.S[py][i] * z1[i];
+                }
+                Yb[((c * P + pl) * Q + py) * N + a0] = y00;
+                if (c < 4) {
+                    Yb[(((8 + c) * P + pl) * Q + py) * N + a0] = y10;
+                    Yb[(((12 + c) * P + pl) * Q + py) * N + a0] = y01;
+                }
+            }
+        }
+        __syncthreads();
+        // points of the chunk: x contraction and the integrands
+        for (int it = tid; it < P * Q2; it += nth) {
+            const int px = it % Q, py = (it / Q) % Q, pl = it / Q2, pz = pz0 + pl;
+            if (pz >= Q) continue;
+            double v[8], g[4][3];
+#pragma unroll
+            for (int c = 0; c < 8; ++c) {
+                double s = 0, dx = 0, dy = 0, dz = 0;
+#pragma unroll
+                for (int i = 0; i < N; ++i) {
+                    const double y00 = Yb[((c * P + pl) * Q + py) * N + i];
+                    s += lt.S[px][i] * y00;
+                    if (c < 4) {
+                        dx += lt.D[px][i] * y00;
+                        dy += lt.S[px][i] * Yb[(((8 + c) * P + pl) * Q + py) * N + i];
+                        dz += lt.S[px][i] * Yb[(((12 + c) * P + pl) * Q + py) * N + i];
+                    }
+                }
+                v[c] = s;
+                if (c < 4) {
+                    g[c][0] = dx;
+                    g[c][1] = dy;
+                    g[c][2] = dz;
+                }
+            }
+            double J[9], jxw;
+            if constexpr (GEN) {
+                const int p = px + Q * (py + Q * pz);
+                const double* gm = a.cell_metric + e * 10 * Q3 + p;
+#pragma unroll
+                for (int m = 0; m < 9; ++m) J[m] = gm[m * Q3];
+                jxw = gm[9 * Q3];
+            } else {
+#pragma unroll
+                for (int m = 0; m < 9; ++m) J[m] = Jc[m];
+                jxw = detJ * lt.w[px] * lt.w[py] * lt.w[pz];
+            }
+            const double rinv = 1.0 / v[0];
+            const double u[3] = {v[1] * rinv, v[2] * rinv, v[3] * rinv};
+            double gg = 0;
+#pragma unroll
+            for (int al = 0; al < 3; ++al)
+#pragma unroll
+                for (int j = 0; j < 3; ++j) {
+                    double gm_ = 0, gr = 0;
+#pragma unroll
+                    for (int d = 0; d < 3; ++d) {
+                        gm_ += J[d * 3 + j] * g[1 + al][d];
+                        gr += J[d * 3 + j] * g[0][d];
+                    }
+                    const double du = (gm_ - u[al] * gr) * rinv;
+                    gg += du * du;
+                }
+            acc[0] += 0.5 * (u[0] * u[0] + u[1] * u[1] + u[2] * u[2]) * jxw;
+            acc[1] += gg * jxw;
+            if (L) {
+                double r = 0;
+#pragma unroll
+                for (int al = 0; al < 3; ++al) r += u[al] * (v[5 + al] - u[al] * v[4]) * rinv;
+                acc[2] -= r * jxw;
+            }
+            acc[8] += jxw;
+        }
+        __syncthreads();
+    }
+
+    // conserved totals with the k+1 rule: values at the mass points, times |J| w
+    double* t0 = sW;
+    double* t1 = sW + 5 * N3;
+    sweep_nn<N, double, false>(lm.Sm, sX, t0, 0);
+    __syncthreads();
+    sweep_nn<N, double, false>(lm.Sm, t0, t1, 1);
+    __syncthreads();
+    sweep_nn<N, double, false>(lm.Sm, t1, t0, 2);
+    __syncthreads();
+    for (int p = tid; p < N3; p += nth) {
+        double jxw;
+        if constexpr (GEN) jxw = a.mass_jxw[e * N3 + p];
+        else jxw = detJ * lm.wm[p % N] * lm.wm[(p / N) % N] * lm.wm[p / N2];
+#pragma unroll
+        for (int c = 0; c < 5; ++c) acc[3 + c] += t0[c * N3 + p] * jxw;
+    }
+    block_sums<kDiagSums>(acc, red);
+    if (tid < kDiagSums) {
+        double s = 0;
+#pragma unroll
+        for (int m = 0; m < kDiagSums; ++m)
+            if (m == tid) s = acc[m];
+        partial[e * kDiagSums + tid] = s;
+    }
+}
+
+template <int N, int Q, bool GEN>
+__global__ void __launch_bounds__(kDiagBlock)
+ke_vjp_kernel(OpArgs a, double* Ub, KTab<N, Q, double> tb) {
+    constexpr int N2 = N * N, N3 = N2 * N, Q2 = Q * Q, Q3 = Q2 * Q;
+    // values of rho, m at all n_q^3 points: X -> Z [4][Q][N^2] -> Y [4][Q][Q][N] -> G [4][Q^3]
+    constexpr int SZ = 4 * Q * N2, SY = 4 * Q2 * N, SG = 4 * Q3;
+    __shared__ double sX[4 * N3];
+    __shared__ double sA[CMax<SZ, SG>::v];
+    __shared__ double sB[CMax<SY, 4 * N2 * Q>::v];
+    __shared__ KTab<N, Q, double> lt;
+    const int64_t e = blockIdx.x;
+    const int tid = threadIdx.x, nth = blockDim.x;
+    const int64_t cs = a.ncell * N3;
+    for (int i = tid; i < 4 * N3; i += nth) sX[i] = a.U[(i / N3) * cs + e * N3 + i % N3];
+    copy_table<KTab<N, Q, double>, double>(tb, lt);
+    __syncthreads();
+    // forward: Z = S_z X, Y = S_y Z, G = S_x Y
+    for (int it = tid; it < 4 * N2; it += nth) {
+        const int c = it / N2, r = it % N2;
+        for (int pz = 0; pz < Q; ++pz) {
+            double s = 0;
+#pragma unroll
+            for (int i = 0; i < N; ++i) s += lt.S[pz][i] * sX[c * N3 + i * N2 + r];
+            sA[(c * Q + pz) * N2 + r] = s;
+        }
+    }
+    __syncthreads();
+    for (int it = tid; it < 4 * Q * N; it += nth) {
+        const int a0 = it % N, pz = (it / N) % Q, c = it / (N * Q);
+        for (int py = 0; py < Q; ++py) {
+            double s = 0;
+#pragma unroll
+            for (int i = 0; i < N; ++i) s += lt.S[py][i] * sA[(c * Q + pz) * N2 + i * N + a0];
+            sB[((c * Q + pz) * Q + py) * N + a0] = s;
+        }
+    }
+    __syncthreads();
+    // point values and the integrand's derivative g = d(|u|^2/2)/d(rho, m) w|J|
+    for (int p = tid; p < Q3; p += nth) {
+        const int px = p % Q, py = (p / Q) % Q, pz = p / Q2;
+        double v[4];
+#pragma unroll
+        for (int c = 0; c < 4; ++c) {
+            double s = 0;
+#pragma unroll
+            for (int i = 0; i < N; ++i) s += lt.S[px][i] * sB[((c * Q + pz) * Q + py) * N + i];
+            v[c] = s;
+        }
+        double jxw;
+        if constexpr (GEN) jxw = a.cell_metric[(e * 10 + 9) * Q3 + p];
+        else jxw = a.cell_metric[e * 10 + 9] * lt.w[px] * lt.w[py] * lt.w[pz];
+        const double r = 1.0 / v[0];
+        const double u0 = v[1] * r, u1 = v[2] * r, u2 = v[3] * r;
+        const double wr = jxw * r;
+        // |u|^2/2 = |m|^2 / (2 rho^2): d/dm = u / rho, d/drho = -|u|^2 / rho
+        sA[p] = -(u0 * u0 + u1 * u1 + u2 * u2) * wr;
+        sA[Q3 + p] = u0 * wr;
+        sA[2 * Q3 + p] = u1 * wr;
+        sA[3 * Q3 + p] = u2 * wr;
+    }
+    __syncthreads();
+    // transposed: Bx = S_x^T G [4][pz][py][a0], By = S_y^T Bx [4][pz][a1][a0], Ub = S_z^T By
+    for (int it = tid; it < 4 * Q2 * N; it += nth) {
+        const int a0 = it % N, py = (it / N) % Q, pz = (it / (N * Q)) % Q, c = it / (N * Q2);
+        double s = 0;
+        for (int px = 0; px < Q; ++px) s += lt.S[px][a0] * sA[c * Q3 + (pz * Q + py) * Q + px];
+        sB[((c * Q + pz) * Q + py) * N + a0] = s;
+    }
+    __syncthreads();
+    // By [4][Q][N^2] goes to sA: the point values G are dead
+    for (int it = tid; it < 4 * Q * N2; it += nth) {
+        const int a0 = it % N, a1 = (it / N) % N, pz = (it / N2) % Q, c = it / (N2 * Q);
+        double s = 0;
+        for (int py = 0; py < Q; ++py) s += lt.S[py][a1] * sB[((c * Q + pz) * Q + py) * N + a0];
+        sA[(c * Q + pz) * N2 + a1 * N + a0] = s;
+    }
+    __syncthreads();
+    for (int it = tid; it < 5 * N3; it += nth) {
+        const int c = it / N3, i = it % N3, a2 = i / N2, r = i % N2;
+        double s = 0;
+        if (c < 4)
+            for (int pz = 0; pz < Q; ++pz) s += lt.S[pz][a2] * sA[(c * Q + pz) * N2 + r];
+        Ub[c * cs + e * N3 + i] = s;
+    }
+}
+
+template <int N, int Q, bool GEN>
+inline int launch_diag_t(const OpArgs& a, const Tables1D& t, const double* L, double* partial, hipStream_t st) {
+    KTab<N, Q, double> kt;
+    MTab<N, double> mt;
+    fill_tables<N, Q, double>(t, kt, mt);
+    hipLaunchKernelGGL((diag_kernel<N, Q, GEN>), dim3((unsigned)a.ncell), dim3(kDiagBlock), 0, st, a, L, partial, kt, mt);
+    return hipGetLastError() == hipSuccess ? 0 : -1;
+}
+
+template <int N, int Q, bool GEN>
+inline int launch_ke_vjp_t(const OpArgs& a, const Tables1D& t, double* Ub, hipStream_t st) {
+    KTab<N, Q, double> kt;
+    MTab<N, double> mt;
+    fill_tables<N, Q, double>(t, kt, mt);
+    hipLaunchKernelGGL((ke_vjp_kernel<N, Q, GEN>), dim3((unsigned)a.ncell), dim3(kDiagBlock), 0, st, a, Ub, kt);
+    return hipGetLastError() == hipSuccess ? 0 : -1;
+}
+
+}  // namespace dgns

@@ -1,5 +1,6 @@
 // Operator (and adjoint) kernels of polynomial degree 1: the supported n_q values.
 #include "adj_impl.h"
+#include "diag_impl.h"
 #include "dg_kernels.h"
 
 namespace dgns {
@@ -26,6 +27,22 @@ int launch_adjoint_k1(const OpArgs& a, const double* Rb, const Tables1D& t, bool
     switch (t.q) {
         case 2: return gen ? launch_adjoint_t<2, 2, true>(a, Rb, t, st) : launch_adjoint_t<2, 2, false>(a, Rb, t, st);
         case 3: return gen ? launch_adjoint_t<2, 3, true>(a, Rb, t, st) : launch_adjoint_t<2, 3, false>(a, Rb, t, st);
+        default: return 1;
+    }
+}
+
+int launch_diagnostics_k1(const OpArgs& a, const Tables1D& t, const double* L, double* partial, bool gen, hipStream_t st) {
+    switch (t.q) {
+        case 2: return gen ? launch_diag_t<2, 2, true>(a, t, L, partial, st) : launch_diag_t<2, 2, false>(a, t, L, partial, st);
+        case 3: return gen ? launch_diag_t<2, 3, true>(a, t, L, partial, st) : launch_diag_t<2, 3, false>(a, t, L, partial, st);
+        default: return 1;
+    }
+}
+
+int launch_ke_vjp_k1(const OpArgs& a, const Tables1D& t, double* Ub, bool gen, hipStream_t st) {
+    switch (t.q) {
+        case 2: return gen ? launch_ke_vjp_t<2, 2, true>(a, t, Ub, st) : launch_ke_vjp_t<2, 2, false>(a, t, Ub, st);
+        case 3: return gen ? launch_ke_vjp_t<2, 3, true>(a, t, Ub, st) : launch_ke_vjp_t<2, 3, false>(a, t, Ub, st);
         default: return 1;
     }
 }

@@ -1,5 +1,6 @@
 // Operator (and adjoint) kernels of polynomial degree 4: the supported n_q values.
 #include "adj_impl.h"
+#include "diag_impl.h"
 #include "dg_kernels.h"
 
 namespace dgns {
@@ -29,6 +30,24 @@ int launch_adjoint_k4(const OpArgs& a, const double* Rb, const Tables1D& t, bool
         case 5: return gen ? launch_adjoint_t<5, 5, true>(a, Rb, t, st) : launch_adjoint_t<5, 5, false>(a, Rb, t, st);
         case 6: return gen ? launch_adjoint_t<5, 6, true>(a, Rb, t, st) : launch_adjoint_t<5, 6, false>(a, Rb, t, st);
         case 7: return gen ? launch_adjoint_t<5, 7, true>(a, Rb, t, st) : launch_adjoint_t<5, 7, false>(a, Rb, t, st);
+        default: return 1;
+    }
+}
+
+int launch_diagnostics_k4(const OpArgs& a, const Tables1D& t, const double* L, double* partial, bool gen, hipStream_t st) {
+    switch (t.q) {
+        case 5: return gen ? launch_diag_t<5, 5, true>(a, t, L, partial, st) : launch_diag_t<5, 5, false>(a, t, L, partial, st);
+        case 6: return gen ? launch_diag_t<5, 6, true>(a, t, L, partial, st) : launch_diag_t<5, 6, false>(a, t, L, partial, st);
+        case 7: return gen ? launch_diag_t<5, 7, true>(a, t, L, partial, st) : launch_diag_t<5, 7, false>(a, t, L, partial, st);
+        default: return 1;
+    }
+}
+
+int launch_ke_vjp_k4(const OpArgs& a, const Tables1D& t, double* Ub, bool gen, hipStream_t st) {
+    switch (t.q) {
+        case 5: return gen ? launch_ke_vjp_t<5, 5, true>(a, t, Ub, st) : launch_ke_vjp_t<5, 5, false>(a, t, Ub, st);
+        case 6: return gen ? launch_ke_vjp_t<5, 6, true>(a, t, Ub, st) : launch_ke_vjp_t<5, 6, false>(a, t, Ub, st);
+        case 7: return gen ? launch_ke_vjp_t<5, 7, true>(a, t, Ub, st) : launch_ke_vjp_t<5, 7, false>(a, t, Ub, st);
         default: return 1;
     }
 }

@@ -1,5 +1,6 @@
 // Operator (and adjoint) kernels of polynomial degree 6: the supported n_q values.
 #include "op_impl.h"
+#include "diag_impl.h"
 #include "dg_kernels.h"
 
 namespace dgns {
@@ -24,5 +25,21 @@ int launch_inverse_mass_k6(const double* R, double* L, int64_t ncell, const doub
 
 // The adjoint's LDS work area exceeds one workgroup's 160 KB at this degree.
 int launch_adjoint_k6(const OpArgs&, const double*, const Tables1D&, bool, hipStream_t) { return 1; }
+
+int launch_diagnostics_k6(const OpArgs& a, const Tables1D& t, const double* L, double* partial, bool gen, hipStream_t st) {
+    switch (t.q) {
+        case 7: return gen ? launch_diag_t<7, 7, true>(a, t, L, partial, st) : launch_diag_t<7, 7, false>(a, t, L, partial, st);
+        case 10: return gen ? launch_diag_t<7, 10, true>(a, t, L, partial, st) : launch_diag_t<7, 10, false>(a, t, L, partial, st);
+        default: return 1;
+    }
+}
+
+int launch_ke_vjp_k6(const OpArgs& a, const Tables1D& t, double* Ub, bool gen, hipStream_t st) {
+    switch (t.q) {
+        case 7: return gen ? launch_ke_vjp_t<7, 7, true>(a, t, Ub, st) : launch_ke_vjp_t<7, 7, false>(a, t, Ub, st);
+        case 10: return gen ? launch_ke_vjp_t<7, 10, true>(a, t, Ub, st) : launch_ke_vjp_t<7, 10, false>(a, t, Ub, st);
+        default: return 1;
+    }
+}
 
 }  // namespace dgns
