@@ -8,7 +8,8 @@ be formed.  The state is built by the oracle on the sampled cells and their
 neighbours (L2 projection plus seeded noise) over a uniform background state
 elsewhere; both sides receive the same array.
 
-Workloads: Taylor-Green 32^3 cells k=3 n_q=6 (float64 and float32); stretched
+Workloads: Taylor-Green 32^3 cells k=3 n_q=6 (float64 and float32) and 64^3 (the
+largest mesh, past the last-level cache); stretched
 channel 16^3 cells k=4 n_q=7 with walls and body force; Taylor-Green 16^3 k=7
 n_q=11 and 24^3 k=5 n_q=8 (the precision-study sizes).
 """
@@ -94,6 +95,19 @@ def test_tgv_32cubed_k3_nq6_operator_sampled():
         Rs = R[:, torch.as_tensor(cells, device="cuda"), :].cpu()
         _check_low_mach(Rs, oop.residual(U, cells=cells, terms=terms), "R_%s 32^3 sample" % terms, norm_tol=nt,
                         field_tol=ft)
+
+
+def test_tgv_64cubed_k3_nq6_operator_sampled():
+    # the largest mesh exercised: 262,144 cells, 83.9M DoFs (671 MB per vector), past the
+    # 256 MB last-level cache
+    announce("tgv 64^3 k=3 nq=6 fp64 operator, sampled cells")
+    n = (64, 64, 64)
+    oop, gop = make_pair(n, 3, 6)
+    cells = _sample_cells(n, 48, seed=13)
+    U = _patched_state(oop, cells, _tgv_func(oop, 0.1), _rest_background(oop.fl, 0.1), seed=14, noise=1e-3)
+    got = _gpu_apply_sampled(gop, U, cells)
+    nt, ft = _low_mach_tol(oop, 3)
+    _check_low_mach(got, oop.apply(U, cells=cells), "L 64^3 sample", norm_tol=nt, field_tol=ft)
 
 
 def test_tgv_32cubed_fp32_error_sampled():

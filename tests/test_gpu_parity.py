@@ -96,6 +96,11 @@ CASES = [
     ((2, 2, 2), 5, 8, "affine", 0.0, "LGL"),
     ((2, 1, 2), 7, 11, "affine", 0.0, "LGL"),
     ((1, 2, 2), 7, 11, "curved", 0.1, "LGL"),
+    # degenerate meshes: one cell per direction is its own periodic neighbour
+    ((1, 1, 1), 2, 4, "affine", 0.0, "LGL"),
+    ((1, 1, 1), 3, 6, "curved", 0.1, "GL"),
+    ((1, 1, 3), 1, 2, "affine", 0.0, "LGL"),
+    ((3, 1, 1), 6, 10, "affine", 0.0, "LGL"),
 ]
 
 
