@@ -184,6 +184,39 @@ def adjoint_timing():
             "grad_finite": bool(torch.isfinite(g).all())}
 
 
+def degree_sweep(target_dofs=10_000_000, calls=20):
+    """Operator throughput over every compiled (k, n_q), float64 and float32, on
+    Taylor-Green meshes of about target_dofs DoFs (the mesh size n^3 with n the
+    nearest integer to (target_dofs / (5 (k+1)^3))^(1/3)); also F_c, F_v and M^{-1}
+    separately (the paper's operation breakdown)."""
+    import torch
+    from paper_1806_03095_amd import taylor_green
+    qs = {1: (2, 3), 2: (3, 4), 3: (4, 5, 6), 4: (5, 6, 7), 5: (6, 8), 6: (7, 10), 7: (8, 11)}
+    rows = []
+    for k, nqs in qs.items():
+        ne = max(2, int(round((target_dofs / (5.0 * (k + 1) ** 3)) ** (1.0 / 3.0))))
+        for nq in nqs:
+            row = {"k": k, "n_q": nq, "cells": ne ** 3}
+            for prec in ("fp64", "fp32"):
+                op = taylor_green(k, ne, n_q=nq, precision=prec)
+                U = op.project_ic("taylor_green", [1.0, 1.0, 0.1, 1.0])
+                L = torch.empty_like(U)
+                t = time_call(lambda: op.apply(U, L), calls)
+                row["n_dof"] = op.n_dof
+                row[prec + "_L_dofs_per_s"] = op.n_dof / t
+                if prec == "fp64":
+                    for name, mask in (("F_c", 1), ("F_v", 2)):
+                        tt = time_call(lambda: op.residual(U, L, terms=mask), calls)
+                        row["fp64_%s_dofs_per_s" % name] = op.n_dof / tt
+                    tt = time_call(lambda: op.inverse_mass(U, L), calls)
+                    row["fp64_M_inv_dofs_per_s"] = op.n_dof / tt
+                op.close()
+            log("k=%d n_q=%d %d^3: L fp64 %.3e fp32 %.3e DoF/s" % (k, nq, ne, row["fp64_L_dofs_per_s"],
+                                                                    row["fp32_L_dofs_per_s"]))
+            rows.append(row)
+    return rows
+
+
 def precision_study(steps):
     """Float32 vs float64 operator over `steps` RK steps from the same state, for
     the Taylor-Green 16^3 k=7 n_q=11 and 24^3 k=5 n_q=8 workloads: relative
@@ -269,6 +302,8 @@ def main():
                     help="profiling mode: one device-to-device copy of MIB MiB (HBM counter calibration)")
     ap.add_argument("--no-extras", action="store_true",
                     help="skip the operation breakdown, copy bandwidth and channel figures")
+    ap.add_argument("--sweep", action="store_true",
+                    help="study mode: operator throughput over every compiled (k, n_q); one JSON line")
     ap.add_argument("--precision-study", type=int, default=0, metavar="STEPS",
                     help="study mode: float32 vs float64 over STEPS RK steps (16^3 k=7, 24^3 k=5); one JSON line")
     args = ap.parse_args()
@@ -290,6 +325,9 @@ def main():
         log("copied %d MiB (read %d B, write %d B)" % (args.copy_calibration, 8 * n, 8 * n))
         return
 
+    if args.sweep:
+        print(json.dumps({"degree_sweep": degree_sweep()}), flush=True)
+        return
     if args.precision_study:
         print(json.dumps({"precision_study": precision_study(args.precision_study)}), flush=True)
         return
