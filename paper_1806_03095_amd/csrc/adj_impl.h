@@ -263,7 +263,7 @@ __device__ __forceinline__ void adj_face_group(const OpArgs& a, const double* Rb
         }
     }
     __syncthreads();
-    face_test_accumulate<N, Q, Real>(lt, s, r1, r2, sUb);
+    face_test_accumulate<N, Q, Real>(lt, s, 0, r1, r2, sUb);
 }
 
 template <int N, int Q, bool GEN>

@@ -37,22 +37,22 @@ namespace dgns {
 template <int A, int B>
 struct CMax { static constexpr int v = A > B ? A : B; };
 
-template <int N, int Q, int B>
+template <int N, int Q, int B, int NF = 3>
 struct FaceSizes {
     static constexpr int N2 = N * N, Q2 = Q * Q;
-    // group of three faces
-    static constexpr int TR = 3 * 2 * 2 * 5 * N2;      // traces [f][side][v/n][c][N^2]
-    static constexpr int SW = 3 * 2 * 3 * 5 * N * Q;   // t0 sweep [f][side][3][c][N][Q]
-    static constexpr int OUT = 3 * 4 * 5 * Q2;         // point outputs [f][4][c][Q^2]
-    static constexpr int T1 = 3 * 3 * 5 * N * Q;       // t1-transposed [f][3][c][N][Q]
-    static constexpr int W = 3 * 2 * 5 * N2;           // lifted [f][2][c][N^2]
+    // group of NF faces xi_d = s (NF = 3: all three directions; NF = 1: one face)
+    static constexpr int TR = NF * 2 * 2 * 5 * N2;      // traces [f][side][v/n][c][N^2]
+    static constexpr int SW = NF * 2 * 3 * 5 * N * Q;   // t0 sweep [f][side][3][c][N][Q]
+    static constexpr int OUT = NF * 4 * 5 * Q2;         // point outputs [f][4][c][Q^2]
+    static constexpr int T1 = NF * 3 * 5 * N * Q;       // t1-transposed [f][3][c][N][Q]
+    static constexpr int W = NF * 2 * 5 * N2;           // lifted [f][2][c][N^2]
     // Two regions that alternate between phases: R1 = {SW, T1}, R2 = {TR, OUT, W}.
     static constexpr int R1 = CMax<SW, T1>::v;
     static constexpr int R2 = CMax<CMax<TR, OUT>::v, W>::v;
     static constexpr int SPLIT_TOTAL = R1 + R2;
     // With one face point per thread, OUT can overwrite SW (the point results wait
     // in registers across a barrier): SW | TR, then OUT | T1, then W | T1.
-    static constexpr bool ALIAS = 3 * Q2 <= B;
+    static constexpr bool ALIAS = NF * Q2 <= B;
     static constexpr int TR_OFF = ALIAS ? SW : R1;
     static constexpr int OUT_OFF = ALIAS ? 0 : R1;
     static constexpr int T1_OFF = ALIAS ? OUT : 0;
@@ -77,15 +77,22 @@ struct ChooseP {
     static constexpr int v = fit(Q);
 };
 
-template <int N, int Q, int B>
+// LDS plan of the operator kernel for block size B and RS-byte reals: the work area
+// (largest of the cell chunk, the face group and the mass-matrix sweeps), the number
+// NF of faces per face group (three, or one when three do not leave room for the 1D
+// table copies), and whether the table copies fit.
+template <int N, int Q, int B, int RS>
 struct OpSizes {
+    static constexpr int N3 = N * N * N;
     static constexpr int P = ChooseP<N, Q>::v;
-    static constexpr int WORK = CMax<CMax<CellSizes<N, Q, P>::TOTAL, FaceSizes<N, Q, B>::TOTAL>::v, 10 * N * N * N>::v;
-    // whether the LDS copies of the 1D tables fit beside the work arrays
-    template <typename Real>
-    static constexpr bool lds_tables() {
-        return (WORK + 10 * N * N * N + 2 * Q * N + Q + 4 * N + 2 * N * N + N) * (int)sizeof(Real) + 1024 <= 160 * 1024;
-    }
+    static constexpr int CELL = CellSizes<N, Q, P>::TOTAL;
+    static constexpr int TABLES = 2 * Q * N + Q + 4 * N + 2 * N * N + N;   // KTab + MTab entries
+    static constexpr int W3 = CMax<CMax<CELL, FaceSizes<N, Q, B, 3>::TOTAL>::v, 10 * N3>::v;
+    static constexpr int W1 = CMax<CMax<CELL, FaceSizes<N, Q, B, 1>::TOTAL>::v, 10 * N3>::v;
+    static constexpr bool fits(int work) { return (work + 10 * N3 + TABLES) * RS + 1024 <= 160 * 1024; }
+    static constexpr int NF = fits(W3) ? 3 : 1;
+    static constexpr int WORK = NF == 3 ? W3 : W1;
+    static constexpr bool LDS_TAB = fits(WORK);
 };
 
 // Workgroup size of the operator kernel: 128 threads (two waves) per cell while
@@ -95,9 +102,9 @@ struct OpSizes {
 // it only add spill traffic).
 template <int N, int Q, typename Real>
 struct OpBlock {
-    static constexpr int lds128 =
-        (OpSizes<N, Q, 128>::WORK + 10 * N * N * N + 2 * Q * N + Q + 4 * N + 2 * N * N + N) * (int)sizeof(Real) + 1024;
-    static constexpr int threads = (lds128 <= 40 * 1024 || lds128 > 160 * 1024) ? 128 : 256;
+    using S128 = OpSizes<N, Q, 128, (int)sizeof(Real)>;
+    static constexpr int lds128 = (S128::WORK + 10 * N * N * N + S128::TABLES) * (int)sizeof(Real) + 1024;
+    static constexpr int threads = (lds128 <= 40 * 1024 || !S128::LDS_TAB) ? 128 : 256;
 };
 
 // Applies an N x N matrix M along axis `ax` of the NC arrays src[NC][N^3] ->
@@ -230,14 +237,15 @@ __device__ __forceinline__ void load_face_point_rows(const KTab<N, Q, Real>& tb,
 }
 
 // Test integration of the face-point coefficients r2 [f][val, g_t0, g_t1, g_n][c][q1][q0]
-// of the three faces xi_d = s against the cell's basis functions, accumulated
-// into sR: value part through phi_i, gradient part through grad_xi phi_i.
-template <int N, int Q, typename Real>
-__device__ __forceinline__ void face_test_accumulate(const KTab<N, Q, Real>& tb, int s, Real* r1, Real* r2, Real* sR) {
+// of the NF faces xi_d = s, d = d0 .. d0 + NF - 1, against the cell's basis functions,
+// accumulated into sR: value part through phi_i, gradient part through grad_xi phi_i.
+template <int N, int Q, typename Real, int NF = 3>
+__device__ __forceinline__ void face_test_accumulate(const KTab<N, Q, Real>& tb, int s, int d0, Real* r1, Real* r2,
+                                                     Real* sR) {
     constexpr int N2 = N * N, N3 = N2 * N, Q2 = Q * Q;
     const int tid = threadIdx.x, nth = blockDim.x;
     // transposed along t1: P0 = S^T val + D^T g_t1, P1 = S^T g_t0, Pn = S^T g_n    r1 [f][3][c][b][q0]
-    for (int it = tid; it < 3 * 5 * N * Q; it += nth) {
+    for (int it = tid; it < NF * 5 * N * Q; it += nth) {
         const int q0 = it % Q, ib = (it / Q) % N, c = (it / (Q * N)) % 5, d = it / (5 * Q * N);
         const Real* o = r2 + d * 4 * 5 * Q2 + c * Q2 + q0;
         Real p0 = 0, p1 = 0, pn = 0;
@@ -255,7 +263,7 @@ __device__ __forceinline__ void face_test_accumulate(const KTab<N, Q, Real>& tb,
     __syncthreads();
 
     // transposed along t0: W0 = S^T P0 + D^T P1, W1 = S^T Pn    r2 [f][2][c][b][a]
-    for (int it = tid; it < 3 * 5 * N2; it += nth) {
+    for (int it = tid; it < NF * 5 * N2; it += nth) {
         const int ia = it % N, ib = (it / N) % N, c = (it / N2) % 5, d = it / (5 * N2);
         const Real* t = r1 + d * 3 * 5 * N * Q + c * N * Q + ib * Q;
         Real w0 = 0, w1 = 0;
@@ -275,25 +283,34 @@ __device__ __forceinline__ void face_test_accumulate(const KTab<N, Q, Real>& tb,
         const int c = it / N3, r = it % N3;
         const int x0 = r % N, x1 = (r / N) % N, x2 = r / N2;
         const Real* w = r2 + c * N2;
-        // face d = 0: (a, b, m) = (x1, x2, x0); d = 1: (x0, x2, x1); d = 2: (x0, x1, x2)
-        Real acc = w[0 * 2 * 5 * N2 + x2 * N + x1] * tb.fv[s][x0] + w[(0 * 2 + 1) * 5 * N2 + x2 * N + x1] * tb.fd[s][x0];
-        acc += w[1 * 2 * 5 * N2 + x2 * N + x0] * tb.fv[s][x1] + w[(1 * 2 + 1) * 5 * N2 + x2 * N + x0] * tb.fd[s][x1];
-        acc += w[2 * 2 * 5 * N2 + x1 * N + x0] * tb.fv[s][x2] + w[(2 * 2 + 1) * 5 * N2 + x1 * N + x0] * tb.fd[s][x2];
+        Real acc;
+        if constexpr (NF == 3) {
+            // face d = 0: (a, b, m) = (x1, x2, x0); d = 1: (x0, x2, x1); d = 2: (x0, x1, x2)
+            acc = w[0 * 2 * 5 * N2 + x2 * N + x1] * tb.fv[s][x0] + w[(0 * 2 + 1) * 5 * N2 + x2 * N + x1] * tb.fd[s][x0];
+            acc += w[1 * 2 * 5 * N2 + x2 * N + x0] * tb.fv[s][x1] + w[(1 * 2 + 1) * 5 * N2 + x2 * N + x0] * tb.fd[s][x1];
+            acc += w[2 * 2 * 5 * N2 + x1 * N + x0] * tb.fv[s][x2] + w[(2 * 2 + 1) * 5 * N2 + x1 * N + x0] * tb.fd[s][x2];
+        } else {
+            // the single face d0 (uniform over the workgroup)
+            const int ab = d0 == 0 ? x2 * N + x1 : (d0 == 1 ? x2 * N + x0 : x1 * N + x0);
+            const int m = d0 == 0 ? x0 : (d0 == 1 ? x1 : x2);
+            acc = w[ab] * tb.fv[s][m] + w[5 * N2 + ab] * tb.fd[s][m];
+        }
         sR[it] += acc;
     }
     __syncthreads();
 }
 
-// One face point it = d * n_q^2 + q0 + n_q q1 of the group of faces xi_d = s: the
-// t1 contraction of both sides' t0-swept traces A (layout [f][side][3][c][N][Q]),
-// the numerical fluxes, and the reference-space test coefficients
-//   res[kind * 5 + c], kind = value, g_t0, g_t1, g_n.
+// One face point it = f * n_q^2 + q0 + n_q q1 of the group of faces xi_d = s,
+// d = d0 + f: the t1 contraction of both sides' t0-swept traces A (layout
+// [f][side][3][c][N][Q]), the numerical fluxes, and the reference-space test
+// coefficients res[kind * 5 + c], kind = value, g_t0, g_t1, g_n.
 template <int N, int Q, typename Real, bool GEN>
 __device__ __forceinline__ void face_point(const OpArgs& a, const KTab<N, Q, Real>& lt, const Phys<Real>& ph, bool conv,
-                                           bool visc, int s, const FaceInfo& fi, const Real* sTau, const Real* sFn,
-                                           const Real* sJr, Real detJ, const Real* r1, int it, Real (&res)[20]) {
+                                           bool visc, int s, int d0, const FaceInfo& fi, const Real* sTau,
+                                           const Real* sFn, const Real* sJr, Real detJ, const Real* r1, int it,
+                                           Real (&res)[20]) {
     constexpr int Q2 = Q * Q;
-    const int d = it / Q2, pt = it % Q2, q0 = pt % Q, q1 = pt / Q;
+    const int f = it / Q2, d = d0 + f, pt = it % Q2, q0 = pt % Q, q1 = pt / Q;
     const int fslot = d + 3 * s;
     const bool wall = fi.wall[fslot] != 0;
     // reference axes of the face: tangential t0 < t1, normal d; rows[r] is the
@@ -329,7 +346,7 @@ __device__ __forceinline__ void face_point(const OpArgs& a, const KTab<N, Q, Rea
     Prim<Real> sm;
     {
         Real G[5][3], Fn[5];
-        load_face_point_rows<N, Q, Real>(lt, r1 + (d * 2 + 0) * 3 * 5 * N * Q, q0, q1, Jm, Um, G);
+        load_face_point_rows<N, Q, Real>(lt, r1 + (f * 2 + 0) * 3 * 5 * N * Q, q0, q1, Jm, Um, G);
         sm = primitives(Um, ph);
 #pragma unroll
         for (int c = 0; c < 5; ++c) val[c] = 0;
@@ -360,7 +377,7 @@ __device__ __forceinline__ void face_point(const OpArgs& a, const KTab<N, Q, Rea
 #pragma unroll
                     for (int j = 0; j < 3; ++j) Jp[3 * r + j] = (Real)cm[3 * rows[r] + j];
             }
-            load_face_point_rows<N, Q, Real>(lt, r1 + (d * 2 + 1) * 3 * 5 * N * Q, q0, q1, Jp, Up, G);
+            load_face_point_rows<N, Q, Real>(lt, r1 + (f * 2 + 1) * 3 * 5 * N * Q, q0, q1, Jp, Up, G);
         }
         const Prim<Real> sp = primitives(Up, ph);
         if (conv) {
@@ -405,13 +422,14 @@ __device__ __forceinline__ void face_point(const OpArgs& a, const KTab<N, Q, Rea
 }
 
 // The three faces xi_d = s (d = 0, 1, 2) of the cell: traces, fluxes, test
-// integration, accumulated into sR.
-template <int N, int Q, typename Real, bool GEN>
+// integration, accumulated into sR.  NF = 3 processes the faces of all three
+// directions together (d0 = 0); NF = 1 the single face xi_{d0} = s.
+template <int N, int Q, typename Real, bool GEN, int NF>
 __device__ __forceinline__ void face_group(const OpArgs& a, const KTab<N, Q, Real>& lt, const Phys<Real>& ph, bool conv,
-                                           bool visc, int s, int64_t e, const FaceInfo& fi, const Real* sTau,
+                                           bool visc, int s, int d0, const FaceInfo& fi, const Real* sTau,
                                            const Real* sFn, const Real* sJr, Real detJ, const Real* sU, Real* sR,
                                            Real* sW) {
-    using FS = FaceSizes<N, Q, OpBlock<N, Q, Real>::threads>;
+    using FS = FaceSizes<N, Q, OpBlock<N, Q, Real>::threads, NF>;
     constexpr int N2 = N * N, N3 = N2 * N, Q2 = Q * Q;
     // work regions: SW (swept traces, read by the point phase), TR (traces), OUT
     // (point results), T1 (t1-transposed), W (lifted): see FaceSizes
@@ -423,8 +441,8 @@ __device__ __forceinline__ void face_group(const OpArgs& a, const KTab<N, Q, Rea
     const int64_t cstride = a.ncell * N3;
 
     // traces: value and normal derivative of both sides at the face nodes
-    for (int it = tid; it < 3 * 5 * N2; it += nth) {
-        const int d = it / (5 * N2), c = (it / N2) % 5, ab = it % N2, ia = ab % N, ib = ab / N;
+    for (int it = tid; it < NF * 5 * N2; it += nth) {
+        const int f = it / (5 * N2), d = d0 + f, c = (it / N2) % 5, ab = it % N2, ia = ab % N, ib = ab / N;
         const int t0 = d == 0 ? 1 : 0, t1 = d == 2 ? 1 : 2;
         const int base = ia * axis_stride(t0, N) + ib * axis_stride(t1, N), sd = axis_stride(d, N);
         Real tv = 0, tn = 0, uv = 0, un = 0;
@@ -443,7 +461,7 @@ __device__ __forceinline__ void face_group(const OpArgs& a, const KTab<N, Q, Rea
                 un += lt.fd[1 - s][m] * x;
             }
         }
-        Real* tr = rtr + d * (2 * 2 * 5 * N2) + c * N2 + ab;
+        Real* tr = rtr + f * (2 * 2 * 5 * N2) + c * N2 + ab;
         tr[(0 * 2 + 0) * 5 * N2] = tv;
         tr[(0 * 2 + 1) * 5 * N2] = tn;
         tr[(1 * 2 + 0) * 5 * N2] = uv;
@@ -452,17 +470,17 @@ __device__ __forceinline__ void face_group(const OpArgs& a, const KTab<N, Q, Rea
     __syncthreads();
 
     // sweep along t0: A0 = S tv, A1 = D tv, An = S tn     r1 [f][side][3][c][b][q0]
-    for (int it = tid; it < 3 * 2 * 5 * N; it += nth) {
-        const int ib = it % N, c = (it / N) % 5, side = (it / (5 * N)) % 2, d = it / (10 * N);
+    for (int it = tid; it < NF * 2 * 5 * N; it += nth) {
+        const int ib = it % N, c = (it / N) % 5, side = (it / (5 * N)) % 2, f = it / (10 * N), d = d0 + f;
         if (side == 1 && fi.wall[d + 3 * s]) continue;
-        const Real* tr = rtr + d * (2 * 2 * 5 * N2) + side * (2 * 5 * N2) + c * N2 + ib * N;
+        const Real* tr = rtr + f * (2 * 2 * 5 * N2) + side * (2 * 5 * N2) + c * N2 + ib * N;
         Real tv[N], tn[N];
 #pragma unroll
         for (int ia = 0; ia < N; ++ia) {
             tv[ia] = tr[ia];
             tn[ia] = tr[5 * N2 + ia];
         }
-        Real* o = r1 + ((d * 2 + side) * 3 * 5 + c) * N * Q + ib * Q;
+        Real* o = r1 + ((f * 2 + side) * 3 * 5 + c) * N * Q + ib * Q;
 #pragma unroll
         for (int q0 = 0; q0 < Q; ++q0) {
             Real a0 = 0, a1 = 0, an = 0;
@@ -485,8 +503,8 @@ __device__ __forceinline__ void face_group(const OpArgs& a, const KTab<N, Q, Rea
     // across a barrier and overwrite the swept traces (smaller LDS footprint).
     if constexpr (FS::ALIAS) {
         Real res[20];
-        const bool act = tid < 3 * Q2;
-        if (act) face_point<N, Q, Real, GEN>(a, lt, ph, conv, visc, s, fi, sTau, sFn, sJr, detJ, r1, tid, res);
+        const bool act = tid < NF * Q2;
+        if (act) face_point<N, Q, Real, GEN>(a, lt, ph, conv, visc, s, d0, fi, sTau, sFn, sJr, detJ, r1, tid, res);
         __syncthreads();
         if (act) {
             Real* o = r2 + (tid / Q2) * 4 * 5 * Q2 + tid % Q2;
@@ -494,9 +512,9 @@ __device__ __forceinline__ void face_group(const OpArgs& a, const KTab<N, Q, Rea
             for (int m = 0; m < 20; ++m) o[m * Q2] = res[m];
         }
     } else {
-        for (int it = tid; it < 3 * Q2; it += nth) {
+        for (int it = tid; it < NF * Q2; it += nth) {
             Real res[20];
-            face_point<N, Q, Real, GEN>(a, lt, ph, conv, visc, s, fi, sTau, sFn, sJr, detJ, r1, it, res);
+            face_point<N, Q, Real, GEN>(a, lt, ph, conv, visc, s, d0, fi, sTau, sFn, sJr, detJ, r1, it, res);
             Real* o = r2 + (it / Q2) * 4 * 5 * Q2 + it % Q2;
 #pragma unroll
             for (int m = 0; m < 20; ++m) o[m * Q2] = res[m];
@@ -504,13 +522,13 @@ __device__ __forceinline__ void face_group(const OpArgs& a, const KTab<N, Q, Rea
     }
     __syncthreads();
 
-    face_test_accumulate<N, Q, Real>(lt, s, rt1, r2, sR);
+    face_test_accumulate<N, Q, Real, NF>(lt, s, d0, rt1, r2, sR);
 }
 
 template <int N, int Q, typename Real, bool GEN>
 __global__ void __launch_bounds__((OpBlock<N, Q, Real>::threads)) __attribute__((amdgpu_waves_per_eu(2)))
 dg_operator_kernel(OpArgs a, KTab<N, Q, Real> tb, MTab<N, Real> mt) {
-    using Sz = OpSizes<N, Q, OpBlock<N, Q, Real>::threads>;
+    using Sz = OpSizes<N, Q, OpBlock<N, Q, Real>::threads, (int)sizeof(Real)>;
     constexpr int P = Sz::P;
     constexpr int N2 = N * N, N3 = N2 * N, Q2 = Q * Q, Q3 = Q2 * Q;
     constexpr int ZS = CellSizes<N, Q, P>::Z, YS = CellSizes<N, Q, P>::Y;
@@ -541,7 +559,7 @@ dg_operator_kernel(OpArgs a, KTab<N, Q, Real> tb, MTab<N, Real> mt) {
     // exceed the scalar register file and spill through vector lanes.
     const KTab<N, Q, Real>* ltp;
     const MTab<N, Real>* lmp;
-    if constexpr (Sz::template lds_tables<Real>()) {
+    if constexpr (Sz::LDS_TAB) {
         __shared__ KTab<N, Q, Real> lt_lds;
         copy_table<KTab<N, Q, Real>, Real>(tb, lt_lds);
         ltp = &lt_lds;
@@ -770,8 +788,14 @@ dg_operator_kernel(OpArgs a, KTab<N, Q, Real> tb, MTab<N, Real> mt) {
         }
 
         // ------------------------------------------------------------ face terms
-        face_group<N, Q, Real, GEN>(a, lt, ph, conv, visc, 0, e, fi, sTau, sFn, sJr, detJ, sU, sR, sW);
-        face_group<N, Q, Real, GEN>(a, lt, ph, conv, visc, 1, e, fi, sTau, sFn, sJr, detJ, sU, sR, sW);
+        if constexpr (Sz::NF == 3) {
+            face_group<N, Q, Real, GEN, 3>(a, lt, ph, conv, visc, 0, 0, fi, sTau, sFn, sJr, detJ, sU, sR, sW);
+            face_group<N, Q, Real, GEN, 3>(a, lt, ph, conv, visc, 1, 0, fi, sTau, sFn, sJr, detJ, sU, sR, sW);
+        } else {
+            for (int s = 0; s < 2; ++s)
+                for (int d0 = 0; d0 < 3; ++d0)
+                    face_group<N, Q, Real, GEN, 1>(a, lt, ph, conv, visc, s, d0, fi, sTau, sFn, sJr, detJ, sU, sR, sW);
+        }
     }
 
     // ------------------------------------------------------------ body force (k+1 rule)
@@ -1027,7 +1051,7 @@ inline int launch_op_t(const OpArgs& a, const Tables1D& t, hipStream_t st) {
     MTab<N, Real> mt;
     fill_tables<N, Q, Real>(t, kt, mt);
     constexpr int B = OpBlock<N, Q, Real>::threads;
-    static_assert((OpSizes<N, Q, B>::WORK + 10 * N * N * N) * sizeof(Real) <= 160 * 1024, "LDS budget");
+    static_assert((OpSizes<N, Q, B, (int)sizeof(Real)>::WORK + 10 * N * N * N) * sizeof(Real) <= 160 * 1024, "LDS budget");
     hipLaunchKernelGGL((dg_operator_kernel<N, Q, Real, GEN>), dim3((unsigned)a.ncell), dim3(B), 0, st, a, kt, mt);
     return hipGetLastError() == hipSuccess ? 0 : -1;
 }

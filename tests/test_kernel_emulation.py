@@ -9,6 +9,7 @@ per-field bound a wide margin.
 import math
 
 import numpy as np
+import torch
 import pytest
 
 from oracle import mesh as omesh, operator as ooperator
@@ -30,17 +31,24 @@ def _tgv_case(n, k, nq, kind=0, amp=0.0, basis="LGL"):
     ((2, 2, 2), 2, 3, 2, 0.15, "GL"),
     ((2, 1, 2), 3, 6, 0, 0.0, "LGL"),
     ((1, 2, 2), 3, 6, 2, 0.1, "GL"),
+    # k = 7, n_q = 11 in float64: one face per face phase (the three-face layout leaves
+    # no room in LDS for the 1D tables), 256-thread workgroups
+    ((2, 1, 1), 7, 11, 0, 0.0, "LGL"),
 ])
 def test_emulated_residual_per_term(n, k, nq, kind, amp, basis):
     fl, oop, U = _tgv_case(n, k, nq, kind, amp, basis)
     b = 0 if basis == "LGL" else 1
+    tol = 1e-12 * max(1.0, ((k + 1) / 4.0) ** 2)   # derivative matrices grow like (k+1)^2
     for mask, t in ((1, "c"), (2, "v"), (3, "cv")):
         R = ed.run(U.numpy(), k, nq, n, *PI3, kind=kind, amp=amp, basis=b, mu=fl.mu, lam=fl.lam, terms=mask)
         errs = rel_err_fields(R, oop.residual(U, terms=t))
-        assert max(errs) < 1e-12, (t, errs)
+        assert max(errs) < tol, (t, errs)
     L = ed.run(U.numpy(), k, nq, n, *PI3, kind=kind, amp=amp, basis=b, mu=fl.mu, lam=fl.lam, terms=7, fuse=1)
-    errs = rel_err_fields(L, oop.apply(U))
-    assert max(errs) < 1e-12, errs
+    R = oop.residual(U)
+    M = oop.mass_matrices()
+    ML = torch.einsum("eij,cej->cei", M, torch.as_tensor(L))
+    errs = rel_err_fields(ML, R)   # backward error of L = M^{-1} R (cond(M) grows with k)
+    assert max(errs) < tol, errs
 
 
 def test_emulated_channel_walls_and_force():
