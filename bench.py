@@ -188,7 +188,9 @@ def degree_sweep(target_dofs=10_000_000, calls=20):
     """Operator throughput over every compiled (k, n_q), float64 and float32, on
     Taylor-Green meshes of about target_dofs DoFs (the mesh size n^3 with n the
     nearest integer to (target_dofs / (5 (k+1)^3))^(1/3)); also F_c, F_v and M^{-1}
-    separately (the paper's operation breakdown)."""
+    separately (the paper's operation breakdown); and L on the same mesh deformed
+    by the sinusoidal warp (amplitude 0.1 h), where the metric is read per
+    quadrature point (the paper's Cartesian versus deformed comparison, Sec. 4)."""
     import torch
     from paper_1806_03095_amd import taylor_green
     qs = {1: (2, 3), 2: (3, 4), 3: (4, 5, 6), 4: (5, 6, 7), 5: (6, 8), 6: (7, 10), 7: (8, 11)}
@@ -197,22 +199,25 @@ def degree_sweep(target_dofs=10_000_000, calls=20):
         ne = max(2, int(round((target_dofs / (5.0 * (k + 1) ** 3)) ** (1.0 / 3.0))))
         for nq in nqs:
             row = {"k": k, "n_q": nq, "cells": ne ** 3}
-            for prec in ("fp64", "fp32"):
-                op = taylor_green(k, ne, n_q=nq, precision=prec)
+            for prec, mesh in (("fp64", "affine"), ("fp32", "affine"), ("fp64", "curved"), ("fp32", "curved")):
+                kw = {} if mesh == "affine" else {"kind": "curved", "deform_amp": 0.1 * 2 * math.pi / ne}
+                op = taylor_green(k, ne, n_q=nq, precision=prec, **kw)
                 U = op.project_ic("taylor_green", [1.0, 1.0, 0.1, 1.0])
                 L = torch.empty_like(U)
                 t = time_call(lambda: op.apply(U, L), calls)
                 row["n_dof"] = op.n_dof
-                row[prec + "_L_dofs_per_s"] = op.n_dof / t
-                if prec == "fp64":
+                tag = prec if mesh == "affine" else prec + "_deformed"
+                row[tag + "_L_dofs_per_s"] = op.n_dof / t
+                if prec == "fp64" and mesh == "affine":
                     for name, mask in (("F_c", 1), ("F_v", 2)):
                         tt = time_call(lambda: op.residual(U, L, terms=mask), calls)
                         row["fp64_%s_dofs_per_s" % name] = op.n_dof / tt
                     tt = time_call(lambda: op.inverse_mass(U, L), calls)
                     row["fp64_M_inv_dofs_per_s"] = op.n_dof / tt
                 op.close()
-            log("k=%d n_q=%d %d^3: L fp64 %.3e fp32 %.3e DoF/s" % (k, nq, ne, row["fp64_L_dofs_per_s"],
-                                                                    row["fp32_L_dofs_per_s"]))
+            log("k=%d n_q=%d %d^3: L fp64 %.3e fp32 %.3e, deformed fp64 %.3e fp32 %.3e DoF/s"
+                % (k, nq, ne, row["fp64_L_dofs_per_s"], row["fp32_L_dofs_per_s"],
+                   row["fp64_deformed_L_dofs_per_s"], row["fp32_deformed_L_dofs_per_s"]))
             rows.append(row)
     return rows
 

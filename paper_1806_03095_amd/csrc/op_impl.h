@@ -77,22 +77,45 @@ struct ChooseP {
     static constexpr int v = fit(Q);
 };
 
-// LDS plan of the operator kernel for block size B and RS-byte reals: the work area
-// (largest of the cell chunk, the face group and the mass-matrix sweeps), the number
-// NF of faces per face group (three, or one when three do not leave room for the 1D
-// table copies), and whether the table copies fit.
+// LDS plan of the operator kernel for block size B and RS-byte reals: the number NF
+// of faces per face group, the number P of planes per cell chunk, the work area
+// (largest of the cell chunk, the face group and the mass-matrix sweeps) and whether
+// the 1D table copies fit beside it.  The preferred plan is three faces per group
+// and ChooseP's plane count.  When LDS keeps that plan below two waves per SIMD
+// (eight per compute unit):
+//  - fewer planes, if that reaches two waves;
+//  - else, for 256-thread workgroups, one face per group if that reaches two waves
+//    and the face-point phase still gains: 3 ceil(n_q^2 / B) passes at w1 waves per
+//    SIMD against ceil(3 n_q^2 / B) passes at w3 waves;
+//  - else one face per group only when three faces leave no room for the tables.
 template <int N, int Q, int B, int RS>
 struct OpSizes {
-    static constexpr int N3 = N * N * N;
-    static constexpr int P = ChooseP<N, Q>::v;
-    static constexpr int CELL = CellSizes<N, Q, P>::TOTAL;
+    static constexpr int N3 = N * N * N, Q2 = Q * Q;
     static constexpr int TABLES = 2 * Q * N + Q + 4 * N + 2 * N * N + N;   // KTab + MTab entries
-    static constexpr int W3 = CMax<CMax<CELL, FaceSizes<N, Q, B, 3>::TOTAL>::v, 10 * N3>::v;
-    static constexpr int W1 = CMax<CMax<CELL, FaceSizes<N, Q, B, 1>::TOTAL>::v, 10 * N3>::v;
-    static constexpr bool fits(int work) { return (work + 10 * N3 + TABLES) * RS + 1024 <= 160 * 1024; }
-    static constexpr int NF = fits(W3) ? 3 : 1;
-    static constexpr int WORK = NF == 3 ? W3 : W1;
-    static constexpr bool LDS_TAB = fits(WORK);
+    static constexpr int LDS_MAX = 160 * 1024;
+    static constexpr int TARGET = LDS_MAX / (8 * 64 / B);   // LDS per workgroup at eight waves per CU
+    static constexpr int cell(int p) { return 10 * Q * N * N + 15 * p * Q * (N + Q); }
+    static constexpr int face(int nf) { return nf == 3 ? FaceSizes<N, Q, B, 3>::TOTAL : FaceSizes<N, Q, B, 1>::TOTAL; }
+    static constexpr int work(int nf, int p) {
+        return cell(p) > face(nf) ? (cell(p) > 10 * N3 ? cell(p) : 10 * N3) : (face(nf) > 10 * N3 ? face(nf) : 10 * N3);
+    }
+    static constexpr int lds(int nf, int p) { return (work(nf, p) + 10 * N3 + TABLES) * RS + 1024; }
+    static constexpr int fewer(int nf, int p) { return p <= 1 || lds(nf, p) <= TARGET ? p : fewer(nf, p - 1); }
+    // waves per SIMD that the LDS footprint allows, at most two (the register budget)
+    static constexpr int waves(int bytes) {
+        return (LDS_MAX / bytes) * (B / 64) / 4 < 2 ? (LDS_MAX / bytes) * (B / 64) / 4 : 2;
+    }
+    static constexpr int P0 = ChooseP<N, Q>::v;
+    static constexpr bool REACH3 = lds(3, fewer(3, P0)) <= TARGET;
+    static constexpr bool REACH1 = B == 256 && lds(1, fewer(1, P0)) <= TARGET &&
+                                   3 * ((Q2 + B - 1) / B) * waves(lds(3, P0)) <
+                                       ((3 * Q2 + B - 1) / B) * waves(lds(1, fewer(1, P0)));
+    static constexpr int NF = REACH3 ? 3 : (REACH1 ? 1 : (lds(3, P0) <= LDS_MAX ? 3 : 1));
+    static constexpr int P = lds(NF, fewer(NF, P0)) <= TARGET ? fewer(NF, P0) : P0;
+    static constexpr int CELL = cell(P);
+    static constexpr int WORK = work(NF, P);
+    static constexpr bool LDS_TAB = lds(NF, P) <= LDS_MAX;
+    static_assert(CELL == CellSizes<N, Q, P>::TOTAL, "cell work area");
 };
 
 // Workgroup size of the operator kernel: 128 threads (two waves) per cell while
