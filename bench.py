@@ -190,7 +190,7 @@ def degree_sweep(target_dofs=10_000_000, calls=20):
     nearest integer to (target_dofs / (5 (k+1)^3))^(1/3)); also F_c, F_v and M^{-1}
     separately (the paper's operation breakdown); and L on the same mesh deformed
     by the sinusoidal warp (amplitude 0.1 h), where the metric is read per
-    quadrature point (the paper's Cartesian versus deformed comparison, Sec. 4)."""
+    quadrature point (the paper's Cartesian versus deformed comparison, Sec. 5.1.1)."""
     import torch
     from paper_1806_03095_amd import taylor_green
     qs = {1: (2, 3), 2: (3, 4), 3: (4, 5, 6), 4: (5, 6, 7), 5: (6, 8), 6: (7, 10), 7: (8, 11)}
