@@ -126,9 +126,14 @@ def operations(op, U, t_op, t_step, calls):
         out[name] = {"us": 1e6 * t, "dofs_per_s": ndof / t}
     t = time_call(lambda: op.inverse_mass(U, R), calls)
     out["M_inv"] = {"us": 1e6 * t, "dofs_per_s": ndof / t, "hbm_frac": 16 * ndof / t / PEAK_HBM}
-    t_upd = max(t_step / 5.0 - t_op, 0.0)
-    out["rk_update"] = {"us": 1e6 * t_upd, "hbm_frac": (40 * ndof / t_upd / PEAK_HBM) if t_upd > 0 else None,
-                        "note": "per stage: RK step time / 5 minus one operator launch"}
+    # the stand-alone stage update (read L, dU, U; write dU, U) on scratch copies
+    Uc, dU = U.clone(), torch.zeros_like(U)
+    t_upd = time_call(lambda: op.rk_stage_update(Uc, dU, R, 1, 1e-12), calls)
+    out["rk_update"] = {"us": 1e6 * t_upd, "hbm_frac": 40 * ndof / t_upd / PEAK_HBM,
+                        "in_step_us_per_stage": 1e6 * (t_step / 5.0 - t_op),
+                        "note": "stand-alone stage update; inside rk_step stages 1-4 fuse it into the operator "
+                                "kernel, and in_step_us_per_stage is the step time / 5 minus one operator launch"}
+    del Uc, dU
     out["L"] = {"us": 1e6 * t_op, "dofs_per_s": ndof / t_op}
     return out
 

@@ -131,8 +131,17 @@ int dgns_apply_operator(dgns_ctx* ctx, const double* U, double* L, double t);
  * (Carpenter & Kennedy 1994) in Williamson form, one L per stage:
  *   dU <- A_i dU + dt L(U, t + c_i dt);  U <- U + B_i dU.
  * U is updated in place.  work: device scratch of at least 2*n_dof doubles owned
- * by the caller (contents on return are unspecified). */
+ * by the caller (contents on return are unspecified): dU and a second copy of the
+ * state, since stages 1-4 fuse the update into the operator kernel and write the
+ * new state into the other buffer (U -> work[n_dof:] -> U -> work[n_dof:] -> U). */
 int dgns_rk_step(dgns_ctx* ctx, double* U, double* work, double t, double dt);
+
+/* The vector update of one stage of that scheme on its own (Sec. 2.4; the paper's
+ * "RK update" operation): dU <- A_i dU + dt L, then U <- U + B_i dU, for stage
+ * i = 0..4 (the first stage does not read dU).  U, dU, L: device, n_dof doubles
+ * each, pairwise non-overlapping; U and dU are updated in place.  Returns
+ * DGNS_EINVAL for a stage outside 0..4, a non-finite dt or overlapping vectors. */
+int dgns_rk_stage_update(dgns_ctx* ctx, double* U, double* dU, const double* L, int stage, double dt);
 
 /* The time step of eq. (TimeStepRestrictions_Compressible):
  * dt = min(Cr/k^e * h_min/(umax + umax/mach), D/k^f * h_min^2/nu), h_min the

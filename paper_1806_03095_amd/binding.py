@@ -44,7 +44,7 @@ class BoxMesh(ctypes.Structure):
 
 EXPORTS = ["dgns_last_error", "dgns_create", "dgns_destroy", "dgns_sizes", "dgns_set_stream",
            "dgns_apply_residual", "dgns_apply_inverse_mass", "dgns_apply_operator", "dgns_rk_step",
-           "dgns_compute_dt", "dgns_diagnostics", "dgns_project_ic", "dgns_apply_residual_vjp",
+           "dgns_rk_stage_update", "dgns_compute_dt", "dgns_diagnostics", "dgns_project_ic", "dgns_apply_residual_vjp",
            "dgns_apply_operator_vjp", "dgns_rk_step_vjp", "dgns_kinetic_energy", "dgns_kinetic_energy_vjp"]
 
 _lib = None
@@ -69,6 +69,7 @@ def load_library(path=LIB_PATH):
     lib.dgns_apply_inverse_mass.argtypes = [vp, vp, vp]
     lib.dgns_apply_operator.argtypes = [vp, vp, vp, ctypes.c_double]
     lib.dgns_rk_step.argtypes = [vp, vp, vp, ctypes.c_double, ctypes.c_double]
+    lib.dgns_rk_stage_update.argtypes = [vp, vp, vp, vp, ctypes.c_int, ctypes.c_double]
     lib.dgns_compute_dt.argtypes = [vp] + [ctypes.c_double] * 6 + [dp]
     lib.dgns_diagnostics.argtypes = [vp, vp, vp, dp]
     lib.dgns_project_ic.argtypes = [vp, ctypes.c_int, dp, vp, vp]
@@ -180,6 +181,14 @@ class Operator:
             raise ValueError("work must be a contiguous float64 CUDA tensor of >= 2 n_dof entries")
         self._bind()
         _check(self.lib.dgns_rk_step(self.h, _ptr(U), _ptr(work), t, dt))
+        return U
+
+    def rk_stage_update(self, U, dU, L, stage, dt):
+        """The stage-`stage` vector update alone: dU <- A dU + dt L, U <- U + B dU (in place)."""
+        for t, name in ((U, "U"), (dU, "dU"), (L, "L")):
+            self._vec(t, name)
+        self._bind()
+        _check(self.lib.dgns_rk_stage_update(self.h, _ptr(U), _ptr(dU), _ptr(L), int(stage), dt))
         return U
 
     def compute_dt(self, Cr, D, e, f, umax, mach):

@@ -24,16 +24,16 @@ __global__ void __launch_bounds__(256) rk_update_kernel(double* __restrict__ U, 
         const double2 l = L2[i];
         double2 d;
         if (FIRST) {
-            d.x = dt * l.x;
-            d.y = dt * l.y;
+            d.x = rk_increment(true, A, 0.0, dt, l.x);
+            d.y = rk_increment(true, A, 0.0, dt, l.y);
         } else {
             const double2 o = dU2[i];
-            d.x = A * o.x + dt * l.x;
-            d.y = A * o.y + dt * l.y;
+            d.x = rk_increment(false, A, o.x, dt, l.x);
+            d.y = rk_increment(false, A, o.y, dt, l.y);
         }
         double2 u = U2[i];
-        u.x += B * d.x;
-        u.y += B * d.y;
+        u.x = rk_advance(u.x, B, d.x);
+        u.y = rk_advance(u.y, B, d.y);
         dU2[i] = d;
         U2[i] = u;
     }
@@ -41,9 +41,9 @@ __global__ void __launch_bounds__(256) rk_update_kernel(double* __restrict__ U, 
 
 __global__ void rk_update_tail(double* U, double* dU, const double* L, int64_t i, double A, double B, double dt,
                                int first) {
-    const double d = first ? dt * L[i] : A * dU[i] + dt * L[i];
+    const double d = rk_increment(first != 0, A, first ? 0.0 : dU[i], dt, L[i]);
     dU[i] = d;
-    U[i] += B * d;
+    U[i] = rk_advance(U[i], B, d);
 }
 
 int launch_rk_update(double* U, double* dU, const double* L, int64_t n, double A, double B, double dt,

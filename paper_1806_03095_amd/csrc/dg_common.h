@@ -58,6 +58,23 @@ struct MTab {
 //           mass_jxw[e*N^3 + p] = |det J| w at the mass-rule points.
 // Face numbering in direction d: position pos = i_d (lower face of cell i_d, 0..n_d),
 // f = pos + (n_d + 1) * (i_t0 + n_t0 * i_t1), t0 < t1 the two other directions.
+// One stage of the 2N-storage Runge-Kutta scheme (Sec. 2.4) fused into the operator
+// kernel: with dU set, the kernel writes dU <- A dU + dt L and U_out <- U + B dU in
+// place of L.  U_out must not alias U, which the other workgroups read as neighbour
+// data.  A == 0 marks the first stage, where the old dU is not read.
+struct RkStage {
+    double* dU;
+    double* U_out;
+    double A, B, dt;
+};
+
+// The stage arithmetic at one DoF, shared by the fused and the standalone update so
+// that both round alike: dU <- A dU + dt L (dt L alone in the first stage), U <- U + B dU.
+__host__ __device__ inline double rk_increment(bool first, double A, double dU_old, double dt, double L) {
+    return first ? dt * L : fma(A, dU_old, dt * L);
+}
+__host__ __device__ inline double rk_advance(double U, double B, double dU) { return fma(B, dU, U); }
+
 struct OpArgs {
     const double* U;
     double* out;
@@ -72,6 +89,7 @@ struct OpArgs {
     double force[3];
     unsigned terms;
     int fuse_minv;
+    RkStage rk;   // dU == nullptr: write L (or R) to out
 };
 
 template <typename Real>

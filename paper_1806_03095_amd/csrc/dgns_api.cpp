@@ -344,13 +344,42 @@ int dgns_rk_step(dgns_ctx* c, double* U, double* work, double t, double dt) {
     if (overlap(U, c->ndof, work, 2 * c->ndof)) return fail(DGNS_EINVAL, "U and work overlap");
     if (!std::isfinite(dt)) return fail(DGNS_EINVAL, "dt is not finite");
     double* dU = work;
-    double* L = work + c->ndof;
-    for (int i = 0; i < 5; ++i) {
-        int rc = dispatch_operator(c, make_args(c, U, L, DGNS_TERM_ALL, 1));
+    double* U2 = work + c->ndof;
+    // Stages 1-4 fuse the update into the operator kernel, alternating the state
+    // between U and U2 (a stage cannot overwrite the U its neighbours still read):
+    // U -> U2 -> U -> U2 -> U.  Stage 5 writes L into U2 and updates U in place.
+    const double* src = U;
+    double* dst = U2;
+    for (int i = 0; i < 4; ++i) {
+        OpArgs a = make_args(c, src, nullptr, DGNS_TERM_ALL, 1);
+        a.rk.dU = dU;
+        a.rk.U_out = dst;
+        a.rk.A = kRkA[i];
+        a.rk.B = kRkB[i];
+        a.rk.dt = dt;
+        int rc = dispatch_operator(c, a);
         if (rc) return rc;
-        if (launch_rk_update(U, dU, L, c->ndof, kRkA[i], kRkB[i], dt, c->stream) != 0)
-            return fail(DGNS_EHIP, "rk update launch failed");
+        double* next = const_cast<double*>(src);
+        src = dst;
+        dst = next;
     }
+    int rc = dispatch_operator(c, make_args(c, U, U2, DGNS_TERM_ALL, 1));
+    if (rc) return rc;
+    if (launch_rk_update(U, dU, U2, c->ndof, kRkA[4], kRkB[4], dt, c->stream) != 0)
+        return fail(DGNS_EHIP, "rk update launch failed");
+    return DGNS_OK;
+}
+
+int dgns_rk_stage_update(dgns_ctx* c, double* U, double* dU, const double* L, int stage, double dt) {
+    if (!c || !U || !dU || !L) return fail(DGNS_EINVAL, "null argument");
+    if (stage < 0 || stage > 4) return fail(DGNS_EINVAL, "stage %d outside 0..4", stage);
+    if (!std::isfinite(dt)) return fail(DGNS_EINVAL, "dt is not finite");
+    if (!aligned8(U) || !aligned8(dU) || !aligned8(L)) return fail(DGNS_EINVAL, "vectors must be 8-byte aligned");
+    const int64_t n = c->ndof;
+    if (overlap(U, n, dU, n) || overlap(U, n, L, n) || overlap(dU, n, L, n))
+        return fail(DGNS_EINVAL, "U, dU and L must not overlap");
+    if (launch_rk_update(U, dU, L, n, kRkA[stage], kRkB[stage], dt, c->stream) != 0)
+        return fail(DGNS_EHIP, "rk update launch failed");
     return DGNS_OK;
 }
 

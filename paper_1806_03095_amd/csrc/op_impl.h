@@ -860,9 +860,21 @@ dg_operator_kernel(OpArgs a, KTab<N, Q, Real> tb, MTab<N, Real> mt) {
 
     if (a.fuse_minv) inverse_mass_lds<N, Real, GEN>(lm, lwm, sR, sW, detJ, jxw_m);
 
-    for (int i = tid; i < 5 * N3; i += nth) {
-        const int c = i / N3, j = i % N3;
-        a.out[c * cstride + e * N3 + j] = (double)sR[i];
+    if (a.rk.dU) {
+        // fused Runge-Kutta stage on the cell's own DoFs (U re-read in float64)
+        const bool first = a.rk.A == 0.0;
+        for (int i = tid; i < 5 * N3; i += nth) {
+            const int c = i / N3, j = i % N3;
+            const int64_t g = c * cstride + e * N3 + j;
+            const double d = rk_increment(first, a.rk.A, first ? 0.0 : a.rk.dU[g], a.rk.dt, (double)sR[i]);
+            a.rk.dU[g] = d;
+            a.rk.U_out[g] = rk_advance(a.U[g], a.rk.B, d);
+        }
+    } else {
+        for (int i = tid; i < 5 * N3; i += nth) {
+            const int c = i / N3, j = i % N3;
+            a.out[c * cstride + e * N3 + j] = (double)sR[i];
+        }
     }
 }
 

@@ -171,6 +171,74 @@ def test_rk_steps_tgv_4cubed():
     _check_low_mach(inc_gpu, inc_ora, "U10 - U0", norm_tol=2e-11, field_tol=1e-10)
 
 
+@pytest.mark.parametrize("case", ["channel_k4_fp64", "curved_k3_fp32", "tgv_k2_fp64"])
+def test_rk_step_fused_stages_match_stage_by_stage(case):
+    """rk_step fuses the update of stages 1-4 into the operator kernel; the same two
+    steps taken stage by stage (L from the operator, the update in torch with the
+    scheme's coefficients) must agree to rounding."""
+    announce("rk_step fused stages vs stage by stage: " + case)
+    if case == "channel_k4_fp64":
+        fl = tgv_fluid(mu=1.0 / 180.0)
+        T0 = (18.3 / 0.1) ** 2 / (fl.gamma * fl.R)
+        oop, gop = make_pair((2, 4, 2), 4, 7, lo=(0.0, -1.0, 0.0), hi=(2 * math.pi, 1.0, math.pi),
+                             periodic=(1, 0, 1), kind="channel", fluid=fl, force=(1.0, 0.0, 0.0), wall_T=T0)
+        U0 = channel_input(oop)
+        umax = 18.3
+    elif case == "curved_k3_fp32":
+        oop, gop = make_pair((3, 3, 3), 3, 6, kind="curved", amp=0.1, precision="fp32")
+        U0 = tgv_input(oop, seed=5)
+        umax = 1.0
+    else:
+        oop, gop = make_pair((3, 2, 2), 2, 4)
+        U0 = tgv_input(oop, seed=6)
+        umax = 1.0
+    dt = gop.compute_dt(0.3, 0.02, 1.5, 3.0, umax, 0.1)
+    Ug = _cuda(U0.clone())
+    work = torch.empty(2 * gop.n_dof, dtype=torch.float64, device="cuda")
+    for s in range(2):
+        gop.rk_step(Ug, work, s * dt, dt)
+    U = _cuda(U0.clone())
+    dU = torch.zeros_like(U)
+    A = [float(v) for v in timeint.CK54_A]
+    B = [float(v) for v in timeint.CK54_B]
+    for s in range(2):
+        for i in range(5):
+            L = gop.apply(U)
+            dU = dt * L if i == 0 else A[i] * dU + dt * L
+            U = U + B[i] * dU
+    torch.cuda.synchronize()
+    inc = (U - _cuda(U0)).abs().amax(dim=(1, 2))
+    diff = (Ug - U).abs().amax(dim=(1, 2))
+    rel = [float(d / max(i, 1e-300)) for d, i in zip(diff, inc)]
+    print("fused vs stage-by-stage, max difference relative to the increment per field:", rel, flush=True)
+    assert max(rel) < 1e-12, rel
+
+
+def test_rk_stage_update_alone():
+    announce("rk_stage_update: stages 0 and 3 against the scheme's coefficients; argument checks")
+    from paper_1806_03095_amd.binding import DgnsError
+    oop, gop = make_pair((3, 2, 1), 2, 3)
+    g = torch.Generator().manual_seed(3)
+    U0, dU0, L = (torch.randn(gop.shape, generator=g, dtype=torch.float64) for _ in range(3))
+    A = [float(v) for v in timeint.CK54_A]
+    B = [float(v) for v in timeint.CK54_B]
+    dt = 0.37
+    for stage in (0, 3):
+        U, dU = _cuda(U0.clone()), _cuda(dU0.clone())
+        if stage == 0:
+            dU.fill_(float("nan"))   # the first stage must not read dU
+        gop.rk_stage_update(U, dU, _cuda(L), stage, dt)
+        torch.cuda.synchronize()
+        d = dt * L if stage == 0 else A[stage] * dU0 + dt * L
+        assert torch.allclose(dU.cpu(), d, rtol=1e-15, atol=1e-15)
+        assert torch.allclose(U.cpu(), U0 + B[stage] * d, rtol=1e-15, atol=1e-15)
+    U, dU = _cuda(U0.clone()), _cuda(dU0.clone())
+    with pytest.raises(DgnsError):
+        gop.rk_stage_update(U, dU, _cuda(L), 5, dt)
+    with pytest.raises(DgnsError):
+        gop.rk_stage_update(U, U, _cuda(L), 1, dt)
+
+
 def test_diagnostics_and_projection():
     announce("tgv 4^3 k=3 nq=6: diagnostics and IC projection")
     oop, gop = make_pair((4, 4, 4), 3, 6)
