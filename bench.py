@@ -318,8 +318,8 @@ def main():
                     help="study mode: float32 vs float64 over STEPS RK steps (16^3 k=7, 24^3 k=5); one JSON line")
     args = ap.parse_args()
     if args.gpus != 1:
-        print("bench.py measures one GPU only: this build has no multi-GPU path (the halo-exchange "
-              "design is described in DESIGN.md); run with --gpus 1", file=sys.stderr)
+        print("bench.py measures one GPU only: the operator has no multi-GPU path (no halo exchange "
+              "between GPUs is implemented); run with --gpus 1", file=sys.stderr)
         sys.exit(2)
 
     import torch

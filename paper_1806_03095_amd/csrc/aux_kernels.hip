@@ -64,9 +64,9 @@ int launch_rk_update(double* U, double* dU, const double* L, int64_t n, double A
 }
 
 // ------------------------------------------------------------------ diagnostics
-// Per cell: [0] int |u|^2/2, [1] int grad u : grad u, [2] -int u.(L_m - u L_rho)/rho,
-// [3..7] int U (k+1 rule), [8] volume.  One workgroup per cell, direct evaluation
-// of the nodal expansion at each point (not on the hot path).
+// Totals of the nine per-cell partial sums that diag_kernel (diag_impl.h) writes:
+// [0] int |u|^2/2, [1] int grad u : grad u, [2] -int u.(L_m - u L_rho)/rho,
+// [3..7] int U (k+1 rule), [8] volume.
 constexpr int kDiag = 9;
 
 __device__ inline double block_sum(double v, double* red) {

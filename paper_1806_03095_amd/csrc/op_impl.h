@@ -878,182 +878,110 @@ dg_operator_kernel(OpArgs a, KTab<N, Q, Real> tb, MTab<N, Real> mt) {
     }
 }
 
-// Standalone inverse mass, LDS layout of one component block: index a0 + RP (a1 + N a2)
-// with rows padded to an odd length RP for even N, so that the lines of all three
-// sweep directions spread over the LDS banks.
-template <int N>
-struct MinvLayout {
-    static constexpr int RP = N % 2 == 0 ? N + 1 : N;
-    static constexpr int BLK = RP * N * N;
-    __device__ static constexpr int index(int a0, int a1, int a2) { return a0 + RP * (a1 + N * a2); }
-};
+// Standalone inverse mass, one x-line of one (component, cell) block per thread: the
+// workgroup's RPB blocks are one contiguous run of RPB N^3 values, which consecutive
+// threads load and store N values apiece (fully coalesced).  The sweep
+// along xi_0 runs in registers; the sweeps along xi_1 and xi_2 re-read the block from
+// LDS as lines of that axis, each thread writing back exactly the values it read, so
+// that one barrier per change of axis suffices (four in all).  In place allowed: a
+// workgroup reads all of its blocks before it writes them.
+constexpr int kMinvLineBlock = 256;
 
-// Cells per workgroup of the standalone inverse mass: about 20 KB of LDS each, so
-// that every phase has several independent lines per thread and the barriers are
-// shared by CPB cells.
-template <int N, typename Real>
-struct MinvCells {
-    static constexpr int bytes = 10 * MinvLayout<N>::BLK * (int)sizeof(Real);
-    static constexpr int v = bytes >= 20480 ? 1 : 20480 / bytes;
-};
-
-// M (or M^T) along axis ax of NC padded component blocks src -> dst (see MinvLayout).
-template <int N, typename Real, bool TRANS, int NC>
-__device__ __forceinline__ void sweep_padded(const Real (&M)[N][N], const Real* src, Real* dst, int ax) {
-    using LY = MinvLayout<N>;
-    constexpr int N2 = N * N;
-    const int stride = ax == 0 ? 1 : (ax == 1 ? LY::RP : LY::RP * N);
-    for (int it = threadIdx.x; it < NC * N2; it += blockDim.x) {
-        const int c = it / N2, i = it % N2, j0 = i % N, j1 = i / N;
-        const int base = c * LY::BLK + (ax == 0 ? LY::index(0, j0, j1) : (ax == 1 ? LY::index(j0, 0, j1) : LY::index(j0, j1, 0)));
-        Real v[N];
+template <int N, bool TRANS, typename Real>
+__device__ __forceinline__ void apply_line(const Real (&M)[N][N], Real (&v)[N]) {
+    Real t[N];
 #pragma unroll
-        for (int m = 0; m < N; ++m) v[m] = src[base + m * stride];
+    for (int o = 0; o < N; ++o) {
+        Real acc = 0;
 #pragma unroll
-        for (int o = 0; o < N; ++o) {
-            Real acc = 0;
-#pragma unroll
-            for (int m = 0; m < N; ++m) acc += (TRANS ? M[m][o] : M[o][m]) * v[m];
-            dst[base + o * stride] = acc;
-        }
+        for (int m = 0; m < N; ++m) acc += (TRANS ? M[m][o] : M[o][m]) * v[m];
+        t[o] = acc;
     }
-}
-
-// Standalone inverse mass: L = M^{-1} R for CPB consecutive cells per workgroup
-// (in place allowed: a workgroup reads all of its cells before it writes them, and
-// no other workgroup touches them).  For each component the CPB cells' coefficients
-// are one contiguous run in memory, loaded and stored with consecutive threads.
-template <int N, typename Real, bool GEN>
-__global__ void __launch_bounds__(kBlock)
-inverse_mass_kernel(const double* R, double* L, int64_t ncell, const double* cell_metric, const double* mass_jxw,
-                    MTab<N, Real> mt) {
-    using LY = MinvLayout<N>;
-    constexpr int N2 = N * N, N3 = N2 * N, CPB = MinvCells<N, Real>::v, NC = 5 * CPB;
-    __shared__ Real sR[NC * LY::BLK];   // [cell][c][padded N^3]
-    __shared__ Real sW[NC * LY::BLK];
-    __shared__ Real sJ[CPB];            // affine: det J per cell
-    __shared__ Real lwm[N];
-    const int tid = threadIdx.x, nth = blockDim.x;
-    for (int i = tid; i < N; i += nth) lwm[i] = mt.wm[i];
-    const int64_t e0 = (int64_t)blockIdx.x * CPB;
-    const int ncb = (int)((ncell - e0) < CPB ? (ncell - e0) : CPB);   // cells of this workgroup
-    const int64_t cs = ncell * N3;
-    // load: i = (c, cb, r) with (cb, r) contiguous in memory for fixed c
-    for (int i = tid; i < 5 * ncb * N3; i += nth) {
-        const int c = i / (ncb * N3), rest = i % (ncb * N3), cb = rest / N3, r = rest % N3;
-        sR[(cb * 5 + c) * LY::BLK + LY::index(r % N, (r / N) % N, r / N2)] = (Real)R[c * cs + e0 * N3 + rest];
-    }
-    for (int cb = tid; cb < CPB; cb += nth) {
-        Real dj = 1;
-        if constexpr (!GEN) {
-            if (cb < ncb) dj = (Real)cell_metric[(e0 + cb) * 10 + 9];
-        }
-        sJ[cb] = dj;
-    }
-    __syncthreads();
-    // sR <- (Smi)^{x3} diag(1/(|J| w)) (Smi^T)^{x3} sR on all cells of the block
-    sweep_padded<N, Real, true, NC>(mt.Smi, sR, sW, 0);
-    __syncthreads();
-    sweep_padded<N, Real, true, NC>(mt.Smi, sW, sR, 1);
-    __syncthreads();
-    sweep_padded<N, Real, true, NC>(mt.Smi, sR, sW, 2);
-    __syncthreads();
-    for (int it = tid; it < NC * N3; it += nth) {
-        const int cc = it / N3, p = it % N3, cb = cc / 5;
-        const int p0 = p % N, p1 = (p / N) % N, p2 = p / N2;
-        Real jxw;
-        if constexpr (GEN) jxw = cb < ncb ? (Real)mass_jxw[(e0 + cb) * N3 + p] : Real(1);
-        else jxw = sJ[cb] * lwm[p0] * lwm[p1] * lwm[p2];
-        const int q = cc * LY::BLK + LY::index(p0, p1, p2);
-        sW[q] = sW[q] / jxw;
-    }
-    __syncthreads();
-    sweep_padded<N, Real, false, NC>(mt.Smi, sW, sR, 0);
-    __syncthreads();
-    sweep_padded<N, Real, false, NC>(mt.Smi, sR, sW, 1);
-    __syncthreads();
-    sweep_padded<N, Real, false, NC>(mt.Smi, sW, sR, 2);
-    __syncthreads();
-    for (int i = tid; i < 5 * ncb * N3; i += nth) {
-        const int c = i / (ncb * N3), rest = i % (ncb * N3), cb = rest / N3, r = rest % N3;
-        L[c * cs + e0 * N3 + rest] = (double)sR[(cb * 5 + c) * LY::BLK + LY::index(r % N, (r / N) % N, r / N2)];
-    }
-}
-
-// largest N whose N^3 coefficients a thread of the standalone inverse mass holds in
-// registers (N = 5: 125 values, one wave per SIMD); larger N use the LDS kernel
-#ifndef DGNS_MINV_REG_MAX_N
-#define DGNS_MINV_REG_MAX_N 5
-#endif
-// Standalone inverse mass for small N: one thread per (component, cell) holds the
-// cell's N^3 coefficients of that component in registers and applies the six 1D
-// sweeps and the diagonal scaling with compile-time indices.  Consecutive threads
-// take consecutive cells of one component, so a wave reads one contiguous run of
-// 64 N^3 values.  No LDS, no barriers; in place allowed (each thread reads its
-// block before writing it).
-template <int N, bool TRANS, int AX, typename Real>
-__device__ __forceinline__ void sweep_regs(const Real (&M)[N][N], Real (&v)[N * N * N]) {
-    constexpr int S = AX == 0 ? 1 : (AX == 1 ? N : N * N);
 #pragma unroll
-    for (int j1 = 0; j1 < N; ++j1)
-#pragma unroll
-        for (int j0 = 0; j0 < N; ++j0) {
-            // line through (j0, j1) in the two other axes
-            const int base = AX == 0 ? N * j0 + N * N * j1 : (AX == 1 ? j0 + N * N * j1 : j0 + N * j1);
-            Real t[N];
-#pragma unroll
-            for (int m = 0; m < N; ++m) t[m] = v[base + m * S];
-#pragma unroll
-            for (int o = 0; o < N; ++o) {
-                Real acc = 0;
-#pragma unroll
-                for (int m = 0; m < N; ++m) acc += (TRANS ? M[m][o] : M[o][m]) * t[m];
-                v[base + o * S] = acc;
-            }
-        }
+    for (int o = 0; o < N; ++o) v[o] = t[o];
 }
 
 template <int N, typename Real, bool GEN>
-__global__ void __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(N <= 4 ? 2 : 1)))
-inverse_mass_reg_kernel(const double* R, double* L, int64_t ncell, const double* cell_metric, const double* mass_jxw,
-                        MTab<N, Real> mt) {
-    constexpr int N3 = N * N * N;
-    // thread t = c * ncell + e owns the block of component c of cell e: the N^3
-    // values at R + t * N^3
-    const int64_t t = (int64_t)blockIdx.x * 64 + threadIdx.x;
-    if (t >= 5 * ncell) return;
-    const double* src = R + t * N3;
-    Real v[N3];
-#pragma unroll
-    for (int i = 0; i < N3; ++i) v[i] = (Real)src[i];
-    sweep_regs<N, true, 0>(mt.Smi, v);
-    sweep_regs<N, true, 1>(mt.Smi, v);
-    sweep_regs<N, true, 2>(mt.Smi, v);
-    const int64_t e = t % ncell;
-    if constexpr (GEN) {
-        const double* jw = mass_jxw + e * N3;
-#pragma unroll
-        for (int i = 0; i < N3; ++i) v[i] = v[i] / (Real)jw[i];
-    } else {
-        Real iw[N];
-#pragma unroll
-        for (int i = 0; i < N; ++i) iw[i] = Real(1) / mt.wm[i];
-        const Real idet = Real(1) / (Real)cell_metric[e * 10 + 9];
-#pragma unroll
-        for (int i2 = 0; i2 < N; ++i2)
-#pragma unroll
-            for (int i1 = 0; i1 < N; ++i1) {
-                const Real f = idet * iw[i1] * iw[i2];
-#pragma unroll
-                for (int i0 = 0; i0 < N; ++i0) v[i0 + N * (i1 + N * i2)] *= f * iw[i0];
-            }
+__global__ void __launch_bounds__(kMinvLineBlock)
+inverse_mass_line_kernel(const double* R, double* L, int64_t ncell, const double* cell_metric,
+                         const double* mass_jxw, MTab<N, Real> mt) {
+    constexpr int N2 = N * N, N3 = N2 * N, RPB = kMinvLineBlock / N2;
+    __shared__ Real buf[RPB * N3];   // [block][a2][a1][a0]
+    __shared__ Real lwm[N];          // mass-rule weights, indexed per lane
+    const int tid = threadIdx.x;
+    if (tid < N) lwm[tid] = mt.wm[tid];
+    // the N x N table stays a kernel argument up to N = 7; for N = 8 it is read from
+    // an LDS copy (as a kernel argument the compiler keeps that one in scratch memory)
+    const MTab<N, Real>* tp = &mt;
+    if constexpr (N > 7) {
+        __shared__ MTab<N, Real> lmt;
+        copy_table<MTab<N, Real>, Real>(mt, lmt);
+        tp = &lmt;
+        __syncthreads();
     }
-    sweep_regs<N, false, 0>(mt.Smi, v);
-    sweep_regs<N, false, 1>(mt.Smi, v);
-    sweep_regs<N, false, 2>(mt.Smi, v);
-    double* dst = L + t * N3;
+    const auto& Smi = tp->Smi;
+    const int lr = tid / N2, ln = tid % N2;   // local block, line within the block
+    const int64_t row = (int64_t)blockIdx.x * RPB + lr;   // row = c * ncell + e
+    const bool act = lr < RPB && row < 5 * ncell;
+    Real* blk = buf + lr * N3;
+    Real v[N];
+    // x-lines: line ln = a1 + N a2 holds a0 = 0..N-1
+    if (act) {
+        const double* src = R + row * N3 + ln * N;
 #pragma unroll
-    for (int i = 0; i < N3; ++i) dst[i] = (double)v[i];
+        for (int m = 0; m < N; ++m) v[m] = (Real)src[m];
+        apply_line<N, true>(Smi, v);
+#pragma unroll
+        for (int m = 0; m < N; ++m) blk[ln * N + m] = v[m];
+    }
+    __syncthreads();
+    // y-lines: (a0, a2) = (ln % N, ln / N)
+    const int y0 = ln % N, y2 = ln / N;
+    if (act) {
+#pragma unroll
+        for (int m = 0; m < N; ++m) v[m] = blk[y2 * N2 + m * N + y0];
+        apply_line<N, true>(Smi, v);
+#pragma unroll
+        for (int m = 0; m < N; ++m) blk[y2 * N2 + m * N + y0] = v[m];
+    }
+    __syncthreads();
+    // z-lines: (a0, a1) = (ln % N, ln / N); scaling by 1 / (|J| w) at the mass points
+    const int z0 = ln % N, z1 = ln / N;
+    if (act) {
+#pragma unroll
+        for (int m = 0; m < N; ++m) v[m] = blk[m * N2 + z1 * N + z0];
+        apply_line<N, true>(Smi, v);
+        const int64_t e = row % ncell;
+        if constexpr (GEN) {
+            const double* jw = mass_jxw + e * N3 + z1 * N + z0;
+#pragma unroll
+            for (int m = 0; m < N; ++m) v[m] = v[m] / (Real)jw[m * N2];
+        } else {
+            const Real f = Real(1) / ((Real)cell_metric[e * 10 + 9] * lwm[z0] * lwm[z1]);
+#pragma unroll
+            for (int m = 0; m < N; ++m) v[m] = v[m] * (f / tp->wm[m]);
+        }
+        apply_line<N, false>(Smi, v);
+#pragma unroll
+        for (int m = 0; m < N; ++m) blk[m * N2 + z1 * N + z0] = v[m];
+    }
+    __syncthreads();
+    if (act) {
+#pragma unroll
+        for (int m = 0; m < N; ++m) v[m] = blk[y2 * N2 + m * N + y0];
+        apply_line<N, false>(Smi, v);
+#pragma unroll
+        for (int m = 0; m < N; ++m) blk[y2 * N2 + m * N + y0] = v[m];
+    }
+    __syncthreads();
+    if (act) {
+#pragma unroll
+        for (int m = 0; m < N; ++m) v[m] = blk[ln * N + m];
+        apply_line<N, false>(Smi, v);
+        double* dst = L + row * N3 + ln * N;
+#pragma unroll
+        for (int m = 0; m < N; ++m) dst[m] = (double)v[m];
+    }
 }
 
 // ------------------------------------------------------------------ launchers
@@ -1102,17 +1030,10 @@ inline int launch_minv_t(const double* R, double* L, int64_t ncell, const double
         }
         mt.wm[i] = (Real)t.wm[i];
     }
-    if constexpr (N <= DGNS_MINV_REG_MAX_N) {
-        // coefficients in registers
-        const int64_t grid = (5 * ncell + 63) / 64;
-        hipLaunchKernelGGL((inverse_mass_reg_kernel<N, Real, GEN>), dim3((unsigned)grid), dim3(64), 0, st, R, L, ncell,
-                           cm, mj, mt);
-    } else {
-        constexpr int CPB = MinvCells<N, Real>::v;
-        const int64_t grid = (ncell + CPB - 1) / CPB;
-        hipLaunchKernelGGL((inverse_mass_kernel<N, Real, GEN>), dim3((unsigned)grid), dim3(kBlock), 0, st, R, L, ncell,
-                           cm, mj, mt);
-    }
+    constexpr int RPB = kMinvLineBlock / (N * N);
+    const int64_t grid = (5 * ncell + RPB - 1) / RPB;
+    hipLaunchKernelGGL((inverse_mass_line_kernel<N, Real, GEN>), dim3((unsigned)grid), dim3(kMinvLineBlock), 0, st, R,
+                       L, ncell, cm, mj, mt);
     return hipGetLastError() == hipSuccess ? 0 : -1;
 }
 

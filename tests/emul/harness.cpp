@@ -5,8 +5,9 @@
 // usage: harness <in.bin> <out.bin>
 //   in.bin : dgns_params, dgns_box_mesh, uint32 terms, int32 mode, then U (n_dof float64)
 //            and, for mode 2, Rbar (n_dof float64)
-//   mode   : 0 residual R, 1 operator L = M^{-1} R, 2 residual adjoint Ubar = (dR/dU)^T Rbar
-//   out.bin: R, L or Ubar (n_dof float64)
+//   mode   : 0 residual R, 1 operator L = M^{-1} R, 2 residual adjoint Ubar = (dR/dU)^T Rbar,
+//            3 standalone inverse mass M^{-1} U
+//   out.bin: R, L, Ubar or M^{-1} U (n_dof float64)
 #include <cstdio>
 #include <string>
 #include <vector>
@@ -28,6 +29,17 @@ template <int N, int Q>
 int run(const OpArgs& a, const Tables1D& t, int fp32, int gen) {
     if (fp32) return gen ? launch_op_t<N, Q, float, true>(a, t, nullptr) : launch_op_t<N, Q, float, false>(a, t, nullptr);
     return gen ? launch_op_t<N, Q, double, true>(a, t, nullptr) : launch_op_t<N, Q, double, false>(a, t, nullptr);
+}
+
+template <int N>
+int run_minv(const OpArgs& a, const Tables1D& t, int fp32, int gen) {
+    const double* R = a.U;
+    double* L = a.out;
+    if (fp32)
+        return gen ? launch_minv_t<N, float, true>(R, L, a.ncell, a.cell_metric, a.mass_jxw, t, nullptr)
+                   : launch_minv_t<N, float, false>(R, L, a.ncell, a.cell_metric, a.mass_jxw, t, nullptr);
+    return gen ? launch_minv_t<N, double, true>(R, L, a.ncell, a.cell_metric, a.mass_jxw, t, nullptr)
+               : launch_minv_t<N, double, false>(R, L, a.ncell, a.cell_metric, a.mass_jxw, t, nullptr);
 }
 
 }  // namespace
@@ -82,7 +94,9 @@ int main(int argc, char** argv) {
     const int k = prm.degree, q = prm.n_q, fp32 = prm.precision, gen = hs.gen ? 1 : 0;
     rc = -4;
 #define EMU_CASE(K, Q_) \
-    if (k == K && q == Q_) rc = fuse == 2 ? run_adj<K + 1, Q_>(a, Rb.data(), hs.tab, gen) : run<K + 1, Q_>(a, hs.tab, fp32, gen);
+    if (k == K && q == Q_)                                                                                   \
+        rc = fuse == 2 ? run_adj<K + 1, Q_>(a, Rb.data(), hs.tab, gen)                                        \
+                       : (fuse == 3 ? run_minv<K + 1>(a, hs.tab, fp32, gen) : run<K + 1, Q_>(a, hs.tab, fp32, gen));
     EMU_CASES
     if (rc != 0) {
         std::fprintf(stderr, "no emulated kernel for k=%d nq=%d\n", k, q);

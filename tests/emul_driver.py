@@ -54,7 +54,7 @@ class _Mesh(ctypes.Structure):
 
 def run(U, k, nq, n, lo, hi, periodic=(1, 1, 1), kind=0, basis=0, precision=0, gamma=1.4, R=287.0, mu=0.0,
         lam=0.0, rho_ref=1.0, force=(0, 0, 0), wall_T=0.0, amp=0.0, C=1.8, terms=7, fuse=0, Rbar=None):
-    """fuse: 0 residual, 1 operator (with M^{-1}), 2 residual adjoint of Rbar."""
+    """fuse: 0 residual, 1 operator (with M^{-1}), 2 residual adjoint of Rbar, 3 standalone M^{-1} U."""
     exe = build()
     p = _Params(k, nq, basis, precision, gamma, R, mu, lam, rho_ref, (ctypes.c_double * 3)(*force), wall_T)
     m = _Mesh((ctypes.c_int * 3)(*n), (ctypes.c_double * 3)(*lo), (ctypes.c_double * 3)(*hi),

@@ -66,6 +66,27 @@ def test_emulated_channel_walls_and_force():
         assert max(errs) < 1e-12, (t, errs)
 
 
+@pytest.mark.parametrize("n,k,nq,kind,amp,basis,prec", [
+    ((3, 2, 2), 1, 2, 0, 0.0, "LGL", 0),
+    ((2, 2, 2), 2, 3, 2, 0.15, "GL", 0),
+    ((3, 1, 2), 3, 6, 0, 0.0, "LGL", 0),
+    ((1, 2, 2), 3, 6, 2, 0.1, "GL", 1),
+    ((2, 1, 1), 4, 7, 2, 0.1, "LGL", 0),
+    ((2, 1, 1), 7, 11, 0, 0.0, "LGL", 0),
+])
+def test_emulated_standalone_inverse_mass(n, k, nq, kind, amp, basis, prec):
+    # M^{-1} of a seeded vector, checked by its backward error M L - R (cond(M) grows with k)
+    fl, oop, U = _tgv_case(n, k, nq, kind, amp, basis)
+    b = 0 if basis == "LGL" else 1
+    L = ed.run(U.numpy(), k, nq, n, *PI3, kind=kind, amp=amp, basis=b, precision=prec, mu=fl.mu, lam=fl.lam,
+               fuse=3)
+    M = oop.mass_matrices()
+    ML = torch.einsum("eij,cej->cei", M, torch.as_tensor(L))
+    errs = rel_err_fields(ML, U)
+    tol = (1e-5 if prec else 1e-13) * max(1.0, ((k + 1) / 4.0) ** 2)
+    assert max(errs) < tol, errs
+
+
 @pytest.mark.parametrize("n,k,nq", [
     ((2, 2, 2), 3, 6),
     # k = 7, n_q = 11 in float32: one face per face phase, so that two waves per SIMD fit
