@@ -198,7 +198,7 @@ def degree_sweep(target_dofs=10_000_000, calls=20):
     quadrature point (the paper's Cartesian versus deformed comparison, Sec. 5.1.1)."""
     import torch
     from paper_1806_03095_amd import taylor_green
-    qs = {1: (2, 3), 2: (3, 4), 3: (4, 5, 6), 4: (5, 6, 7), 5: (6, 8), 6: (7, 10), 7: (8, 11)}
+    qs = {1: (2, 3), 2: (3, 4, 5), 3: (4, 5, 6, 7), 4: (5, 6, 7, 9), 5: (6, 8), 6: (7, 10), 7: (8, 11)}
     rows = []
     for k, nqs in qs.items():
         ne = max(2, int(round((target_dofs / (5.0 * (k + 1) ** 3)) ** (1.0 / 3.0))))

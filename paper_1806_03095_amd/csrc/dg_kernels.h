@@ -39,7 +39,8 @@ int launch_adjoint_k6(const OpArgs& a, const double* Rb, const Tables1D& t, bool
 int launch_adjoint_k7(const OpArgs& a, const double* Rb, const Tables1D& t, bool gen, hipStream_t st);
 
 // (degree, n_q) pairs with compiled operator kernels
-constexpr int kSupported[][2] = {{1, 2}, {1, 3}, {2, 3}, {2, 4}, {3, 4}, {3, 5}, {3, 6}, {4, 5}, {4, 6}, {4, 7}, {5, 6}, {5, 8}, {6, 7}, {6, 10}, {7, 8}, {7, 11}};
+constexpr int kSupported[][2] = {{1, 2}, {1, 3}, {2, 3}, {2, 4}, {2, 5}, {3, 4}, {3, 5}, {3, 6}, {3, 7}, {4, 5},
+                                 {4, 6}, {4, 7}, {4, 9}, {5, 6}, {5, 8}, {6, 7}, {6, 10}, {7, 8}, {7, 11}};
 
 // LSRK stage update dU <- A dU + dt L; U <- U + B dU (A == 0: dU <- dt L).
 int launch_rk_update(double* U, double* dU, const double* L, int64_t n, double A, double B, double dt, hipStream_t st);

@@ -11,6 +11,8 @@ int launch_operator_k2(const OpArgs& a, const Tables1D& t, bool fp32, bool gen, 
                        : (gen ? launch_op_t<3, 3, double, true>(a, t, st) : launch_op_t<3, 3, double, false>(a, t, st));
         case 4: return fp32 ? (gen ? launch_op_t<3, 4, float, true>(a, t, st) : launch_op_t<3, 4, float, false>(a, t, st))
                        : (gen ? launch_op_t<3, 4, double, true>(a, t, st) : launch_op_t<3, 4, double, false>(a, t, st));
+        case 5: return fp32 ? (gen ? launch_op_t<3, 5, float, true>(a, t, st) : launch_op_t<3, 5, float, false>(a, t, st))
+                       : (gen ? launch_op_t<3, 5, double, true>(a, t, st) : launch_op_t<3, 5, double, false>(a, t, st));
         default: return 1;
     }
 }
@@ -27,6 +29,7 @@ int launch_adjoint_k2(const OpArgs& a, const double* Rb, const Tables1D& t, bool
     switch (t.q) {
         case 3: return gen ? launch_adjoint_t<3, 3, true>(a, Rb, t, st) : launch_adjoint_t<3, 3, false>(a, Rb, t, st);
         case 4: return gen ? launch_adjoint_t<3, 4, true>(a, Rb, t, st) : launch_adjoint_t<3, 4, false>(a, Rb, t, st);
+        case 5: return gen ? launch_adjoint_t<3, 5, true>(a, Rb, t, st) : launch_adjoint_t<3, 5, false>(a, Rb, t, st);
         default: return 1;
     }
 }
@@ -35,6 +38,7 @@ int launch_diagnostics_k2(const OpArgs& a, const Tables1D& t, const double* L, d
     switch (t.q) {
         case 3: return gen ? launch_diag_t<3, 3, true>(a, t, L, partial, st) : launch_diag_t<3, 3, false>(a, t, L, partial, st);
         case 4: return gen ? launch_diag_t<3, 4, true>(a, t, L, partial, st) : launch_diag_t<3, 4, false>(a, t, L, partial, st);
+        case 5: return gen ? launch_diag_t<3, 5, true>(a, t, L, partial, st) : launch_diag_t<3, 5, false>(a, t, L, partial, st);
         default: return 1;
     }
 }
@@ -43,6 +47,7 @@ int launch_ke_vjp_k2(const OpArgs& a, const Tables1D& t, double* Ub, bool gen, h
     switch (t.q) {
         case 3: return gen ? launch_ke_vjp_t<3, 3, true>(a, t, Ub, st) : launch_ke_vjp_t<3, 3, false>(a, t, Ub, st);
         case 4: return gen ? launch_ke_vjp_t<3, 4, true>(a, t, Ub, st) : launch_ke_vjp_t<3, 4, false>(a, t, Ub, st);
+        case 5: return gen ? launch_ke_vjp_t<3, 5, true>(a, t, Ub, st) : launch_ke_vjp_t<3, 5, false>(a, t, Ub, st);
         default: return 1;
     }
 }

@@ -13,6 +13,8 @@ int launch_operator_k3(const OpArgs& a, const Tables1D& t, bool fp32, bool gen, 
                        : (gen ? launch_op_t<4, 5, double, true>(a, t, st) : launch_op_t<4, 5, double, false>(a, t, st));
         case 6: return fp32 ? (gen ? launch_op_t<4, 6, float, true>(a, t, st) : launch_op_t<4, 6, float, false>(a, t, st))
                        : (gen ? launch_op_t<4, 6, double, true>(a, t, st) : launch_op_t<4, 6, double, false>(a, t, st));
+        case 7: return fp32 ? (gen ? launch_op_t<4, 7, float, true>(a, t, st) : launch_op_t<4, 7, float, false>(a, t, st))
+                       : (gen ? launch_op_t<4, 7, double, true>(a, t, st) : launch_op_t<4, 7, double, false>(a, t, st));
         default: return 1;
     }
 }
@@ -30,6 +32,7 @@ int launch_adjoint_k3(const OpArgs& a, const double* Rb, const Tables1D& t, bool
         case 4: return gen ? launch_adjoint_t<4, 4, true>(a, Rb, t, st) : launch_adjoint_t<4, 4, false>(a, Rb, t, st);
         case 5: return gen ? launch_adjoint_t<4, 5, true>(a, Rb, t, st) : launch_adjoint_t<4, 5, false>(a, Rb, t, st);
         case 6: return gen ? launch_adjoint_t<4, 6, true>(a, Rb, t, st) : launch_adjoint_t<4, 6, false>(a, Rb, t, st);
+        case 7: return gen ? launch_adjoint_t<4, 7, true>(a, Rb, t, st) : launch_adjoint_t<4, 7, false>(a, Rb, t, st);
         default: return 1;
     }
 }
@@ -39,6 +42,7 @@ int launch_diagnostics_k3(const OpArgs& a, const Tables1D& t, const double* L, d
         case 4: return gen ? launch_diag_t<4, 4, true>(a, t, L, partial, st) : launch_diag_t<4, 4, false>(a, t, L, partial, st);
         case 5: return gen ? launch_diag_t<4, 5, true>(a, t, L, partial, st) : launch_diag_t<4, 5, false>(a, t, L, partial, st);
         case 6: return gen ? launch_diag_t<4, 6, true>(a, t, L, partial, st) : launch_diag_t<4, 6, false>(a, t, L, partial, st);
+        case 7: return gen ? launch_diag_t<4, 7, true>(a, t, L, partial, st) : launch_diag_t<4, 7, false>(a, t, L, partial, st);
         default: return 1;
     }
 }
@@ -48,6 +52,7 @@ int launch_ke_vjp_k3(const OpArgs& a, const Tables1D& t, double* Ub, bool gen, h
         case 4: return gen ? launch_ke_vjp_t<4, 4, true>(a, t, Ub, st) : launch_ke_vjp_t<4, 4, false>(a, t, Ub, st);
         case 5: return gen ? launch_ke_vjp_t<4, 5, true>(a, t, Ub, st) : launch_ke_vjp_t<4, 5, false>(a, t, Ub, st);
         case 6: return gen ? launch_ke_vjp_t<4, 6, true>(a, t, Ub, st) : launch_ke_vjp_t<4, 6, false>(a, t, Ub, st);
+        case 7: return gen ? launch_ke_vjp_t<4, 7, true>(a, t, Ub, st) : launch_ke_vjp_t<4, 7, false>(a, t, Ub, st);
         default: return 1;
     }
 }

@@ -13,6 +13,8 @@ int launch_operator_k4(const OpArgs& a, const Tables1D& t, bool fp32, bool gen, 
                        : (gen ? launch_op_t<5, 6, double, true>(a, t, st) : launch_op_t<5, 6, double, false>(a, t, st));
         case 7: return fp32 ? (gen ? launch_op_t<5, 7, float, true>(a, t, st) : launch_op_t<5, 7, float, false>(a, t, st))
                        : (gen ? launch_op_t<5, 7, double, true>(a, t, st) : launch_op_t<5, 7, double, false>(a, t, st));
+        case 9: return fp32 ? (gen ? launch_op_t<5, 9, float, true>(a, t, st) : launch_op_t<5, 9, float, false>(a, t, st))
+                       : (gen ? launch_op_t<5, 9, double, true>(a, t, st) : launch_op_t<5, 9, double, false>(a, t, st));
         default: return 1;
     }
 }
@@ -30,6 +32,7 @@ int launch_adjoint_k4(const OpArgs& a, const double* Rb, const Tables1D& t, bool
         case 5: return gen ? launch_adjoint_t<5, 5, true>(a, Rb, t, st) : launch_adjoint_t<5, 5, false>(a, Rb, t, st);
         case 6: return gen ? launch_adjoint_t<5, 6, true>(a, Rb, t, st) : launch_adjoint_t<5, 6, false>(a, Rb, t, st);
         case 7: return gen ? launch_adjoint_t<5, 7, true>(a, Rb, t, st) : launch_adjoint_t<5, 7, false>(a, Rb, t, st);
+        case 9: return gen ? launch_adjoint_t<5, 9, true>(a, Rb, t, st) : launch_adjoint_t<5, 9, false>(a, Rb, t, st);
         default: return 1;
     }
 }
@@ -39,6 +42,7 @@ int launch_diagnostics_k4(const OpArgs& a, const Tables1D& t, const double* L, d
         case 5: return gen ? launch_diag_t<5, 5, true>(a, t, L, partial, st) : launch_diag_t<5, 5, false>(a, t, L, partial, st);
         case 6: return gen ? launch_diag_t<5, 6, true>(a, t, L, partial, st) : launch_diag_t<5, 6, false>(a, t, L, partial, st);
         case 7: return gen ? launch_diag_t<5, 7, true>(a, t, L, partial, st) : launch_diag_t<5, 7, false>(a, t, L, partial, st);
+        case 9: return gen ? launch_diag_t<5, 9, true>(a, t, L, partial, st) : launch_diag_t<5, 9, false>(a, t, L, partial, st);
         default: return 1;
     }
 }
@@ -48,6 +52,7 @@ int launch_ke_vjp_k4(const OpArgs& a, const Tables1D& t, double* Ub, bool gen, h
         case 5: return gen ? launch_ke_vjp_t<5, 5, true>(a, t, Ub, st) : launch_ke_vjp_t<5, 5, false>(a, t, Ub, st);
         case 6: return gen ? launch_ke_vjp_t<5, 6, true>(a, t, Ub, st) : launch_ke_vjp_t<5, 6, false>(a, t, Ub, st);
         case 7: return gen ? launch_ke_vjp_t<5, 7, true>(a, t, Ub, st) : launch_ke_vjp_t<5, 7, false>(a, t, Ub, st);
+        case 9: return gen ? launch_ke_vjp_t<5, 9, true>(a, t, Ub, st) : launch_ke_vjp_t<5, 9, false>(a, t, Ub, st);
         default: return 1;
     }
 }

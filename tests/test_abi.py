@@ -46,7 +46,7 @@ def _mesh(**kw):
     (dict(degree=0), {}, binding.EINVAL),
     (dict(degree=8), {}, binding.EINVAL),
     (dict(n_q=0), {}, binding.EINVAL),
-    (dict(n_q=9), {}, binding.EUNSUPPORTED),
+    (dict(n_q=10), {}, binding.EUNSUPPORTED),
     (dict(basis=5), {}, binding.EINVAL),
     (dict(precision=3), {}, binding.EINVAL),
     (dict(gamma=1.0), {}, binding.EINVAL),

@@ -96,6 +96,10 @@ CASES = [
     ((2, 2, 2), 5, 8, "affine", 0.0, "LGL"),
     ((2, 1, 2), 7, 11, "affine", 0.0, "LGL"),
     ((1, 2, 2), 7, 11, "curved", 0.1, "LGL"),
+    # n_q = 2k+1
+    ((2, 2, 2), 2, 5, "curved", 0.1, "LGL"),
+    ((2, 2, 1), 3, 7, "affine", 0.0, "GL"),
+    ((2, 1, 1), 4, 9, "curved", 0.1, "LGL"),
     # degenerate meshes: one cell per direction is its own periodic neighbour
     ((1, 1, 1), 2, 4, "affine", 0.0, "LGL"),
     ((1, 1, 1), 3, 6, "curved", 0.1, "GL"),
