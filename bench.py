@@ -159,6 +159,35 @@ def channel_throughput(calls):
     return res
 
 
+def graph_timing(steps=50):
+    """RK steps on the small Taylor-Green meshes (4^3 and 8^3 cells, k=3, n_q=6), launched
+    eagerly from Python one rk_step at a time and as one HIP graph of `steps` steps: on
+    meshes this small the host-side launch cost, not the kernels, sets the step rate."""
+    import torch
+    from paper_1806_03095_amd import taylor_green
+    res = {}
+    for ne in (4, 8):
+        op = taylor_green(3, ne, 6)
+        U = op.project_ic("taylor_green", [1.0, 1.0, 0.1, 1.0])
+        work = torch.empty(2 * op.n_dof, dtype=torch.float64, device="cuda")
+        dt = op.compute_dt(CR, 0.02, 1.5, 3.0, 1.0, 0.1)
+        t_eager, _ = time_rk(op, U, work, dt, steps, 5)
+        g = op.rk_graph(U, work, dt, steps)
+        g.replay()
+        torch.cuda.synchronize()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        g.replay()
+        e1.record()
+        torch.cuda.synchronize()
+        t_graph = e0.elapsed_time(e1) / 1e3
+        res["taylor_green_%dcubed_k3_nq6" % ne] = {"n_dof": op.n_dof, "eager_us_per_step": 1e6 * t_eager / steps,
+                                                   "graph_us_per_step": 1e6 * t_graph / steps}
+        del g
+        op.close()
+    return res
+
+
 def adjoint_timing():
     """The differentiation workload: gradient of the kinetic energy after 50 RK steps
     with respect to the initial state (Taylor-Green 16^3 cells, k=3, n_q=6, float64),
@@ -398,6 +427,7 @@ def main():
                                  "operator_hbm_frac_of_copy": BYTES_PER_DOF * ndof / t_op / bw}
         out["channel"] = channel_throughput(max(args.op_calls // 4, 10))
         out["adjoint"] = adjoint_timing()
+        out["hip_graph"] = graph_timing()
         log("operations: " + ", ".join("%s %.1f us" % (n, v["us"]) for n, v in out["operations"].items()))
         log("copy %.2f TB/s; channel fp64 %.3e DoF/s" % (bw / 1e12, out["channel"]["fp64"]["dofs_per_s"]))
 

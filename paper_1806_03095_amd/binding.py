@@ -183,6 +183,19 @@ class Operator:
         _check(self.lib.dgns_rk_step(self.h, _ptr(U), _ptr(work), t, dt))
         return U
 
+    def rk_graph(self, U, work, dt, steps=1):
+        """Captures `steps` rk_step calls on U (in place, work as in rk_step) into a HIP
+        graph (torch.cuda.CUDAGraph): each replay() advances U by `steps` steps with one
+        launch from the host.  U and work must stay allocated while the graph is used."""
+        self._vec(U, "U")
+        if not (work.is_cuda and work.dtype == torch.float64 and work.is_contiguous() and work.numel() >= 2 * self.n_dof):
+            raise ValueError("work must be a contiguous float64 CUDA tensor of >= 2 n_dof entries")
+        g = torch.cuda.CUDAGraph()
+        with torch.cuda.graph(g):
+            for s in range(int(steps)):
+                self.rk_step(U, work, s * dt, dt)
+        return g
+
     def rk_stage_update(self, U, dU, L, stage, dt):
         """The stage-`stage` vector update alone: dU <- A dU + dt L, U <- U + B dU (in place)."""
         for t, name in ((U, "U"), (dU, "dU"), (L, "L")):
