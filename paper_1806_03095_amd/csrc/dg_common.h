@@ -31,7 +31,8 @@ struct Tables1D {
 };
 
 // Exactly sized copy in the operator's working precision, passed by value as a
-// kernel argument so that every entry is a wave-uniform (scalar) operand.
+// kernel argument; the kernels copy it to LDS where it fits (held in scalar
+// registers for a whole kernel, the larger tables spill).
 template <int N, int Q, typename Real>
 struct KTab {
     Real S[Q][N];

@@ -21,12 +21,14 @@
 // Work organisation: a workgroup of B threads; every phase is a cooperative loop
 // over independent items (lines of a sweep, quadrature points) separated by
 // barriers.  The cell's quadrature points are processed in chunks of P planes
-// along xi_2; the faces in two groups (the three faces xi_d = 0, then the three
-// faces xi_d = 1), each phase covering all three faces of a group.  The sweep
-// along the second tangential direction of a face is fused into the pointwise
-// flux phase (each face point contracts its own line), so no n_q^2 intermediate
-// is stored.  LDS holds sU[5][N^3] (own coefficients), sR[5][N^3] (residual) and
-// a work area sized for the largest phase.
+// along xi_2; the faces in groups (the three faces xi_d = 0, then the three faces
+// xi_d = 1, each phase covering all three faces of a group; or one face per group
+// where the LDS plan asks for it, see OpSizes).  The sweep along the second
+// tangential direction of a face is fused into the pointwise flux phase (each face
+// point contracts its own line), so no n_q^2 intermediate is stored.  LDS holds
+// sU[5][N^3] (own coefficients), sR[5][N^3] (residual), copies of the 1D tables
+// and a work area sized for the largest phase.  With a Runge-Kutta stage attached
+// (OpArgs::rk), the epilogue applies the stage update instead of writing L.
 
 #pragma once
 
