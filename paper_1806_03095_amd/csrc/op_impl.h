@@ -578,6 +578,23 @@ dg_operator_kernel(OpArgs a, KTab<N, Q, Real> tb, MTab<N, Real> mt) {
         sU[i] = (Real)a.U[c * cstride + e * N3 + j];
         sR[i] = Real(0);
     }
+    // Fused Runge-Kutta stage: in the 128-thread float64 kernels (k <= 3), whose register
+    // budget has the room for a thread's share of the cell's dU (at most three values),
+    // load it now, so that its latency overlaps the whole evaluation instead of the
+    // epilogue's.
+    constexpr int B = OpBlock<N, Q, Real>::threads;
+    constexpr int RKV = (5 * N3 + B - 1) / B;
+    constexpr bool RK_PREFETCH = RKV <= 3 && B == 128 && sizeof(Real) == sizeof(double);
+    double dU_old[RK_PREFETCH ? RKV : 1];
+    if constexpr (RK_PREFETCH) {
+        if (a.rk.dU && a.rk.A != 0.0) {
+#pragma unroll
+            for (int v = 0; v < RKV; ++v) {
+                const int i = tid + v * B;
+                dU_old[v] = i < 5 * N3 ? a.rk.dU[(i / N3) * cstride + e * N3 + i % N3] : 0.0;
+            }
+        }
+    }
     // LDS copy of the 1D tables when it fits beside the work arrays (otherwise the
     // kernel argument is read directly).  Reading every table entry from LDS keeps
     // the tables out of the scalar registers: held there for the whole kernel they
@@ -863,14 +880,29 @@ dg_operator_kernel(OpArgs a, KTab<N, Q, Real> tb, MTab<N, Real> mt) {
     if (a.fuse_minv) inverse_mass_lds<N, Real, GEN>(lm, lwm, sR, sW, detJ, jxw_m);
 
     if (a.rk.dU) {
-        // fused Runge-Kutta stage on the cell's own DoFs (U re-read in float64)
+        // fused Runge-Kutta stage on the cell's own DoFs; the old state comes from sU when
+        // that holds it exactly (float64), else it is re-read
         const bool first = a.rk.A == 0.0;
-        for (int i = tid; i < 5 * N3; i += nth) {
-            const int c = i / N3, j = i % N3;
-            const int64_t g = c * cstride + e * N3 + j;
-            const double d = rk_increment(first, a.rk.A, first ? 0.0 : a.rk.dU[g], a.rk.dt, (double)sR[i]);
-            a.rk.dU[g] = d;
-            a.rk.U_out[g] = rk_advance(a.U[g], a.rk.B, d);
+        if constexpr (RK_PREFETCH) {
+#pragma unroll
+            for (int v = 0; v < RKV; ++v) {
+                const int i = tid + v * B;
+                if (i < 5 * N3) {
+                    const int64_t g = (i / N3) * cstride + e * N3 + i % N3;
+                    const double u = sizeof(Real) == sizeof(double) ? (double)sU[i] : a.U[g];
+                    const double d = rk_increment(first, a.rk.A, first ? 0.0 : dU_old[v], a.rk.dt, (double)sR[i]);
+                    a.rk.dU[g] = d;
+                    a.rk.U_out[g] = rk_advance(u, a.rk.B, d);
+                }
+            }
+        } else {
+            for (int i = tid; i < 5 * N3; i += nth) {
+                const int64_t g = (i / N3) * cstride + e * N3 + i % N3;
+                const double u = sizeof(Real) == sizeof(double) ? (double)sU[i] : a.U[g];
+                const double d = rk_increment(first, a.rk.A, first ? 0.0 : a.rk.dU[g], a.rk.dt, (double)sR[i]);
+                a.rk.dU[g] = d;
+                a.rk.U_out[g] = rk_advance(u, a.rk.B, d);
+            }
         }
     } else {
         for (int i = tid; i < 5 * N3; i += nth) {
