@@ -161,6 +161,14 @@ def channel_throughput(calls):
         L = torch.empty_like(U)
         t = time_call(lambda: op.apply(U, L), calls)
         res[prec] = {"us": 1e6 * t, "dofs_per_s": op.n_dof / t}
+        if prec == "fp64":
+            # wall-normal statistics profile (synchronous call: host wall time)
+            op.channel_statistics(U)
+            w0 = time.perf_counter()
+            for _ in range(10):
+                st = op.channel_statistics(U)
+            res["statistics_us_per_call"] = 1e6 * (time.perf_counter() - w0) / 10
+            res["statistics_points"] = int(st.shape[0])
         op.close()
     res["workload"] = "channel_16cubed_k4_nq7_tanh1.8"
     return res

@@ -187,6 +187,19 @@ int dgns_apply_operator_vjp(dgns_ctx* ctx, const double* U, const double* Lbar, 
 int dgns_rk_step_vjp(dgns_ctx* ctx, const double* U_n, double t, double dt, const double* Ubar_np1,
                      double* Ubar_n, double* work);
 
+/* Profiles of the channel-flow statistics (Sec. 5.3: averages over the homogeneous
+ * directions x and z).  At each of the n[1]*n_q wall-normal Gauss points y_{j,p} (cell
+ * row j in direction 1, point p of the n_q rule) the averages over the plane of
+ * constant y (all cells of row j, all (x, z) Gauss points, weighted by |det J| w) of
+ * rho, u, v, w, uu, vv, ww, uv with (u, v, w) = (rho u)/rho.  Time averages and the
+ * Reynolds stresses <u'v'> = <uv> - <u><v> are left to the caller.
+ * U: device, n_dof doubles.  out: HOST array of n[1]*n_q*9 doubles owned by the
+ * caller, rows [y, rho, u, v, w, uu, vv, ww, uv] ordered by j, then p.  Synchronous.
+ * Needs planes of constant y: affine or channel mesh, else DGNS_EUNSUPPORTED;
+ * DGNS_ENOMEM if the first call cannot allocate its 9*n_q*(n_cells + n[1]) doubles of
+ * device buffer (kept for later calls); DGNS_ENONFINITE for a non-finite average. */
+int dgns_channel_statistics(dgns_ctx* ctx, const double* U, double* out);
+
 /* K = int |u|^2/2 over the domain (n_q rule, u = (rho u)/rho), returned to the
  * host (synchronises the stream); DGNS_ENONFINITE if not finite. */
 int dgns_kinetic_energy(dgns_ctx* ctx, const double* U, double* ke);

@@ -49,3 +49,33 @@ def diagnostics(op, U, L=None):
     out["eps"] *= fl.nu / V
     out["rate"] = out["rate"] / V if L is not None else float("nan")
     return out
+
+
+def channel_statistics(op, U):
+    """Plane averages for the statistics of the channel flow (Sec. 5.3), where x and z
+    are homogeneous: for each wall-normal Gauss point (cell row j in direction 1, point
+    p of the n_q rule) the |det J| w weighted averages over all cells of the row and all
+    (x, z) Gauss points of y, rho, u, v, w, uu, vv, ww, uv with u = (rho u)/rho.
+
+    Returns an (n[1] * n_q, 9) array, rows ordered by j, then p.  Meant for meshes on
+    which y depends on the second reference coordinate alone (box and channel)."""
+    m = op.mesh
+    nx, ny, nz = m.n
+    q = op.n_q
+    py = (np.arange(q ** 3) // q) % q       # point p = px + q (py + q pz)
+    out = np.zeros((ny * q, 9))
+    for j in range(ny):
+        cells = np.array([i + nx * (j + ny * k) for k in range(nz) for i in range(nx)], dtype=np.int64)
+        x, _, detJ = op._geometry(cells, op.cell_pts)
+        w = (detJ * torch.as_tensor(op.cell_w)).numpy()                 # [E, P]
+        Uq = torch.einsum("pi,cei->epc", op.Phi, U[:, cells, :]).numpy()  # [E, P, 5]
+        rho = Uq[..., 0]
+        u = Uq[..., 1:4] / rho[..., None]
+        x = np.asarray(x)
+        fields = [x[..., 1], rho, u[..., 0], u[..., 1], u[..., 2],
+                  u[..., 0] * u[..., 0], u[..., 1] * u[..., 1], u[..., 2] * u[..., 2], u[..., 0] * u[..., 1]]
+        for p in range(q):
+            sel = py == p
+            ws = w[:, sel]
+            out[j * q + p] = [float((f[:, sel] * ws).sum() / ws.sum()) for f in fields]
+    return out

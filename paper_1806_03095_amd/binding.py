@@ -44,7 +44,7 @@ class BoxMesh(ctypes.Structure):
 
 EXPORTS = ["dgns_last_error", "dgns_create", "dgns_destroy", "dgns_sizes", "dgns_set_stream",
            "dgns_apply_residual", "dgns_apply_inverse_mass", "dgns_apply_operator", "dgns_rk_step",
-           "dgns_rk_stage_update", "dgns_compute_dt", "dgns_diagnostics", "dgns_project_ic", "dgns_apply_residual_vjp",
+           "dgns_rk_stage_update", "dgns_compute_dt", "dgns_channel_statistics", "dgns_diagnostics", "dgns_project_ic", "dgns_apply_residual_vjp",
            "dgns_apply_operator_vjp", "dgns_rk_step_vjp", "dgns_kinetic_energy", "dgns_kinetic_energy_vjp"]
 
 _lib = None
@@ -70,6 +70,7 @@ def load_library(path=LIB_PATH):
     lib.dgns_apply_operator.argtypes = [vp, vp, vp, ctypes.c_double]
     lib.dgns_rk_step.argtypes = [vp, vp, vp, ctypes.c_double, ctypes.c_double]
     lib.dgns_rk_stage_update.argtypes = [vp, vp, vp, vp, ctypes.c_int, ctypes.c_double]
+    lib.dgns_channel_statistics.argtypes = [vp, vp, ctypes.POINTER(ctypes.c_double)]
     lib.dgns_compute_dt.argtypes = [vp] + [ctypes.c_double] * 6 + [dp]
     lib.dgns_diagnostics.argtypes = [vp, vp, vp, dp]
     lib.dgns_project_ic.argtypes = [vp, ctypes.c_int, dp, vp, vp]
@@ -108,6 +109,7 @@ class Operator:
             raise RuntimeError("the DG operator runs on the GPU only; no GPU is visible")
         self.lib = lib
         self.degree, self.n_q = int(degree), int(n_q)
+        self.n = tuple(int(v) for v in n)
         p = Params(self.degree, self.n_q, BASIS[basis], PRECISION[precision], gamma, R, mu, lam, rho_ref,
                    (ctypes.c_double * 3)(*body_force), wall_T)
         m = BoxMesh((ctypes.c_int * 3)(*n), (ctypes.c_double * 3)(*lo), (ctypes.c_double * 3)(*hi),
@@ -182,6 +184,16 @@ class Operator:
         self._bind()
         _check(self.lib.dgns_rk_step(self.h, _ptr(U), _ptr(work), t, dt))
         return U
+
+    def channel_statistics(self, U):
+        """Plane averages at the wall-normal Gauss points: a (n[1] * n_q, 9) numpy array with
+        columns y, rho, u, v, w, uu, vv, ww, uv (rows by cell row, then point)."""
+        import numpy as np
+        self._vec(U, "U")
+        self._bind()
+        out = np.empty((self.n[1] * self.n_q, 9), dtype=np.float64)
+        _check(self.lib.dgns_channel_statistics(self.h, _ptr(U), out.ctypes.data_as(ctypes.POINTER(ctypes.c_double))))
+        return out
 
     def rk_graph(self, U, work, dt, steps=1):
         """Captures `steps` rk_step calls on U (in place, work as in rk_step) into a HIP

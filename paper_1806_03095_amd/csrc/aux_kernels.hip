@@ -98,6 +98,30 @@ int launch_diag_total(const double* partial, int64_t ncell, double* total, hipSt
     return hipGetLastError() == hipSuccess ? 0 : -1;
 }
 
+// Totals of the channel statistics over each plane of cells: thread (j, p, m) sums
+// quantity m at wall-normal point p over the cells (i, j, k) of row j in a fixed order.
+constexpr int kChanStats = 9;
+__global__ void __launch_bounds__(256) chan_stats_total_kernel(const double* partial, int n0, int n1, int n2, int q,
+                                                             double* total) {
+    const int t = blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= n1 * q * kChanStats) return;
+    const int m = t % kChanStats, p = (t / kChanStats) % q, j = t / (kChanStats * q);
+    double s = 0;
+    for (int k = 0; k < n2; ++k)
+        for (int i = 0; i < n0; ++i) {
+            const int64_t e = i + (int64_t)n0 * (j + (int64_t)n1 * k);
+            s += partial[(e * q + p) * kChanStats + m];
+        }
+    total[t] = s;
+}
+
+int launch_chan_stats_total(const double* partial, const int n[3], int q, double* total, hipStream_t st) {
+    const int nt = n[1] * q * kChanStats;
+    hipLaunchKernelGGL(chan_stats_total_kernel, dim3((unsigned)((nt + 255) / 256)), dim3(256), 0, st, partial, n[0], n[1],
+                       n[2], q, total);
+    return hipGetLastError() == hipSuccess ? 0 : -1;
+}
+
 // ------------------------------------------------------------------ initial states
 __device__ inline void initial_state(int ic, const double* q, double gamma, double R, const double x[3], double U[5]) {
     double rho, u[3], p;

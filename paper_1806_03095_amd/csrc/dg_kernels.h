@@ -57,6 +57,17 @@ int launch_diagnostics_k7(const OpArgs& a, const Tables1D& t, const double* L, d
 // Deterministic totals of the nine per-cell partial sums.
 int launch_diag_total(const double* partial, int64_t ncell, double* total, hipStream_t st);
 
+// Channel statistics: per cell and wall-normal Gauss point, nine weighted sums (see
+// diag_impl.h); then their totals over each plane of cells (n[1] * n_q * 9 values).
+int launch_chan_stats_k1(const OpArgs& a, const Tables1D& t, double* partial, bool gen, hipStream_t st);
+int launch_chan_stats_k2(const OpArgs& a, const Tables1D& t, double* partial, bool gen, hipStream_t st);
+int launch_chan_stats_k3(const OpArgs& a, const Tables1D& t, double* partial, bool gen, hipStream_t st);
+int launch_chan_stats_k4(const OpArgs& a, const Tables1D& t, double* partial, bool gen, hipStream_t st);
+int launch_chan_stats_k5(const OpArgs& a, const Tables1D& t, double* partial, bool gen, hipStream_t st);
+int launch_chan_stats_k6(const OpArgs& a, const Tables1D& t, double* partial, bool gen, hipStream_t st);
+int launch_chan_stats_k7(const OpArgs& a, const Tables1D& t, double* partial, bool gen, hipStream_t st);
+int launch_chan_stats_total(const double* partial, const int n[3], int q, double* total, hipStream_t st);
+
 // L2 projection right-hand side of an analytic initial state, U_rhs = (phi_i, U0).
 int launch_ic_rhs(const OpArgs& a, const Tables1D& t, const Tables1D* t_dev, const double* geo_nodes, int ic,
                   const double* icp, double* out, bool gen, hipStream_t st);

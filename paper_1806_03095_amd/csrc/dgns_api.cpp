@@ -68,6 +68,7 @@ struct dgns_ctx {
     double* d_total = nullptr;
     Tables1D* d_tab = nullptr;
     double* d_scratch = nullptr;   // n_dof doubles, allocated on the first operator VJP
+    double* d_stats = nullptr;     // channel statistics partial sums and totals, on first use
 };
 
 namespace {
@@ -90,6 +91,7 @@ void free_ctx(dgns_ctx* c) {
     hipFree(c->d_total);
     hipFree(c->d_tab);
     hipFree(c->d_scratch);
+    hipFree(c->d_stats);
 }
 
 OpArgs make_args(const dgns_ctx* c, const double* U, double* out, unsigned terms, int fuse) {
@@ -422,6 +424,54 @@ int dgns_apply_residual_vjp(dgns_ctx* c, const double* U, const double* Rbar, do
         return fail(DGNS_EINVAL, "Ubar overlaps an input");
     if (term_mask & ~DGNS_TERM_ALL) return fail(DGNS_EINVAL, "unknown term bits");
     return dispatch_adjoint(c, make_args(c, U, Ubar, term_mask, 0), Rbar);
+}
+
+int dgns_channel_statistics(dgns_ctx* c, const double* U, double* out) {
+    if (!c || !U || !out) return fail(DGNS_EINVAL, "null argument");
+    if (!aligned8(U)) return fail(DGNS_EINVAL, "U must be 8-byte aligned");
+    if (c->msh.kind == DGNS_MESH_CURVED)
+        return fail(DGNS_EUNSUPPORTED, "channel statistics need planes of constant y (affine or channel mesh)");
+    const int q = c->q, n1 = c->msh.n[1];
+    const int64_t np = c->ncell * q * 9, nt = (int64_t)n1 * q * 9;
+    if (!c->d_stats && hipMalloc((void**)&c->d_stats, sizeof(double) * (np + nt)) != hipSuccess) {
+        c->d_stats = nullptr;
+        return fail(DGNS_ENOMEM, "channel statistics buffer (%lld doubles)", (long long)(np + nt));
+    }
+    OpArgs a = make_args(c, U, nullptr, 0, 0);
+    int rc = 1;
+    switch (c->k) {
+        case 1: rc = launch_chan_stats_k1(a, c->tab, c->d_stats, c->gen, c->stream); break;
+        case 2: rc = launch_chan_stats_k2(a, c->tab, c->d_stats, c->gen, c->stream); break;
+        case 3: rc = launch_chan_stats_k3(a, c->tab, c->d_stats, c->gen, c->stream); break;
+        case 4: rc = launch_chan_stats_k4(a, c->tab, c->d_stats, c->gen, c->stream); break;
+        case 5: rc = launch_chan_stats_k5(a, c->tab, c->d_stats, c->gen, c->stream); break;
+        case 6: rc = launch_chan_stats_k6(a, c->tab, c->d_stats, c->gen, c->stream); break;
+        case 7: rc = launch_chan_stats_k7(a, c->tab, c->d_stats, c->gen, c->stream); break;
+    }
+    if (rc == 1) return fail(DGNS_EUNSUPPORTED, "no statistics kernel for degree %d, n_q %d", c->k, c->q);
+    if (rc == 0) rc = launch_chan_stats_total(c->d_stats, c->msh.n, q, c->d_stats + np, c->stream);
+    if (rc != 0) return fail(DGNS_EHIP, "channel statistics launch failed");
+    std::vector<double> tot(nt);
+    HIP_TRY(hipMemcpyAsync(tot.data(), c->d_stats + np, sizeof(double) * nt, hipMemcpyDeviceToHost, c->stream));
+    HIP_TRY(hipStreamSynchronize(c->stream));
+    // y of the wall-normal points: the geometry interpolant of cell row j along xi_1
+    // (y depends on xi_1 alone on these meshes), read from the first cell of the row
+    const int N = c->n;
+    for (int j = 0; j < n1; ++j) {
+        const int64_t e = (int64_t)c->msh.n[0] * j;
+        const double* g = c->geo.data() + (e * 3 + 1) * c->n3;
+        for (int p = 0; p < q; ++p) {
+            double y = 0;
+            for (int i = 0; i < N; ++i) y += g[N * i] * c->tab.Sg[p][i];
+            const double* t = tot.data() + ((int64_t)j * q + p) * 9;
+            double* o = out + ((int64_t)j * q + p) * 9;
+            o[0] = y;
+            for (int m = 1; m < 9; ++m) o[m] = t[m] / t[0];
+            for (int m = 0; m < 9; ++m)
+                if (!std::isfinite(o[m])) return fail(DGNS_ENONFINITE, "statistic %d at row %d, point %d is not finite", m, j, p);
+        }
+    }
+    return DGNS_OK;
 }
 
 static int ensure_scratch(dgns_ctx* c) {

@@ -311,6 +311,98 @@ ke_vjp_kernel(OpArgs a, double* Ub, KTab<N, Q, double> tb) {
     }
 }
 
+// Channel statistics (Sec. 5.3: averages over the homogeneous directions x, z).  Per
+// cell and wall-normal Gauss point p_y, the |det J| w weighted sums over the (p_x, p_z)
+// points of [1, rho, u, v, w, uu, vv, ww, uv], u = (rho u)/rho, written to
+// partial[(e * Q + p_y) * kStats + m].  Values at the points by the z / y / x sweeps;
+// each thread sums one (p_y, p_z) line over p_x, then one (p_y, m) over p_z (fixed order).
+constexpr int kStats = 9;
+
+template <int N, int Q, bool GEN>
+__global__ void __launch_bounds__(kDiagBlock)
+chan_stats_kernel(OpArgs a, double* partial, KTab<N, Q, double> tb) {
+    constexpr int N2 = N * N, N3 = N2 * N, Q2 = Q * Q, Q3 = Q2 * Q;
+    __shared__ double sX[4 * N3];          // rho, m
+    __shared__ double sA[4 * Q * N2];      // z-swept [c][pz][a1 a0]
+    __shared__ double sB[4 * Q2 * N];      // y-swept [c][pz][py][a0]
+    __shared__ double sP[kStats * Q2];     // line sums [m][py][pz]
+    __shared__ KTab<N, Q, double> lt;
+    const int64_t e = blockIdx.x;
+    const int tid = threadIdx.x, nth = blockDim.x;
+    const int64_t cs = a.ncell * N3;
+    for (int i = tid; i < 4 * N3; i += nth) sX[i] = a.U[(i / N3) * cs + e * N3 + i % N3];
+    copy_table<KTab<N, Q, double>, double>(tb, lt);
+    __syncthreads();
+    for (int it = tid; it < 4 * N2; it += nth) {
+        const int c = it / N2, r = it % N2;
+        for (int pz = 0; pz < Q; ++pz) {
+            double s = 0;
+#pragma unroll
+            for (int i = 0; i < N; ++i) s += lt.S[pz][i] * sX[c * N3 + i * N2 + r];
+            sA[(c * Q + pz) * N2 + r] = s;
+        }
+    }
+    __syncthreads();
+    for (int it = tid; it < 4 * Q * N; it += nth) {
+        const int a0 = it % N, pz = (it / N) % Q, c = it / (N * Q);
+        for (int py = 0; py < Q; ++py) {
+            double s = 0;
+#pragma unroll
+            for (int i = 0; i < N; ++i) s += lt.S[py][i] * sA[(c * Q + pz) * N2 + i * N + a0];
+            sB[((c * Q + pz) * Q + py) * N + a0] = s;
+        }
+    }
+    __syncthreads();
+    const double detJ = GEN ? 1.0 : a.cell_metric[e * 10 + 9];
+    for (int it = tid; it < Q2; it += nth) {
+        const int py = it % Q, pz = it / Q;
+        double acc[kStats];
+#pragma unroll
+        for (int m = 0; m < kStats; ++m) acc[m] = 0;
+        for (int px = 0; px < Q; ++px) {
+            double v[4];
+#pragma unroll
+            for (int c = 0; c < 4; ++c) {
+                double s = 0;
+#pragma unroll
+                for (int i = 0; i < N; ++i) s += lt.S[px][i] * sB[((c * Q + pz) * Q + py) * N + i];
+                v[c] = s;
+            }
+            const int p = px + Q * (py + Q * pz);
+            const double jxw = GEN ? a.cell_metric[(e * 10 + 9) * Q3 + p] : detJ * lt.w[px] * lt.w[py] * lt.w[pz];
+            const double r = 1.0 / v[0];
+            const double u0 = v[1] * r, u1 = v[2] * r, u2 = v[3] * r;
+            acc[0] += jxw;
+            acc[1] += v[0] * jxw;
+            acc[2] += u0 * jxw;
+            acc[3] += u1 * jxw;
+            acc[4] += u2 * jxw;
+            acc[5] += u0 * u0 * jxw;
+            acc[6] += u1 * u1 * jxw;
+            acc[7] += u2 * u2 * jxw;
+            acc[8] += u0 * u1 * jxw;
+        }
+#pragma unroll
+        for (int m = 0; m < kStats; ++m) sP[(m * Q + py) * Q + pz] = acc[m];
+    }
+    __syncthreads();
+    for (int it = tid; it < kStats * Q; it += nth) {
+        const int m = it / Q, py = it % Q;
+        double s = 0;
+        for (int pz = 0; pz < Q; ++pz) s += sP[(m * Q + py) * Q + pz];
+        partial[(e * Q + py) * kStats + m] = s;
+    }
+}
+
+template <int N, int Q, bool GEN>
+inline int launch_chan_stats_t(const OpArgs& a, const Tables1D& t, double* partial, hipStream_t st) {
+    KTab<N, Q, double> kt;
+    MTab<N, double> mt;
+    fill_tables<N, Q, double>(t, kt, mt);
+    hipLaunchKernelGGL((chan_stats_kernel<N, Q, GEN>), dim3((unsigned)a.ncell), dim3(kDiagBlock), 0, st, a, partial, kt);
+    return hipGetLastError() == hipSuccess ? 0 : -1;
+}
+
 template <int N, int Q, bool GEN>
 inline int launch_diag_t(const OpArgs& a, const Tables1D& t, const double* L, double* partial, hipStream_t st) {
     KTab<N, Q, double> kt;

@@ -6,13 +6,14 @@
 //   in.bin : dgns_params, dgns_box_mesh, uint32 terms, int32 mode, then U (n_dof float64)
 //            and, for mode 2, Rbar (n_dof float64)
 //   mode   : 0 residual R, 1 operator L = M^{-1} R, 2 residual adjoint Ubar = (dR/dU)^T Rbar,
-//            3 standalone inverse mass M^{-1} U
-//   out.bin: R, L, Ubar or M^{-1} U (n_dof float64)
+//            3 standalone inverse mass M^{-1} U, 4 channel-statistics partial sums
+//   out.bin: R, L, Ubar or M^{-1} U (n_dof float64); mode 4: n_cells * n_q * 9 float64
 #include <cstdio>
 #include <string>
 #include <vector>
 
 #include "adj_impl.h"
+#include "diag_impl.h"
 #include "setup.h"
 
 using namespace dgns;
@@ -29,6 +30,11 @@ template <int N, int Q>
 int run(const OpArgs& a, const Tables1D& t, int fp32, int gen) {
     if (fp32) return gen ? launch_op_t<N, Q, float, true>(a, t, nullptr) : launch_op_t<N, Q, float, false>(a, t, nullptr);
     return gen ? launch_op_t<N, Q, double, true>(a, t, nullptr) : launch_op_t<N, Q, double, false>(a, t, nullptr);
+}
+
+template <int N, int Q>
+int run_stats(const OpArgs& a, const Tables1D& t, int gen) {
+    return gen ? launch_chan_stats_t<N, Q, true>(a, t, a.out, nullptr) : launch_chan_stats_t<N, Q, false>(a, t, a.out, nullptr);
 }
 
 template <int N>
@@ -63,7 +69,8 @@ int main(int argc, char** argv) {
         return 5;
     }
     const int64_t ndof = 5 * hs.ncell * hs.n3;
-    std::vector<double> U(ndof), out(ndof, -12345.0), Rb;
+    const int64_t nout = fuse == 4 ? hs.ncell * prm.n_q * kStats : ndof;
+    std::vector<double> U(ndof), out(nout, -12345.0), Rb;
     if ((int64_t)std::fread(U.data(), 8, ndof, f) != ndof) return 6;
     if (fuse == 2) {
         Rb.resize(ndof);
@@ -96,14 +103,15 @@ int main(int argc, char** argv) {
 #define EMU_CASE(K, Q_) \
     if (k == K && q == Q_)                                                                                   \
         rc = fuse == 2 ? run_adj<K + 1, Q_>(a, Rb.data(), hs.tab, gen)                                        \
-                       : (fuse == 3 ? run_minv<K + 1>(a, hs.tab, fp32, gen) : run<K + 1, Q_>(a, hs.tab, fp32, gen));
+                       : (fuse == 3 ? run_minv<K + 1>(a, hs.tab, fp32, gen)                                  \
+                                    : (fuse == 4 ? run_stats<K + 1, Q_>(a, hs.tab, gen) : run<K + 1, Q_>(a, hs.tab, fp32, gen)));
     EMU_CASES
     if (rc != 0) {
         std::fprintf(stderr, "no emulated kernel for k=%d nq=%d\n", k, q);
         return 7;
     }
     f = std::fopen(argv[2], "wb");
-    std::fwrite(out.data(), 8, ndof, f);
+    std::fwrite(out.data(), 8, nout, f);
     std::fclose(f);
     return 0;
 }

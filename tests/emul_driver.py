@@ -17,7 +17,7 @@ CASES = [(1, 2), (2, 3), (3, 6), (4, 7), (7, 11)]
 def build():
     srcs = [os.path.join(EMU, "harness.cpp"), os.path.join(EMU, "hip", "hip_runtime.h"),
             os.path.join(CSRC, "setup.cpp"), os.path.join(CSRC, "setup.h"), os.path.join(CSRC, "op_impl.h"),
-            os.path.join(CSRC, "adj_impl.h"), os.path.join(CSRC, "dg_adjoint.h"),
+            os.path.join(CSRC, "adj_impl.h"), os.path.join(CSRC, "dg_adjoint.h"), os.path.join(CSRC, "diag_impl.h"),
             os.path.join(CSRC, "dg_common.h"), os.path.join(ROOT, "include", "dgns.h")]
     h = hashlib.sha1()
     for s in srcs:
@@ -54,7 +54,8 @@ class _Mesh(ctypes.Structure):
 
 def run(U, k, nq, n, lo, hi, periodic=(1, 1, 1), kind=0, basis=0, precision=0, gamma=1.4, R=287.0, mu=0.0,
         lam=0.0, rho_ref=1.0, force=(0, 0, 0), wall_T=0.0, amp=0.0, C=1.8, terms=7, fuse=0, Rbar=None):
-    """fuse: 0 residual, 1 operator (with M^{-1}), 2 residual adjoint of Rbar, 3 standalone M^{-1} U."""
+    """fuse: 0 residual, 1 operator (with M^{-1}), 2 residual adjoint of Rbar, 3 standalone M^{-1} U,
+    4 channel-statistics partial sums (returned as [n_cells, n_q, 9])."""
     exe = build()
     p = _Params(k, nq, basis, precision, gamma, R, mu, lam, rho_ref, (ctypes.c_double * 3)(*force), wall_T)
     m = _Mesh((ctypes.c_int * 3)(*n), (ctypes.c_double * 3)(*lo), (ctypes.c_double * 3)(*hi),
@@ -73,4 +74,5 @@ def run(U, k, nq, n, lo, hi, periodic=(1, 1, 1), kind=0, basis=0, precision=0, g
         r = subprocess.run([exe, fi, fo], capture_output=True, text=True)
         if r.returncode != 0:
             raise RuntimeError("emulated kernel failed (%d):\n%s" % (r.returncode, r.stderr[-4000:]))
-        return np.fromfile(fo, dtype=np.float64).reshape(U.shape)
+        out = np.fromfile(fo, dtype=np.float64)
+        return out.reshape(-1, nq, 9) if fuse == 4 else out.reshape(U.shape)

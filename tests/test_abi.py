@@ -72,5 +72,6 @@ def test_null_arguments():
     assert lib.dgns_apply_operator(None, None, None, 0.0) == binding.EINVAL
     assert lib.dgns_rk_step(None, None, None, 0.0, 0.1) == binding.EINVAL
     assert lib.dgns_rk_stage_update(None, None, None, None, 0, 0.1) == binding.EINVAL
+    assert lib.dgns_channel_statistics(None, None, None) == binding.EINVAL
     assert lib.dgns_destroy(None) == binding.OK
     assert b"null" in lib.dgns_last_error() or len(lib.dgns_last_error()) > 0

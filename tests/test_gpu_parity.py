@@ -268,6 +268,38 @@ def test_rk_stage_update_alone():
         gop.rk_stage_update(U, U, _cuda(L), 1, dt)
 
 
+@pytest.mark.parametrize("case", ["channel_k4", "tgv_k3"])
+def test_channel_statistics(case):
+    announce("channel statistics (plane averages) vs oracle: " + case)
+    if case == "channel_k4":
+        fl = tgv_fluid(mu=1.0 / 180.0)
+        T0 = (18.3 / 0.1) ** 2 / (fl.gamma * fl.R)
+        oop, gop = make_pair((2, 4, 2), 4, 7, lo=(0.0, -1.0, 0.0), hi=(2 * math.pi, 1.0, math.pi),
+                             periodic=(1, 0, 1), kind="channel", fluid=fl, force=(1.0, 0.0, 0.0), wall_T=T0)
+        U = channel_input(oop)
+    else:
+        oop, gop = make_pair((3, 2, 2), 3, 6)
+        U = tgv_input(oop, seed=8)
+    got = gop.channel_statistics(_cuda(U))
+    want = odiag.channel_statistics(oop, U)
+    assert got.shape == want.shape
+    # Averages of sign-changing quantities (the Taylor-Green <u>, <uv> over a period)
+    # cancel to far below their summands, so each column's error is measured against
+    # the size of its summands: |y|, rho, |u| <= sqrt(max <uu>), |uv| <= max <uu>.
+    q2 = np.abs(want[:, 5:8]).max()
+    scale = [np.abs(want[:, 0]).max(), np.abs(want[:, 1]).max()] + [np.sqrt(q2)] * 3 + [q2] * 4
+    for m in range(9):
+        err = np.abs(got[:, m] - want[:, m]).max() / scale[m]
+        assert err < 1e-12, (m, err)
+
+
+def test_channel_statistics_rejects_curved_mesh():
+    from paper_1806_03095_amd.binding import DgnsError
+    oop, gop = make_pair((2, 2, 2), 2, 3, kind="curved", amp=0.1)
+    with pytest.raises(DgnsError):
+        gop.channel_statistics(_cuda(tgv_input(oop)))
+
+
 def test_diagnostics_and_projection():
     announce("tgv 4^3 k=3 nq=6: diagnostics and IC projection")
     oop, gop = make_pair((4, 4, 4), 3, 6)

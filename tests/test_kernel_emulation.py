@@ -12,7 +12,7 @@ import numpy as np
 import torch
 import pytest
 
-from oracle import mesh as omesh, operator as ooperator
+from oracle import diagnostics as odiag, mesh as omesh, operator as ooperator
 from tests import emul_driver as ed
 from tests.gpu_cases import channel_input, rel_err_fields, tgv_fluid, tgv_input
 
@@ -139,3 +139,24 @@ def test_emulated_adjoint_channel_walls_and_force():
         want = _oracle_vjp(oop, U, Rb, t)
         errs = rel_err_fields(Ub[:2], want[:2]) if t == "f" else rel_err_fields(Ub, want)
         assert max(errs) < 1e-12, (t, errs)
+
+
+@pytest.mark.parametrize("n,k,nq,kind", [((2, 3, 2), 3, 6, 0), ((2, 4, 1), 4, 7, 1)])
+def test_emulated_channel_statistics(n, k, nq, kind):
+    # per-cell partial sums of the statistics kernel, reduced here over each plane of
+    # cells, against the oracle's plane averages (the y column comes from the host)
+    lo, hi = (0.0, -1.0, 0.0), (2 * math.pi, 1.0, math.pi)
+    fl = tgv_fluid(mu=1.0 / 180.0)
+    om = omesh.BoxMesh(n, lo, hi, k, periodic=(True, kind == 0, True), kind=kind)
+    oop = ooperator.DGOperator(om, fl, nq, wall_T=None if kind == 0 else 100.0)
+    U = channel_input(oop)
+    part = ed.run(U.numpy(), k, nq, n, lo, hi, periodic=(1, int(kind == 0), 1), kind=kind, mu=fl.mu, lam=fl.lam,
+                  wall_T=0.0 if kind == 0 else 100.0, fuse=4)
+    nx, ny, nz = n
+    want = odiag.channel_statistics(oop, U)
+    for j in range(ny):
+        cells = [i + nx * (j + ny * kk) for kk in range(nz) for i in range(nx)]
+        tot = part[cells].sum(axis=0)              # [n_q, 9]
+        got = tot[:, 1:] / tot[:, :1]
+        ref = want[j * nq:(j + 1) * nq, 1:]
+        assert np.abs(got - ref).max() <= 1e-12 * np.abs(ref).max(), j
