@@ -407,13 +407,15 @@ int dgns_diagnostics(dgns_ctx* c, const double* U, const double* L, double* out8
     HIP_TRY(hipStreamSynchronize(c->stream));
     const double V = tot[8];
     const double nu = c->prm.mu / c->prm.rho_ref;
-    out8[0] = tot[0] / V;
-    out8[1] = nu * tot[1] / V;
-    out8[2] = L ? tot[2] / V : NAN;
-    for (int i = 0; i < 5; ++i) out8[3 + i] = tot[3 + i];
+    double r[8];
+    r[0] = tot[0] / V;
+    r[1] = nu * tot[1] / V;
+    r[2] = L ? tot[2] / V : NAN;
+    for (int i = 0; i < 5; ++i) r[3 + i] = tot[3 + i];
     for (int i = 0; i < 8; ++i)
         if (i != 2 || L)
-            if (!std::isfinite(out8[i])) return fail(DGNS_ENONFINITE, "diagnostic %d is not finite", i);
+            if (!std::isfinite(r[i])) return fail(DGNS_ENONFINITE, "diagnostic %d is not finite", i);
+    for (int i = 0; i < 8; ++i) out8[i] = r[i];   // written only on success
     return DGNS_OK;
 }
 
@@ -457,6 +459,7 @@ int dgns_channel_statistics(dgns_ctx* c, const double* U, double* out) {
     // y of the wall-normal points: the geometry interpolant of cell row j along xi_1
     // (y depends on xi_1 alone on these meshes), read from the first cell of the row
     const int N = c->n;
+    std::vector<double> res(nt);
     for (int j = 0; j < n1; ++j) {
         const int64_t e = (int64_t)c->msh.n[0] * j;
         const double* g = c->geo.data() + (e * 3 + 1) * c->n3;
@@ -464,13 +467,14 @@ int dgns_channel_statistics(dgns_ctx* c, const double* U, double* out) {
             double y = 0;
             for (int i = 0; i < N; ++i) y += g[N * i] * c->tab.Sg[p][i];
             const double* t = tot.data() + ((int64_t)j * q + p) * 9;
-            double* o = out + ((int64_t)j * q + p) * 9;
+            double* o = res.data() + ((int64_t)j * q + p) * 9;
             o[0] = y;
             for (int m = 1; m < 9; ++m) o[m] = t[m] / t[0];
             for (int m = 0; m < 9; ++m)
                 if (!std::isfinite(o[m])) return fail(DGNS_ENONFINITE, "statistic %d at row %d, point %d is not finite", m, j, p);
         }
     }
+    std::copy(res.begin(), res.end(), out);   // written only on success
     return DGNS_OK;
 }
 
@@ -551,8 +555,8 @@ int dgns_kinetic_energy(dgns_ctx* c, const double* U, double* ke) {
     double tot[9];
     HIP_TRY(hipMemcpyAsync(tot, c->d_total, sizeof tot, hipMemcpyDeviceToHost, c->stream));
     HIP_TRY(hipStreamSynchronize(c->stream));
+    if (!std::isfinite(tot[0])) return fail(DGNS_ENONFINITE, "kinetic energy is not finite");
     *ke = tot[0];
-    if (!std::isfinite(*ke)) return fail(DGNS_ENONFINITE, "kinetic energy is not finite");
     return DGNS_OK;
 }
 
