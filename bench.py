@@ -352,6 +352,8 @@ def main():
     ap.add_argument("--op-only", type=int, default=0, metavar="CALLS",
                     help="profiling mode: only CALLS launches of the float64 operator kernel, no JSON")
     ap.add_argument("--precision", default="fp64", choices=("fp64", "fp32"), help="precision of --op-only")
+    ap.add_argument("--memops-only", type=int, default=0, metavar="CALLS",
+                    help="profiling mode: CALLS stand-alone M^{-1} launches, then CALLS RK stage updates, nothing timed")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
                     help="profiling mode: one device-to-device copy of MIB MiB (HBM counter calibration)")
     ap.add_argument("--no-extras", action="store_true",
@@ -395,6 +397,19 @@ def main():
             op.apply(U0, L)
         torch.cuda.synchronize()
         log("%d operator launches (%s), %d DoFs each" % (args.op_only, args.precision, op.n_dof))
+        return
+    if args.memops_only:
+        op = taylor_green(k, ne, n_q=nq)
+        U0 = op.project_ic("taylor_green", [1.0, 1.0, 0.1, 1.0])
+        L = torch.empty_like(U0)
+        for _ in range(args.memops_only):
+            op.inverse_mass(U0, L)
+        dU = torch.zeros_like(U0)
+        for _ in range(args.memops_only):
+            op.rk_stage_update(U0, dU, L, 1, 1e-12)
+        torch.cuda.synchronize()
+        log("%d inverse-mass launches and %d stage updates, %d DoFs each" % (args.memops_only, args.memops_only,
+                                                                             op.n_dof))
         return
     log("workload: TGV %d^3 cells, k=%d, n_q=%d" % (ne, k, nq))
     op = taylor_green(k, ne, n_q=nq, precision="fp64")
