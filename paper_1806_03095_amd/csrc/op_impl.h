@@ -264,7 +264,7 @@ __device__ __forceinline__ void load_face_point_rows(const KTab<N, Q, Real>& tb,
 // Test integration of the face-point coefficients r2 [f][val, g_t0, g_t1, g_n][c][q1][q0]
 // of the NF faces xi_d = s, d = d0 .. d0 + NF - 1, against the cell's basis functions,
 // accumulated into sR: value part through phi_i, gradient part through grad_xi phi_i.
-template <int N, int Q, typename Real, int NF = 3>
+template <int N, int Q, typename Real, int NF = 3, bool END_SYNC = true>
 __device__ __forceinline__ void face_test_accumulate(const KTab<N, Q, Real>& tb, int s, int d0, Real* r1, Real* r2,
                                                      Real* sR) {
     constexpr int N2 = N * N, N3 = N2 * N, Q2 = Q * Q;
@@ -322,7 +322,7 @@ __device__ __forceinline__ void face_test_accumulate(const KTab<N, Q, Real>& tb,
         }
         sR[it] += acc;
     }
-    __syncthreads();
+    if constexpr (END_SYNC) __syncthreads();
 }
 
 // One face point it = f * n_q^2 + q0 + n_q q1 of the group of faces xi_d = s,
@@ -449,7 +449,7 @@ __device__ __forceinline__ void face_point(const OpArgs& a, const KTab<N, Q, Rea
 // The three faces xi_d = s (d = 0, 1, 2) of the cell: traces, fluxes, test
 // integration, accumulated into sR.  NF = 3 processes the faces of all three
 // directions together (d0 = 0); NF = 1 the single face xi_{d0} = s.
-template <int N, int Q, typename Real, bool GEN, int NF>
+template <int N, int Q, typename Real, bool GEN, int NF, bool END_SYNC = true>
 __device__ __forceinline__ void face_group(const OpArgs& a, const KTab<N, Q, Real>& lt, const Phys<Real>& ph, bool conv,
                                            bool visc, int s, int d0, const FaceInfo& fi, const Real* sTau,
                                            const Real* sFn, const Real* sJr, Real detJ, const Real* sU, Real* sR,
@@ -547,7 +547,10 @@ __device__ __forceinline__ void face_group(const OpArgs& a, const KTab<N, Q, Rea
     }
     __syncthreads();
 
-    face_test_accumulate<N, Q, Real, NF>(lt, s, d0, rt1, r2, sR);
+    // Without END_SYNC the caller runs another face group next: its trace phase writes
+    // only TR, which lies past the lifted values W that the last accumulation reads (with
+    // the aliased layout), and it does not touch sR; its own barrier orders the rest.
+    face_test_accumulate<N, Q, Real, NF, END_SYNC || !FS::ALIAS>(lt, s, d0, rt1, r2, sR);
 }
 
 template <int N, int Q, typename Real, bool GEN>
@@ -826,12 +829,15 @@ dg_operator_kernel(OpArgs a, KTab<N, Q, Real> tb, MTab<N, Real> mt) {
                 }
                 sR[it] += acc;
             }
-            __syncthreads();
+            // The next chunk's y sweep writes only sY, which this phase does not read, and
+            // each thread updates the same sR entries in every chunk, so the barrier after
+            // its y sweep suffices; after the last chunk the face phase reuses sF's space.
+            if (pz0 + P >= Q) __syncthreads();
         }
 
         // ------------------------------------------------------------ face terms
         if constexpr (Sz::NF == 3) {
-            face_group<N, Q, Real, GEN, 3>(a, lt, ph, conv, visc, 0, 0, fi, sTau, sFn, sJr, detJ, sU, sR, sW);
+            face_group<N, Q, Real, GEN, 3, false>(a, lt, ph, conv, visc, 0, 0, fi, sTau, sFn, sJr, detJ, sU, sR, sW);
             face_group<N, Q, Real, GEN, 3>(a, lt, ph, conv, visc, 1, 0, fi, sTau, sFn, sJr, detJ, sU, sR, sW);
         } else {
             for (int s = 0; s < 2; ++s)
