@@ -50,7 +50,9 @@ def test_residual_vjp_tgv(terms, mask):
 
 @pytest.mark.parametrize("case", [((2, 2, 3), 2, 4, "curved", 0.1, "LGL"), ((2, 3, 2), 3, 5, "curved", 0.15, "GL"),
                                   ((3, 2, 2), 1, 2, "affine", 0.0, "LGL"), ((2, 2, 2), 4, 7, "affine", 0.0, "LGL"),
-                                  ((2, 2, 2), 5, 8, "curved", 0.05, "LGL")])
+                                  ((2, 2, 2), 5, 8, "curved", 0.05, "LGL"),
+                                  # n_q = 2k+1
+                                  ((2, 2, 1), 3, 7, "affine", 0.0, "LGL"), ((2, 1, 1), 4, 9, "curved", 0.1, "GL")])
 def test_operator_vjp_range(case):
     n, k, nq, kind, amp, basis = case
     announce("adjoint: operator VJP n=%s k=%d nq=%d %s %s" % (n, k, nq, kind, basis))
