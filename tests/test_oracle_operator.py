@@ -150,6 +150,33 @@ def test_sipg_symmetry_pin_detects_planted_mistakes(planted, monkeypatch):
     assert float((Jm - Jm.T).abs().max() / Jm.abs().max()) > 1e-3
 
 
+def test_sipg_definiteness_pin_detects_missing_penalty(monkeypatch):
+    # plant a zero interior penalty: the SIPG form loses coercivity and the negative
+    # semi-definiteness pin must fail
+    monkeypatch.setattr(operator.DGOperator, "tau_of", lambda self, cells: np.zeros(len(np.atleast_1d(cells))))
+    op = make(n=(2, 1, 1), k=1, nq=3, mu=0.05, lam=0.0, lo=(0, 0, 0), hi=(1, 1, 1))
+    Jm = _viscous_blocks(op)
+    ev = torch.linalg.eigvalsh(0.5 * (Jm + Jm.T))
+    assert float(ev.max()) > 1e-6 * float(ev.abs().max())
+
+
+def test_llf_dissipation_pin_detects_wrong_wave_speed(monkeypatch):
+    # plant a wave speed |u| - 3c < 0 (the LLF term then anti-dissipates): the pin below must fail
+    orig = physics.speed_of_sound
+    monkeypatch.setattr(physics, "speed_of_sound", lambda U, fl: -3.0 * orig(U, fl))
+    op = make(n=(2, 1, 1), k=1, nq=2, mu=0.0, lam=0.0, lo=(0, 0, 0), hi=(1, 1, 1))
+    E, N = op.mesh.n_cells, op.N
+    Uc = physics.conserved_from_primitive(torch.tensor(1.0, dtype=torch.float64),
+                                          torch.tensor([0.4, 0.25, -0.3], dtype=torch.float64),
+                                          torch.tensor(1.0, dtype=torch.float64), op.fl)
+    U = Uc[:, None, None].expand(5, E, N).clone()
+    J = _jacobian(op, U, "c")
+    M = op.mass_matrices()
+    Minv = torch.block_diag(*[torch.linalg.inv(M[e]) for e in range(E)])
+    ev = torch.linalg.eigvals(torch.kron(torch.eye(5, dtype=torch.float64), Minv) @ J)
+    assert float(ev.real.max()) > 1e-6 * float(ev.abs().max())
+
+
 def test_llf_linearisation_is_dissipative():
     op = make(n=(2, 1, 1), k=1, nq=2, mu=0.0, lam=0.0, lo=(0, 0, 0), hi=(1, 1, 1))
     E, N = op.mesh.n_cells, op.N
