@@ -258,3 +258,40 @@ def test_basis_independence():
     assert np.abs(a[0] - b[0]).max() < 1e-11 * np.abs(a[0]).max()
     for key in ("e_k", "eps", "rate"):
         assert abs(a[1][key] - b[1][key]) < 1e-12 * abs(a[1][key])
+
+
+def _rest(op, rho, T):
+    E, N = op.mesh.n_cells, op.N
+    p = rho * op.fl.R * T
+    Uc = physics.conserved_from_primitive(torch.tensor(rho, dtype=torch.float64),
+                                          torch.zeros(3, dtype=torch.float64),
+                                          torch.tensor(p, dtype=torch.float64), op.fl)
+    return Uc[:, None, None].expand(5, E, N).clone()
+
+
+def test_wall_rest_state_at_wall_temperature_is_steady():
+    # a fluid at rest at the wall temperature is a steady state of the channel with
+    # isothermal no-slip walls (no body force): the mirror state equals the interior one
+    Tw = 300.0
+    op = make(n=(2, 3, 1), k=2, nq=4, kind=mesh.CHANNEL, periodic=(True, False, True), lo=(0, -1, 0),
+              hi=(2.0, 1.0, 1.0), wall_T=Tw)
+    U = _rest(op, 1.2, Tw)
+    R = op.residual(U)
+    scale = float(op.residual(U, terms="c").abs().max()) + 1.2 * op.fl.R * Tw
+    assert float(R.abs().max()) < 1e-12 * scale
+
+
+@pytest.mark.parametrize("T_fluid,sign", [(250.0, 1.0), (350.0, -1.0)])
+def test_wall_heat_flux_direction(T_fluid, sign):
+    # a fluid at rest colder than the walls gains energy next to them, a warmer one loses
+    # it (heat flows from hot to cold); mass and momentum stay at rest
+    Tw = 300.0
+    op = make(n=(1, 4, 1), k=2, nq=4, periodic=(True, False, True), lo=(0, -1, 0), hi=(1.0, 1.0, 1.0), wall_T=Tw)
+    U = _rest(op, 1.0, T_fluid)
+    R = op.residual(U)
+    wall_cells = [0, 3]
+    E_wall = float(R[4, wall_cells, :].sum())
+    assert sign * E_wall > 0
+    interior = float(R[4, [1, 2], :].abs().max())
+    assert interior < 1e-10 * abs(E_wall)
+    assert float(R[0].abs().max()) < 1e-10 * abs(E_wall)
