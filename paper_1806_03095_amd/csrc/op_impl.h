@@ -163,31 +163,75 @@ __device__ __forceinline__ void sweep_nn(const Real (&M)[N][N], const Real* src,
 template <int N, typename Real, bool GEN>
 __device__ __forceinline__ void inverse_mass_lds(const MTab<N, Real>& mt, const Real* wm, Real* sR, Real* work,
                                                  Real detJ, const double* jxw_m) {
+    // In place on sR, one line of one component per thread and phase; a thread writes back
+    // exactly the line it read, and the lines of one axis are disjoint, so one barrier per
+    // change of axis suffices: x, y, then z with the scaling and the backward z sweep
+    // fused, then y and x.  (work is not needed.)
+    (void)work;
     constexpr int N2 = N * N, N3 = N2 * N;
-    sweep_nn<N, Real, true>(mt.Smi, sR, work, 0);
-    __syncthreads();
-    sweep_nn<N, Real, true>(mt.Smi, work, sR, 1);
-    __syncthreads();
-    sweep_nn<N, Real, true>(mt.Smi, sR, work, 2);
-    __syncthreads();
-    for (int it = threadIdx.x; it < 5 * N3; it += blockDim.x) {
-        const int p = it % N3;
-        Real jxw;
-        if constexpr (GEN) {
-            jxw = (Real)jxw_m[p];
-        } else {
-            const int p0 = p % N, p1 = (p / N) % N, p2 = p / N2;
-            jxw = detJ * wm[p0] * wm[p1] * wm[p2];
+    const int tid = threadIdx.x, nth = blockDim.x;
+    const auto line = [&](int ax, int it) {
+        const int c = it / N2, rest = it % N2;
+        const int base = ax == 0 ? rest * N : (ax == 1 ? (rest % N) + (rest / N) * N2 : rest);
+        return c * N3 + base;
+    };
+    const auto apply = [&](bool trans, Real (&v)[N]) {
+        Real t[N];
+#pragma unroll
+        for (int o = 0; o < N; ++o) {
+            Real acc = 0;
+#pragma unroll
+            for (int i = 0; i < N; ++i) acc += (trans ? mt.Smi[i][o] : mt.Smi[o][i]) * v[i];
+            t[o] = acc;
         }
-        work[it] = work[it] / jxw;
+#pragma unroll
+        for (int o = 0; o < N; ++o) v[o] = t[o];
+    };
+    for (int ax = 0; ax < 2; ++ax) {
+        const int stride = ax == 0 ? 1 : N;
+        for (int it = tid; it < 5 * N2; it += nth) {
+            Real* r = sR + line(ax, it);
+            Real v[N];
+#pragma unroll
+            for (int i = 0; i < N; ++i) v[i] = r[i * stride];
+            apply(true, v);
+#pragma unroll
+            for (int i = 0; i < N; ++i) r[i * stride] = v[i];
+        }
+        __syncthreads();
+    }
+    for (int it = tid; it < 5 * N2; it += nth) {
+        const int rest = it % N2, a0 = rest % N, a1 = rest / N;
+        Real* r = sR + line(2, it);
+        Real v[N];
+#pragma unroll
+        for (int i = 0; i < N; ++i) v[i] = r[i * N2];
+        apply(true, v);
+#pragma unroll
+        for (int i = 0; i < N; ++i) {
+            Real jxw;
+            if constexpr (GEN) jxw = (Real)jxw_m[a0 + N * a1 + N2 * i];
+            else jxw = detJ * wm[a0] * wm[a1] * wm[i];
+            v[i] = v[i] / jxw;
+        }
+        apply(false, v);
+#pragma unroll
+        for (int i = 0; i < N; ++i) r[i * N2] = v[i];
     }
     __syncthreads();
-    sweep_nn<N, Real, false>(mt.Smi, work, sR, 0);
-    __syncthreads();
-    sweep_nn<N, Real, false>(mt.Smi, sR, work, 1);
-    __syncthreads();
-    sweep_nn<N, Real, false>(mt.Smi, work, sR, 2);
-    __syncthreads();
+    for (int ax = 1; ax >= 0; --ax) {
+        const int stride = ax == 0 ? 1 : N;
+        for (int it = tid; it < 5 * N2; it += nth) {
+            Real* r = sR + line(ax, it);
+            Real v[N];
+#pragma unroll
+            for (int i = 0; i < N; ++i) v[i] = r[i * stride];
+            apply(false, v);
+#pragma unroll
+            for (int i = 0; i < N; ++i) r[i * stride] = v[i];
+        }
+        __syncthreads();
+    }
 }
 
 __device__ __forceinline__ int axis_stride(int ax, int N) { return ax == 0 ? 1 : (ax == 1 ? N : N * N); }
