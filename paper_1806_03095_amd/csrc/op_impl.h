@@ -308,7 +308,7 @@ __device__ __forceinline__ void load_face_point_rows(const KTab<N, Q, Real>& tb,
 // Test integration of the face-point coefficients r2 [f][val, g_t0, g_t1, g_n][c][q1][q0]
 // of the NF faces xi_d = s, d = d0 .. d0 + NF - 1, against the cell's basis functions,
 // accumulated into sR: value part through phi_i, gradient part through grad_xi phi_i.
-template <int N, int Q, typename Real, int NF = 3, bool END_SYNC = true>
+template <int N, int Q, typename Real, int NF = 3>
 __device__ __forceinline__ void face_test_accumulate(const KTab<N, Q, Real>& tb, int s, int d0, Real* r1, Real* r2,
                                                      Real* sR) {
     constexpr int N2 = N * N, N3 = N2 * N, Q2 = Q * Q;
@@ -366,7 +366,7 @@ __device__ __forceinline__ void face_test_accumulate(const KTab<N, Q, Real>& tb,
         }
         sR[it] += acc;
     }
-    if constexpr (END_SYNC) __syncthreads();
+    __syncthreads();
 }
 
 // One face point it = f * n_q^2 + q0 + n_q q1 of the group of faces xi_d = s,
@@ -493,7 +493,7 @@ __device__ __forceinline__ void face_point(const OpArgs& a, const KTab<N, Q, Rea
 // The three faces xi_d = s (d = 0, 1, 2) of the cell: traces, fluxes, test
 // integration, accumulated into sR.  NF = 3 processes the faces of all three
 // directions together (d0 = 0); NF = 1 the single face xi_{d0} = s.
-template <int N, int Q, typename Real, bool GEN, int NF, bool END_SYNC = true>
+template <int N, int Q, typename Real, bool GEN, int NF>
 __device__ __forceinline__ void face_group(const OpArgs& a, const KTab<N, Q, Real>& lt, const Phys<Real>& ph, bool conv,
                                            bool visc, int s, int d0, const FaceInfo& fi, const Real* sTau,
                                            const Real* sFn, const Real* sJr, Real detJ, const Real* sU, Real* sR,
@@ -503,68 +503,130 @@ __device__ __forceinline__ void face_group(const OpArgs& a, const KTab<N, Q, Rea
     // work regions: SW (swept traces, read by the point phase), TR (traces), OUT
     // (point results), T1 (t1-transposed), W (lifted): see FaceSizes
     Real* r1 = sW;                 // SW
-    Real* rtr = sW + FS::TR_OFF;   // TR
     Real* r2 = sW + FS::OUT_OFF;   // OUT, later W
     Real* rt1 = sW + FS::T1_OFF;   // T1
     const int tid = threadIdx.x, nth = blockDim.x;
     const int64_t cstride = a.ncell * N3;
 
-    // traces: value and normal derivative of both sides at the face nodes
-    for (int it = tid; it < NF * 5 * N2; it += nth) {
-        const int f = it / (5 * N2), d = d0 + f, c = (it / N2) % 5, ab = it % N2, ia = ab % N, ib = ab / N;
-        const int t0 = d == 0 ? 1 : 0, t1 = d == 2 ? 1 : 2;
-        const int base = ia * axis_stride(t0, N) + ib * axis_stride(t1, N), sd = axis_stride(d, N);
-        Real tv = 0, tn = 0, uv = 0, un = 0;
-#pragma unroll
-        for (int m = 0; m < N; ++m) {
-            const Real x = sU[c * N3 + base + m * sd];
-            tv += lt.fv[s][m] * x;
-            tn += lt.fd[s][m] * x;
+    if constexpr (N <= 4) {
+        // traces and the sweep along t0 in one phase: item (side, f, c, ib) computes the N
+        // traces (value and normal derivative) on its line a0 = 0..N-1 -- from sU on the own
+        // side, from the neighbour's coefficients in global memory on the other -- and sweeps
+        // them: A0 = S tv, A1 = D tv, An = S tn  ->  r1 [f][side][3][c][b][q0].  The items of
+        // one side fill whole waves, so the own / neighbour branch is uniform in each wave.
+        constexpr int PER_SIDE = NF * 5 * N, SIDE_SPAN = (PER_SIDE + 63) / 64 * 64;
+        for (int it = tid; it < 2 * SIDE_SPAN; it += nth) {
+            const int side = it / SIDE_SPAN, k = it % SIDE_SPAN;
+            if (k >= PER_SIDE) continue;
+            const int ib = k % N, c = (k / N) % 5, f = k / (5 * N), d = d0 + f;
+            if (side == 1 && fi.wall[d + 3 * s]) continue;
+            const int t0 = d == 0 ? 1 : 0, t1 = d == 2 ? 1 : 2;
+            const int sd = axis_stride(d, N), st0 = axis_stride(t0, N), bb = ib * axis_stride(t1, N);
+            Real tv[N], tn[N];
+            if (side == 0) {
+    #pragma unroll
+                for (int ia = 0; ia < N; ++ia) {
+                    Real v = 0, n = 0;
+    #pragma unroll
+                    for (int m = 0; m < N; ++m) {
+                        const Real x = sU[c * N3 + bb + ia * st0 + m * sd];
+                        v += lt.fv[s][m] * x;
+                        n += lt.fd[s][m] * x;
+                    }
+                    tv[ia] = v;
+                    tn[ia] = n;
+                }
+            } else {
+                const double* un_line = a.U + c * cstride + fi.enb[d + 3 * s] * N3 + bb;
+    #pragma unroll
+                for (int ia = 0; ia < N; ++ia) {
+                    Real v = 0, n = 0;
+    #pragma unroll
+                    for (int m = 0; m < N; ++m) {
+                        const Real x = (Real)un_line[ia * st0 + m * sd];
+                        v += lt.fv[1 - s][m] * x;
+                        n += lt.fd[1 - s][m] * x;
+                    }
+                    tv[ia] = v;
+                    tn[ia] = n;
+                }
+            }
+            Real* o = r1 + ((f * 2 + side) * 3 * 5 + c) * N * Q + ib * Q;
+    #pragma unroll
+            for (int q0 = 0; q0 < Q; ++q0) {
+                Real a0 = 0, a1 = 0, an = 0;
+    #pragma unroll
+                for (int ia = 0; ia < N; ++ia) {
+                    a0 += lt.S[q0][ia] * tv[ia];
+                    a1 += lt.D[q0][ia] * tv[ia];
+                    an += lt.S[q0][ia] * tn[ia];
+                }
+                o[q0] = a0;
+                o[5 * N * Q + q0] = a1;
+                o[2 * 5 * N * Q + q0] = an;
+            }
         }
-        if (!fi.wall[d + 3 * s]) {
-            const double* un_line = a.U + c * cstride + fi.enb[d + 3 * s] * N3 + base;
-#pragma unroll
+        __syncthreads();
+    } else {
+        // larger N: the traces as a phase of their own (N^2 lines per face), then the sweep
+        // traces: value and normal derivative of both sides at the face nodes
+        Real* rtr = sW + FS::TR_OFF;   // TR
+        for (int it = tid; it < NF * 5 * N2; it += nth) {
+            const int f = it / (5 * N2), d = d0 + f, c = (it / N2) % 5, ab = it % N2, ia = ab % N, ib = ab / N;
+            const int t0 = d == 0 ? 1 : 0, t1 = d == 2 ? 1 : 2;
+            const int base = ia * axis_stride(t0, N) + ib * axis_stride(t1, N), sd = axis_stride(d, N);
+            Real tv = 0, tn = 0, uv = 0, un = 0;
+    #pragma unroll
             for (int m = 0; m < N; ++m) {
-                const Real x = (Real)un_line[m * sd];
-                uv += lt.fv[1 - s][m] * x;
-                un += lt.fd[1 - s][m] * x;
+                const Real x = sU[c * N3 + base + m * sd];
+                tv += lt.fv[s][m] * x;
+                tn += lt.fd[s][m] * x;
             }
+            if (!fi.wall[d + 3 * s]) {
+                const double* un_line = a.U + c * cstride + fi.enb[d + 3 * s] * N3 + base;
+    #pragma unroll
+                for (int m = 0; m < N; ++m) {
+                    const Real x = (Real)un_line[m * sd];
+                    uv += lt.fv[1 - s][m] * x;
+                    un += lt.fd[1 - s][m] * x;
+                }
+            }
+            Real* tr = rtr + f * (2 * 2 * 5 * N2) + c * N2 + ab;
+            tr[(0 * 2 + 0) * 5 * N2] = tv;
+            tr[(0 * 2 + 1) * 5 * N2] = tn;
+            tr[(1 * 2 + 0) * 5 * N2] = uv;
+            tr[(1 * 2 + 1) * 5 * N2] = un;
         }
-        Real* tr = rtr + f * (2 * 2 * 5 * N2) + c * N2 + ab;
-        tr[(0 * 2 + 0) * 5 * N2] = tv;
-        tr[(0 * 2 + 1) * 5 * N2] = tn;
-        tr[(1 * 2 + 0) * 5 * N2] = uv;
-        tr[(1 * 2 + 1) * 5 * N2] = un;
-    }
-    __syncthreads();
+        __syncthreads();
 
-    // sweep along t0: A0 = S tv, A1 = D tv, An = S tn     r1 [f][side][3][c][b][q0]
-    for (int it = tid; it < NF * 2 * 5 * N; it += nth) {
-        const int ib = it % N, c = (it / N) % 5, side = (it / (5 * N)) % 2, f = it / (10 * N), d = d0 + f;
-        if (side == 1 && fi.wall[d + 3 * s]) continue;
-        const Real* tr = rtr + f * (2 * 2 * 5 * N2) + side * (2 * 5 * N2) + c * N2 + ib * N;
-        Real tv[N], tn[N];
-#pragma unroll
-        for (int ia = 0; ia < N; ++ia) {
-            tv[ia] = tr[ia];
-            tn[ia] = tr[5 * N2 + ia];
-        }
-        Real* o = r1 + ((f * 2 + side) * 3 * 5 + c) * N * Q + ib * Q;
-#pragma unroll
-        for (int q0 = 0; q0 < Q; ++q0) {
-            Real a0 = 0, a1 = 0, an = 0;
-#pragma unroll
+        // sweep along t0: A0 = S tv, A1 = D tv, An = S tn     r1 [f][side][3][c][b][q0]
+        for (int it = tid; it < NF * 2 * 5 * N; it += nth) {
+            const int ib = it % N, c = (it / N) % 5, side = (it / (5 * N)) % 2, f = it / (10 * N), d = d0 + f;
+            if (side == 1 && fi.wall[d + 3 * s]) continue;
+            const Real* tr = rtr + f * (2 * 2 * 5 * N2) + side * (2 * 5 * N2) + c * N2 + ib * N;
+            Real tv[N], tn[N];
+    #pragma unroll
             for (int ia = 0; ia < N; ++ia) {
-                a0 += lt.S[q0][ia] * tv[ia];
-                a1 += lt.D[q0][ia] * tv[ia];
-                an += lt.S[q0][ia] * tn[ia];
+                tv[ia] = tr[ia];
+                tn[ia] = tr[5 * N2 + ia];
             }
-            o[q0] = a0;
-            o[5 * N * Q + q0] = a1;
-            o[2 * 5 * N * Q + q0] = an;
+            Real* o = r1 + ((f * 2 + side) * 3 * 5 + c) * N * Q + ib * Q;
+    #pragma unroll
+            for (int q0 = 0; q0 < Q; ++q0) {
+                Real a0 = 0, a1 = 0, an = 0;
+    #pragma unroll
+                for (int ia = 0; ia < N; ++ia) {
+                    a0 += lt.S[q0][ia] * tv[ia];
+                    a1 += lt.D[q0][ia] * tv[ia];
+                    an += lt.S[q0][ia] * tn[ia];
+                }
+                o[q0] = a0;
+                o[5 * N * Q + q0] = a1;
+                o[2 * 5 * N * Q + q0] = an;
+            }
         }
+        __syncthreads();
     }
-    __syncthreads();
 
     // pointwise: numerical fluxes and reference-space test coefficients at every
     // face point, stored as OUT [f][kind: val, g_t0, g_t1, g_n][c][q1][q0].  When one
@@ -591,10 +653,7 @@ __device__ __forceinline__ void face_group(const OpArgs& a, const KTab<N, Q, Rea
     }
     __syncthreads();
 
-    // Without END_SYNC the caller runs another face group next: its trace phase writes
-    // only TR, which lies past the lifted values W that the last accumulation reads (with
-    // the aliased layout), and it does not touch sR; its own barrier orders the rest.
-    face_test_accumulate<N, Q, Real, NF, END_SYNC || !FS::ALIAS>(lt, s, d0, rt1, r2, sR);
+    face_test_accumulate<N, Q, Real, NF>(lt, s, d0, rt1, r2, sR);
 }
 
 template <int N, int Q, typename Real, bool GEN>
@@ -881,7 +940,7 @@ dg_operator_kernel(OpArgs a, KTab<N, Q, Real> tb, MTab<N, Real> mt) {
 
         // ------------------------------------------------------------ face terms
         if constexpr (Sz::NF == 3) {
-            face_group<N, Q, Real, GEN, 3, false>(a, lt, ph, conv, visc, 0, 0, fi, sTau, sFn, sJr, detJ, sU, sR, sW);
+            face_group<N, Q, Real, GEN, 3>(a, lt, ph, conv, visc, 0, 0, fi, sTau, sFn, sJr, detJ, sU, sR, sW);
             face_group<N, Q, Real, GEN, 3>(a, lt, ph, conv, visc, 1, 0, fi, sTau, sFn, sJr, detJ, sU, sR, sW);
         } else {
             for (int s = 0; s < 2; ++s)
