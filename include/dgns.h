@@ -22,7 +22,8 @@
  *    laid out [5][n_cells][(k+1)^3]: conserved component (rho, rho u1, rho u2,
  *    rho u3, rho E), cell (i0 + n0*(i1 + n1*i2)), node (a0 + (k+1)*(a1 + (k+1)*a2)
  *    of the tensor-product nodal basis, first coordinate fastest).  They must be
- *    8-byte aligned.  The float32 operator variant keeps this float64 interface.
+ *    8-byte aligned (a misaligned vector returns DGNS_EINVAL before anything is
+ *    launched).  The float32 operator variant keeps this float64 interface.
  *  - The library owns only its context (geometry, metric terms, 1D tables).  It
  *    never frees or retains caller memory.
  *  - Calls are asynchronous on the context's HIP stream unless stated otherwise.
@@ -40,7 +41,7 @@ extern "C" {
 #endif
 
 #define DGNS_OK 0
-#define DGNS_EINVAL (-1)         /* bad argument: null pointer, size, range, alias */
+#define DGNS_EINVAL (-1)         /* bad argument: null pointer, alignment, size, range, alias */
 #define DGNS_ENOMEM (-2)         /* device or host allocation failed */
 #define DGNS_EHIP (-3)           /* a HIP runtime call failed */
 #define DGNS_EUNSUPPORTED (-4)   /* (degree, n_q, precision) has no compiled kernel */

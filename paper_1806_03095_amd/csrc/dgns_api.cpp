@@ -149,7 +149,7 @@ int dispatch_minv(const dgns_ctx* c, const double* R, double* L) {
         case 7: rc = launch_inverse_mass_k7(R, L, c->ncell, cm, mj, c->tab, c->fp32, c->gen, c->stream); break;
     }
     if (rc == 1) return fail(DGNS_EUNSUPPORTED, "no inverse-mass kernel for degree %d", c->k);
-    if (rc != 0) return fail(DGNS_EHIP, "inverse-mass launch failed");
+    if (rc != 0) return fail(DGNS_EHIP, "inverse-mass launch failed: %s", hipGetErrorString(hipGetLastError()));
     return 0;
 }
 
@@ -167,7 +167,7 @@ int dispatch_diagnostics(const dgns_ctx* c, const OpArgs& a, const double* L) {
     }
     if (rc == 0) rc = launch_diag_total(c->d_partial, c->ncell, c->d_total, c->stream);
     if (rc == 1) return fail(DGNS_EUNSUPPORTED, "no diagnostics kernel for degree %d, n_q %d", c->k, c->q);
-    if (rc != 0) return fail(DGNS_EHIP, "diagnostics launch failed");
+    if (rc != 0) return fail(DGNS_EHIP, "diagnostics launch failed: %s", hipGetErrorString(hipGetLastError()));
     return 0;
 }
 
@@ -399,6 +399,7 @@ int dgns_compute_dt(const dgns_ctx* c, double Cr, double D, double e, double f, 
 
 int dgns_diagnostics(dgns_ctx* c, const double* U, const double* L, double* out8) {
     if (!c || !U || !out8) return fail(DGNS_EINVAL, "null argument");
+    if (!aligned8(U) || (L && !aligned8(L))) return fail(DGNS_EINVAL, "vectors must be 8-byte aligned");
     OpArgs a = make_args(c, U, nullptr, 0, 0);
     int rc = dispatch_diagnostics(c, a, L);
     if (rc) return rc;
@@ -549,6 +550,7 @@ int dgns_rk_step_vjp(dgns_ctx* c, const double* U_n, double t, double dt, const 
 
 int dgns_kinetic_energy(dgns_ctx* c, const double* U, double* ke) {
     if (!c || !U || !ke) return fail(DGNS_EINVAL, "null argument");
+    if (!aligned8(U)) return fail(DGNS_EINVAL, "U must be 8-byte aligned");
     OpArgs a = make_args(c, U, nullptr, 0, 0);
     int rc = dispatch_diagnostics(c, a, nullptr);
     if (rc) return rc;
@@ -562,6 +564,7 @@ int dgns_kinetic_energy(dgns_ctx* c, const double* U, double* ke) {
 
 int dgns_kinetic_energy_vjp(dgns_ctx* c, const double* U, double* Ubar) {
     if (!c || !U || !Ubar) return fail(DGNS_EINVAL, "null argument");
+    if (!aligned8(U) || !aligned8(Ubar)) return fail(DGNS_EINVAL, "vectors must be 8-byte aligned");
     if (overlap(U, c->ndof, Ubar, c->ndof)) return fail(DGNS_EINVAL, "U and Ubar overlap");
     return dispatch_ke_vjp(c, make_args(c, U, nullptr, 0, 0), Ubar);
 }
@@ -569,6 +572,7 @@ int dgns_kinetic_energy_vjp(dgns_ctx* c, const double* U, double* Ubar) {
 int dgns_project_ic(dgns_ctx* c, int ic, const double* icp, const double* noise, double* U) {
     if (!c || !icp || !U) return fail(DGNS_EINVAL, "null argument");
     if (ic < 0 || ic > 2) return fail(DGNS_EINVAL, "unknown initial condition %d", ic);
+    if (!aligned8(U) || (noise && !aligned8(noise))) return fail(DGNS_EINVAL, "vectors must be 8-byte aligned");
     double q[8] = {0, 0, 0, 0, 0, 0, 0, 0};
     const int np = ic == DGNS_IC_UNIFORM ? 5 : 4;
     for (int i = 0; i < np; ++i) q[i] = icp[i];

@@ -355,3 +355,43 @@ def test_rk_step_adjacent_buffers_and_alias_rejection():
         gop.rk_step(U, buf[n // 2: n // 2 + 2 * n], 0.0, 1e-4)   # overlapping: rejected
     with pytest.raises(DgnsError):
         gop.apply(U, out=U)
+
+
+def test_misaligned_vectors_rejected_before_launch():
+    # every entry point that takes device vectors checks their 8-byte alignment before
+    # it launches anything: a pointer 4 bytes into an allocation returns DGNS_EINVAL
+    announce("misaligned vector arguments rejected by every entry point")
+    import ctypes
+    from paper_1806_03095_amd import binding
+    oop, gop = make_pair((2, 2, 2), 2, 3)
+    lib, h, n = gop.lib, gop.h, gop.n_dof
+    buf = torch.zeros(12 * n + 1, dtype=torch.float64, device="cuda")
+    torch.cuda.synchronize()
+    good = [ctypes.c_void_p(buf.data_ptr() + 8 * n * i) for i in range(3)]
+    bad = ctypes.c_void_p(buf.data_ptr() + 4)
+    work = ctypes.c_void_p(buf.data_ptr() + 8 * 3 * n)
+    out8 = (ctypes.c_double * 8)()
+    icp = (ctypes.c_double * 5)(1.0, 1.0, 0.1, 1.0, 0.0)
+    stats = (ctypes.c_double * (gop.n[1] * gop.n_q * 9))()
+    calls = {
+        "apply_operator": lambda x: lib.dgns_apply_operator(h, x, good[1], 0.0),
+        "apply_operator out": lambda x: lib.dgns_apply_operator(h, good[0], x, 0.0),
+        "apply_residual": lambda x: lib.dgns_apply_residual(h, x, good[1], binding.TERM_ALL),
+        "apply_inverse_mass": lambda x: lib.dgns_apply_inverse_mass(h, good[0], x),
+        "rk_step": lambda x: lib.dgns_rk_step(h, x, work, 0.0, 1e-4),
+        "rk_step work": lambda x: lib.dgns_rk_step(h, good[0], x, 0.0, 1e-4),
+        "rk_stage_update": lambda x: lib.dgns_rk_stage_update(h, good[0], x, good[2], 0, 1e-4),
+        "diagnostics": lambda x: lib.dgns_diagnostics(h, x, None, out8),
+        "diagnostics L": lambda x: lib.dgns_diagnostics(h, good[0], x, out8),
+        "kinetic_energy": lambda x: lib.dgns_kinetic_energy(h, x, out8),
+        "kinetic_energy_vjp": lambda x: lib.dgns_kinetic_energy_vjp(h, good[0], x),
+        "channel_statistics": lambda x: lib.dgns_channel_statistics(h, x, stats),
+        "project_ic": lambda x: lib.dgns_project_ic(h, 0, icp, None, x),
+        "apply_residual_vjp": lambda x: lib.dgns_apply_residual_vjp(h, good[0], good[1], x, binding.TERM_ALL),
+        "apply_operator_vjp": lambda x: lib.dgns_apply_operator_vjp(h, good[0], x, good[2]),
+        "rk_step_vjp": lambda x: lib.dgns_rk_step_vjp(h, good[0], 0.0, 1e-4, good[1], good[2], x),
+    }
+    for name, call in calls.items():
+        assert call(bad) == binding.EINVAL, name
+    torch.cuda.synchronize()
+    assert float(buf.abs().max()) == 0.0   # nothing was written
