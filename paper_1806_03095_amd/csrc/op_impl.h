@@ -120,16 +120,19 @@ struct OpSizes {
     static_assert(CELL == CellSizes<N, Q, P>::TOTAL, "cell work area");
 };
 
-// Workgroup size of the operator kernel: 128 threads (two waves) per cell while
-// four workgroups fit in a compute unit's LDS, so that every SIMD holds two waves;
-// 256 threads for the larger (N, n_q) whose LDS footprint allows fewer workgroups
-// (unless the 1D tables do not fit in LDS: that kernel spills, and more waves of
-// it only add spill traffic).
+// Workgroup size of the operator kernel: 64 threads (one wave) per cell when the
+// n_q^3 cell points fit in one wave (n_q <= 4): such small cells would leave most of a
+// larger workgroup idle in every phase, and one-wave workgroups put twice as many
+// cells on a compute unit.  Otherwise 128 threads (two waves) while four workgroups
+// fit in a compute unit's LDS, so that every SIMD holds two waves; 256 threads for
+// the larger (N, n_q) whose LDS footprint allows fewer workgroups (unless the 1D
+// tables do not fit in LDS: that kernel spills, and more waves of it only add spill
+// traffic).
 template <int N, int Q, typename Real>
 struct OpBlock {
     using S128 = OpSizes<N, Q, 128, (int)sizeof(Real)>;
     static constexpr int lds128 = (S128::WORK + 10 * N * N * N + S128::TABLES) * (int)sizeof(Real) + 1024;
-    static constexpr int threads = (lds128 <= 40 * 1024 || !S128::LDS_TAB) ? 128 : 256;
+    static constexpr int threads = Q <= 4 ? 64 : ((lds128 <= 40 * 1024 || !S128::LDS_TAB) ? 128 : 256);
 };
 
 // Applies an N x N matrix M along axis `ax` of the NC arrays src[NC][N^3] ->
