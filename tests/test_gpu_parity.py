@@ -328,9 +328,18 @@ def test_determinism_bitwise():
     assert torch.equal(a, b)
 
 
-def test_fp32_variant_error_is_small():
-    announce("tgv 4^3 k=3 nq=6 fp32 operator")
-    oop, gop = make_pair((4, 4, 4), 3, 6, precision="fp32")
+@pytest.mark.parametrize("n,k,nq,kind,amp", [
+    ((4, 4, 4), 3, 6, "affine", 0.0),
+    # one-wave workgroups (n_q <= 4)
+    ((3, 2, 2), 1, 2, "affine", 0.0),
+    ((2, 2, 3), 2, 4, "curved", 0.1),
+    ((3, 3, 2), 3, 4, "affine", 0.0),
+])
+def test_fp32_variant_error_is_small(n, k, nq, kind, amp):
+    # float32 rounding against the float64 oracle: at most 4.5e-4 per field in the CPU
+    # emulation of these kernels
+    announce("tgv %s k=%d nq=%d %s fp32 operator" % (n, k, nq, kind))
+    oop, gop = make_pair(n, k, nq, kind=kind, amp=amp, precision="fp32")
     U = tgv_input(oop, seed=2)
     L32 = gop.apply(_cuda(U))
     torch.cuda.synchronize()
