@@ -659,8 +659,10 @@ __device__ __forceinline__ void face_group(const OpArgs& a, const KTab<N, Q, Rea
     face_test_accumulate<N, Q, Real, NF>(lt, s, d0, rt1, r2, sR);
 }
 
+// Registers: at most 256 VGPRs (two waves per SIMD), except for k = 1, whose float64
+// kernels fit in 168 without spilling, so that three waves share a SIMD.
 template <int N, int Q, typename Real, bool GEN>
-__global__ void __launch_bounds__((OpBlock<N, Q, Real>::threads)) __attribute__((amdgpu_waves_per_eu(2)))
+__global__ void __launch_bounds__((OpBlock<N, Q, Real>::threads)) __attribute__((amdgpu_waves_per_eu(N <= 2 ? 3 : 2)))
 dg_operator_kernel(OpArgs a, KTab<N, Q, Real> tb, MTab<N, Real> mt) {
     using Sz = OpSizes<N, Q, OpBlock<N, Q, Real>::threads, (int)sizeof(Real)>;
     constexpr int P = Sz::P;
