@@ -42,8 +42,10 @@ struct CMax { static constexpr int v = A > B ? A : B; };
 template <int N, int Q, int B, int NF = 3>
 struct FaceSizes {
     static constexpr int N2 = N * N, Q2 = Q * Q;
+    // For N <= 4 the traces are computed inside the sweep along t0 and never stored.
+    static constexpr bool FUSED_TRACE = N <= 4;
     // group of NF faces xi_d = s (NF = 3: all three directions; NF = 1: one face)
-    static constexpr int TR = NF * 2 * 2 * 5 * N2;      // traces [f][side][v/n][c][N^2]
+    static constexpr int TR = FUSED_TRACE ? 0 : NF * 2 * 2 * 5 * N2;   // traces [f][side][v/n][c][N^2]
     static constexpr int SW = NF * 2 * 3 * 5 * N * Q;   // t0 sweep [f][side][3][c][N][Q]
     static constexpr int OUT = NF * 4 * 5 * Q2;         // point outputs [f][4][c][Q^2]
     static constexpr int T1 = NF * 3 * 5 * N * Q;       // t1-transposed [f][3][c][N][Q]
@@ -511,7 +513,7 @@ __device__ __forceinline__ void face_group(const OpArgs& a, const KTab<N, Q, Rea
     const int tid = threadIdx.x, nth = blockDim.x;
     const int64_t cstride = a.ncell * N3;
 
-    if constexpr (N <= 4) {
+    if constexpr (FS::FUSED_TRACE) {
         // traces and the sweep along t0 in one phase: item (side, f, c, ib) computes the N
         // traces (value and normal derivative) on its line a0 = 0..N-1 -- from sU on the own
         // side, from the neighbour's coefficients in global memory on the other -- and sweeps
