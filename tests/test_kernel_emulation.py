@@ -1,12 +1,17 @@
-"""The operator kernel source, compiled for the CPU and run one thread per workgroup
-(tests/emul), against the oracle -- with AddressSanitizer and UBSan on.
+"""The operator kernel source, compiled for the CPU (tests/emul: one host thread per
+thread of a workgroup, real barriers) and run against the oracle -- with
+AddressSanitizer and UBSan on.
 
 This checks the kernels' indexing, face handling, geometry and arithmetic without
-a GPU (it does not replace the GPU parity tests: it cannot see races or the
-device compiler).  Inputs use Mach 0.3, where float64 rounding leaves the 1e-12
-per-field bound a wide margin.
+a GPU (it does not replace the GPU parity tests: it catches a race only when the host
+threads happen to interleave badly, and it does not see the device compiler).
+Inputs use Mach 0.3, where float64 rounding leaves the 1e-12 per-field bound a wide
+margin.  test_lds_plan_layout checks the LDS plan of every compiled kernel on the host.
 """
 import math
+import os
+import subprocess
+import tempfile
 
 import numpy as np
 import torch
@@ -160,3 +165,17 @@ def test_emulated_channel_statistics(n, k, nq, kind):
         got = tot[:, 1:] / tot[:, :1]
         ref = want[j * nq:(j + 1) * nq, 1:]
         assert np.abs(got - ref).max() <= 1e-12 * np.abs(ref).max(), j
+
+
+def test_lds_plan_layout():
+    # every compiled (degree, n_q) in both precisions: the work area holds every phase,
+    # regions used at once are disjoint, the fused trace items fill whole waves, and the
+    # footprint fits a compute unit (tests/emul/plan_check.cpp)
+    with tempfile.TemporaryDirectory() as td:
+        exe = os.path.join(td, "plan_check")
+        cmd = ["g++", "-std=c++17", "-O0", "-Wno-unknown-pragmas", "-I", ed.EMU, "-I",
+               os.path.join(ed.ROOT, "include"), "-I", ed.CSRC, os.path.join(ed.EMU, "plan_check.cpp"), "-o", exe]
+        r = subprocess.run(cmd, capture_output=True, text=True)
+        assert r.returncode == 0, r.stderr[-4000:]
+        r = subprocess.run([exe], capture_output=True, text=True)
+        assert r.returncode == 0 and r.stdout.strip().endswith("all ok"), r.stdout[-4000:]
