@@ -39,11 +39,11 @@ namespace dgns {
 template <int A, int B>
 struct CMax { static constexpr int v = A > B ? A : B; };
 
-template <int N, int Q, int B, int NF = 3>
+template <int N, int Q, int B, int NF = 3, bool FUSED = (N <= 4)>
 struct FaceSizes {
     static constexpr int N2 = N * N, Q2 = Q * Q;
-    // For N <= 4 the traces are computed inside the sweep along t0 and never stored.
-    static constexpr bool FUSED_TRACE = N <= 4;
+    // FUSED: the traces are computed inside the sweep along t0 and never stored.
+    static constexpr bool FUSED_TRACE = FUSED;
     // group of NF faces xi_d = s (NF = 3: all three directions; NF = 1: one face)
     static constexpr int TR = FUSED_TRACE ? 0 : NF * 2 * 2 * 5 * N2;   // traces [f][side][v/n][c][N^2]
     static constexpr int SW = NF * 2 * 3 * 5 * N * Q;   // t0 sweep [f][side][3][c][N][Q]
@@ -92,14 +92,16 @@ struct ChooseP {
 //    and the face-point phase still gains: 3 ceil(n_q^2 / B) passes at w1 waves per
 //    SIMD against ceil(3 n_q^2 / B) passes at w3 waves;
 //  - else one face per group only when three faces leave no room for the tables.
-template <int N, int Q, int B, int RS>
+template <int N, int Q, int B, int RS, bool FUSED = (N <= 4)>
 struct OpSizes {
     static constexpr int N3 = N * N * N, Q2 = Q * Q;
     static constexpr int TABLES = 2 * Q * N + Q + 4 * N + 2 * N * N + N;   // KTab + MTab entries
     static constexpr int LDS_MAX = 160 * 1024;
     static constexpr int TARGET = LDS_MAX / (8 * 64 / B);   // LDS per workgroup at eight waves per CU
     static constexpr int cell(int p) { return 10 * Q * N * N + 15 * p * Q * (N + Q); }
-    static constexpr int face(int nf) { return nf == 3 ? FaceSizes<N, Q, B, 3>::TOTAL : FaceSizes<N, Q, B, 1>::TOTAL; }
+    static constexpr int face(int nf) {
+        return nf == 3 ? FaceSizes<N, Q, B, 3, FUSED>::TOTAL : FaceSizes<N, Q, B, 1, FUSED>::TOTAL;
+    }
     static constexpr int work(int nf, int p) {
         return cell(p) > face(nf) ? (cell(p) > 10 * N3 ? cell(p) : 10 * N3) : (face(nf) > 10 * N3 ? face(nf) : 10 * N3);
     }
@@ -132,9 +134,16 @@ struct OpSizes {
 // traffic).
 template <int N, int Q, typename Real>
 struct OpBlock {
-    using S128 = OpSizes<N, Q, 128, (int)sizeof(Real)>;
+    using S128 = OpSizes<N, Q, 128, (int)sizeof(Real), (N <= 4)>;
+    using S128F = OpSizes<N, Q, 128, (int)sizeof(Real), true>;
     static constexpr int lds128 = (S128::WORK + 10 * N * N * N + S128::TABLES) * (int)sizeof(Real) + 1024;
-    static constexpr int threads = Q <= 4 ? 64 : ((lds128 <= 40 * 1024 || !S128::LDS_TAB) ? 128 : 256);
+    static constexpr int lds128f = (S128F::WORK + 10 * N * N * N + S128F::TABLES) * (int)sizeof(Real) + 1024;
+    // traces fused into the t0 sweep: always for N <= 4; for larger N only where dropping
+    // their LDS area is what admits 128-thread workgroups (for N >= 5 the separate trace
+    // phase is otherwise faster: more items per phase)
+    static constexpr bool fused = N <= 4 || (lds128 > 40 * 1024 && lds128f <= 40 * 1024 && S128F::LDS_TAB);
+    static constexpr int threads =
+        Q <= 4 ? 64 : (((fused ? lds128f : lds128) <= 40 * 1024 || !S128::LDS_TAB) ? 128 : 256);
 };
 
 // Applies an N x N matrix M along axis `ax` of the NC arrays src[NC][N^3] ->
@@ -503,7 +512,7 @@ __device__ __forceinline__ void face_group(const OpArgs& a, const KTab<N, Q, Rea
                                            bool visc, int s, int d0, const FaceInfo& fi, const Real* sTau,
                                            const Real* sFn, const Real* sJr, Real detJ, const Real* sU, Real* sR,
                                            Real* sW) {
-    using FS = FaceSizes<N, Q, OpBlock<N, Q, Real>::threads, NF>;
+    using FS = FaceSizes<N, Q, OpBlock<N, Q, Real>::threads, NF, OpBlock<N, Q, Real>::fused>;
     constexpr int N2 = N * N, N3 = N2 * N, Q2 = Q * Q;
     // work regions: SW (swept traces, read by the point phase), TR (traces), OUT
     // (point results), T1 (t1-transposed), W (lifted): see FaceSizes
@@ -666,7 +675,7 @@ __device__ __forceinline__ void face_group(const OpArgs& a, const KTab<N, Q, Rea
 template <int N, int Q, typename Real, bool GEN>
 __global__ void __launch_bounds__((OpBlock<N, Q, Real>::threads)) __attribute__((amdgpu_waves_per_eu(N <= 2 ? 3 : 2)))
 dg_operator_kernel(OpArgs a, KTab<N, Q, Real> tb, MTab<N, Real> mt) {
-    using Sz = OpSizes<N, Q, OpBlock<N, Q, Real>::threads, (int)sizeof(Real)>;
+    using Sz = OpSizes<N, Q, OpBlock<N, Q, Real>::threads, (int)sizeof(Real), OpBlock<N, Q, Real>::fused>;
     constexpr int P = Sz::P;
     constexpr int N2 = N * N, N3 = N2 * N, Q2 = Q * Q, Q3 = Q2 * Q;
     constexpr int ZS = CellSizes<N, Q, P>::Z, YS = CellSizes<N, Q, P>::Y;
@@ -1164,7 +1173,8 @@ inline int launch_op_t(const OpArgs& a, const Tables1D& t, hipStream_t st) {
     MTab<N, Real> mt;
     fill_tables<N, Q, Real>(t, kt, mt);
     constexpr int B = OpBlock<N, Q, Real>::threads;
-    static_assert((OpSizes<N, Q, B, (int)sizeof(Real)>::WORK + 10 * N * N * N) * sizeof(Real) <= 160 * 1024, "LDS budget");
+    static_assert((OpSizes<N, Q, B, (int)sizeof(Real), OpBlock<N, Q, Real>::fused>::WORK + 10 * N * N * N) *
+                          sizeof(Real) <= 160 * 1024, "LDS budget");
     hipLaunchKernelGGL((dg_operator_kernel<N, Q, Real, GEN>), dim3((unsigned)a.ncell), dim3(B), 0, st, a, kt, mt);
     return hipGetLastError() == hipSuccess ? 0 : -1;
 }

@@ -25,8 +25,9 @@ static bool disjoint(int a0, int n0, int a1, int n1) { return a0 + n0 <= a1 || a
 template <int N, int Q, typename Real>
 void plan() {
     constexpr int B = OpBlock<N, Q, Real>::threads;
-    using S = OpSizes<N, Q, B, (int)sizeof(Real)>;
-    using F = FaceSizes<N, Q, B, S::NF>;
+    constexpr bool fused = OpBlock<N, Q, Real>::fused;
+    using S = OpSizes<N, Q, B, (int)sizeof(Real), fused>;
+    using F = FaceSizes<N, Q, B, S::NF, fused>;
     const int k = N - 1, N3 = N * N * N;
     const char* prec = sizeof(Real) == 8 ? "fp64" : "fp32";
     check(B == 64 || B == 128 || B == 256, k, Q, prec, "block size");
@@ -58,7 +59,8 @@ void plan() {
     }
     const int bytes = (S::WORK + 10 * N3 + S::TABLES) * (int)sizeof(Real);
     check(bytes <= 160 * 1024, k, Q, prec, "LDS footprint");
-    std::printf("k=%d n_q=%d %s: B=%d NF=%d P=%d work=%d LDS=%d B\n", k, Q, prec, B, S::NF, S::P, S::WORK, bytes);
+    std::printf("k=%d n_q=%d %s: B=%d NF=%d P=%d fused traces=%d work=%d LDS=%d B\n", k, Q, prec, B, S::NF, S::P,
+                (int)fused, S::WORK, bytes);
 }
 
 template <int N, int Q>

@@ -93,6 +93,7 @@ CASES = [
     ((2, 3, 3), 3, 5, "curved", 0.15, "GL"),
     ((2, 2, 2), 4, 7, "affine", 0.0, "LGL"),
     ((2, 2, 2), 4, 6, "curved", 0.1, "LGL"),
+    ((2, 3, 1), 4, 5, "affine", 0.0, "GL"),
     ((2, 2, 2), 5, 8, "affine", 0.0, "LGL"),
     ((2, 1, 2), 7, 11, "affine", 0.0, "LGL"),
     ((1, 2, 2), 7, 11, "curved", 0.1, "LGL"),
