@@ -11,7 +11,7 @@ ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
 EMU = os.path.join(ROOT, "tests", "emul")
 CSRC = os.path.join(ROOT, "paper_1806_03095_amd", "csrc")
 BUILD = os.path.join(EMU, "_build")
-CASES = [(1, 2), (2, 3), (3, 6), (4, 7), (7, 11)]
+CASES = [(1, 2), (2, 3), (3, 6), (4, 5), (4, 7), (7, 11)]
 
 
 def build():

@@ -36,6 +36,8 @@ def _tgv_case(n, k, nq, kind=0, amp=0.0, basis="LGL"):
     ((2, 2, 2), 2, 3, 2, 0.15, "GL"),
     ((2, 1, 2), 3, 6, 0, 0.0, "LGL"),
     ((1, 2, 2), 3, 6, 2, 0.1, "GL"),
+    # k = 4, n_q = 5 in float64: traces fused into the t0 sweep so that 128 threads fit
+    ((2, 1, 2), 4, 5, 2, 0.1, "LGL"),
     # k = 7, n_q = 11 in float64: one face per face phase (the three-face layout leaves
     # no room in LDS for the 1D tables), 256-thread workgroups
     ((2, 1, 1), 7, 11, 0, 0.0, "LGL"),
