@@ -156,7 +156,8 @@ int dgns_compute_dt(const dgns_ctx* ctx, double Cr, double D, double e, double f
  *   out8[2] = -de_k/dt = -1/V int u.(L_m - u L_rho)/rho   (NaN if L is NULL),
  *   out8[3] = int rho,  out8[4..6] = int rho u,  out8[7] = int rho E.
  * e_k, eps and the rate use the n_q rule, the totals the k+1 rule (= 1^T M U).
- * Returns DGNS_ENONFINITE (after writing out8) if any of them is not finite. */
+ * Returns DGNS_ENONFINITE if any of them is not finite (a state that has blown up,
+ * Sec. 5.2.2); out8 is then left untouched, as for every other error. */
 int dgns_diagnostics(dgns_ctx* ctx, const double* U, const double* L, double* out8);
 
 /* L2 projection of an initial state onto the DG space: U = M^{-1} (phi_i, U0)
@@ -202,7 +203,7 @@ int dgns_rk_step_vjp(dgns_ctx* ctx, const double* U_n, double t, double dt, cons
 int dgns_channel_statistics(dgns_ctx* ctx, const double* U, double* out);
 
 /* K = int |u|^2/2 over the domain (n_q rule, u = (rho u)/rho), returned to the
- * host (synchronises the stream); DGNS_ENONFINITE if not finite. */
+ * host (synchronises the stream); DGNS_ENONFINITE if not finite (ke untouched). */
 int dgns_kinetic_energy(dgns_ctx* ctx, const double* U, double* ke);
 
 /* Ubar = dK/dU for K of dgns_kinetic_energy.  Ubar must not overlap U. */

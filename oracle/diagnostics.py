@@ -35,7 +35,7 @@ def diagnostics(op, U, L=None):
         out["eps"] += float(((gu * gu).sum((-1, -2)) * JxW).sum())
         if L is not None:
             Lq = torch.einsum("pi,cei->epc", op.Phi, L[:, cc, :])
-            dudt = (Lq[..., 1:4] - u * Lq[..., 0:1]) / Uq[..., 0:1]
+            dudt = ph.velocity_rate(Uq, Lq)
             out["rate"] += float(-((u * dudt).sum(-1) * JxW).sum())
         _, _, detJm = op._geometry(cc, op.mass_pts)
         JxWm = detJm * torch.as_tensor(op.mass_w)

@@ -8,7 +8,7 @@ Taylor-Green (Sec. 5.2.1): on [-pi L, pi L]^3,
     T = T0 = c0^2 / (gamma R),  c0 = U0 / M,  p0 = rho0 R T0,  rho = p / (R T0).
 Channel (Sec. 5.3.1): rho = 1, T = T0 = c^2/(gamma R) with c = u_max / M,
     u1 = u_max (1 - x2^2)  (laminar parabola; the paper's (1 - x2^6) is an option)
-    plus a seeded perturbation.
+    plus a seeded perturbation of the velocity at the nodes (channel_perturbed).
 The paper does not say how the initial state enters the discrete space; here it
 is the L2 projection M^{-1} int phi U0(x), the right-hand side integrated with
 the operator's n_q-point rule.
@@ -41,6 +41,35 @@ def channel_laminar(x, fl, umax=18.3, mach=0.1, power=2):
     u[..., 0] = umax * (1.0 - x[..., 1] ** power)
     p = rho * fl.R * T0
     return ph.conserved_from_primitive(torch.as_tensor(rho), torch.as_tensor(u), torch.as_tensor(p), fl)
+
+
+def channel_perturbed(op, U, r, umax=18.3, power=2, amp=0.1):
+    """The perturbed channel initial state (Sec. 5.3.1): at every node of the nodal basis
+    the velocity gets u_a += amp * u1(x2) * r_a with u1(x2) = umax (1 - |x2|^power) the
+    laminar profile, so that the perturbation vanishes at the walls x2 = -1, 1, while the
+    density and the temperature of the node are kept (rho E is recomputed from them).
+
+    U: the state (5, E, N) (for a Lagrange basis its coefficients are its nodal values),
+    r: the random numbers (3, E, N) in [-1, 1], drawn by the caller.  Returns a new array.
+    The paper perturbs the laminar profile with random noise without fixing the recipe;
+    this one scales the noise by the local laminar velocity."""
+    fl = op.fl
+    k = op.k
+    pts = np.array([[op.nodes[a0], op.nodes[a1], op.nodes[a2]]
+                    for a2 in range(k + 1) for a1 in range(k + 1) for a0 in range(k + 1)])
+    x, _ = op.mesh.map_at(pts)                               # (E, N, 3)
+    U = torch.as_tensor(U, dtype=torch.float64)
+    Un = U.permute(1, 2, 0)                                  # (E, N, 5)
+    rho = Un[..., 0]
+    T = ph.temperature(Un, fl)
+    u = ph.velocity(Un)
+    lam = torch.as_tensor(umax * (1.0 - np.abs(x[..., 1]) ** power))
+    u = u + amp * lam[..., None] * torch.as_tensor(np.asarray(r, dtype=np.float64)).permute(1, 2, 0)
+    out = torch.zeros_like(Un)
+    out[..., 0] = rho
+    out[..., 1:4] = rho[..., None] * u
+    out[..., 4] = rho * (fl.c_v * T + 0.5 * (u * u).sum(-1))
+    return out.permute(2, 0, 1).contiguous()
 
 
 def uniform(x, fl, rho=1.0, u=(0.3, -0.2, 0.1), p=None):

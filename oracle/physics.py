@@ -79,6 +79,11 @@ def convective_flux(U, fl):
     return F
 
 
+def velocity_rate(U, dUdt):
+    """du/dt from dU/dt along a trajectory: d(m/rho)/dt = (dm/dt - u drho/dt)/rho (quotient rule)."""
+    return (dUdt[..., 1:4] - velocity(U) * dUdt[..., 0:1]) / U[..., 0:1]
+
+
 def velocity_gradient(U, G):
     """gu[..., a, j] = d u_a / d x_j from the conserved gradients (quotient rule)."""
     rho = U[..., 0]

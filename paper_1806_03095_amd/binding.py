@@ -222,17 +222,22 @@ class Operator:
         return out.value
 
     def diagnostics(self, U, L=None):
-        """e_k, eps, -de_k/dt (nan without L), mass, momentum (3), energy."""
+        """e_k, eps, -de_k/dt (nan without L), mass, momentum (3), energy.
+
+        A state with a NaN or Inf anywhere in these integrals (a blown-up run) does not
+        raise: the library reports DGNS_ENONFINITE and writes nothing, and the result is
+        then all NaN with nonfinite=True and the library's message under "error"."""
         self._vec(U, "U")
         if L is not None:
             self._vec(L, "L")
-        out = (ctypes.c_double * 8)()
+        out = (ctypes.c_double * 8)(*([math.nan] * 8))
         self._bind()
         rc = self.lib.dgns_diagnostics(self.h, _ptr(U), _ptr(L), out)
         vals = list(out)
         res = dict(e_k=vals[0], eps=vals[1], rate=vals[2], mass=vals[3], mom=vals[4:7], energy=vals[7])
         if rc == ENONFINITE:
             res["nonfinite"] = True
+            res["error"] = self.lib.dgns_last_error().decode()
             return res
         _check(rc)
         return res

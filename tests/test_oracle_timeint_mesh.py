@@ -127,3 +127,27 @@ def test_rk_observed_order_nonautonomous():
         errs.append(abs(y - exact(1.0)))
     rates = [math.log2(errs[i] / errs[i + 1]) for i in range(2)]
     assert min(rates) > 3.8, rates
+
+
+def test_blowup_at_large_courant_number_is_non_finite():
+    """Far past the stability limit of the explicit scheme (Cr = 3 against a critical value
+    near 0.4, Sec. 5.2.2), the oracle's solution blows up within a few steps and its
+    diagnostics turn non-finite -- the signal the GPU diagnostics report as
+    DGNS_ENONFINITE; at Cr = 0.3 the same steps stay finite."""
+    import math
+    import torch
+    from oracle import diagnostics, initial, mesh, operator, physics, timeint
+    m = mesh.BoxMesh((3, 3, 3), (-math.pi,) * 3, (math.pi,) * 3, 2)
+    fl = physics.Fluid.from_reynolds(1600.0, 0.71)
+    op = operator.DGOperator(m, fl, 3)
+    U0 = initial.l2_project(op, lambda x: initial.taylor_green(x, fl))
+    finite = {}
+    for Cr in (0.3, 3.0):
+        dt = timeint.time_step(Cr, 10.0, 1.5, 3.0, 2, m.h_min(), 1.0, 0.1, fl.nu)
+        U = U0.clone()
+        for s in range(6):
+            U = timeint.lsrk_step(lambda V, t: op.apply(V), U, s * dt, dt)
+        d = diagnostics.diagnostics(op, U)
+        finite[Cr] = all(math.isfinite(v) for v in (d["e_k"], d["eps"], d["mass"], d["energy"]))
+        finite[Cr] = finite[Cr] and bool(torch.isfinite(U).all())
+    assert finite[0.3] and not finite[3.0], finite
