@@ -66,3 +66,25 @@ def rel_err_fields(a, b):
     a = torch.as_tensor(a, dtype=torch.float64).cpu()
     b = torch.as_tensor(b, dtype=torch.float64).cpu()
     return [float(torch.linalg.norm(a[c] - b[c]) / torch.linalg.norm(b[c])) for c in range(a.shape[0])]
+
+
+def sample_cells(n, count, seed):
+    """Corner and edge cells of the box (periodic wrap-around) plus seeded random ones."""
+    nx, ny, nz = n
+    corners = [0, nx - 1, nx * (ny - 1), nx * ny - 1, nx * ny * (nz - 1), nx * ny * nz - 1]
+    rng = synth.rng(seed)
+    rest = rng.choice(nx * ny * nz, size=count, replace=False)
+    return np.unique(np.concatenate([np.asarray(corners, dtype=np.int64), rest.astype(np.int64)]))
+
+
+def patched_state(oop, cells, func, background, seed, noise):
+    """Uniform `background` everywhere; oracle projection of func plus noise on
+    `cells` and their face neighbours."""
+    m = oop.mesh
+    nbs = m.nb[cells].reshape(-1)
+    need = np.unique(np.concatenate([cells, nbs[nbs >= 0]]))
+    U = torch.empty(5, m.n_cells, oop.N, dtype=torch.float64)
+    U[:] = torch.as_tensor(background, dtype=torch.float64)[:, None, None]
+    P = initial.l2_project(oop, func, cells=need).numpy()
+    U[:, need, :] = torch.as_tensor(synth.relative_noise(P, seed, noise))
+    return U

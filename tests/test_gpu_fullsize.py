@@ -21,44 +21,25 @@ import torch
 
 import synth
 from oracle import initial
-from tests.gpu_cases import announce, make_pair, rel_err_fields, tgv_fluid
-from tests.test_gpu_parity import _check_low_mach, tol_k
+from tests.gpu_cases import announce, make_pair, patched_state as _patched_state, rel_err_fields, \
+    sample_cells as _sample_cells, tgv_fluid
+from tests import floor
 
 pytestmark = pytest.mark.gpu
 
 
-def _sample_cells(n, count, seed):
-    """Corner and edge cells of the box (periodic wrap-around) plus seeded random ones."""
-    nx, ny, nz = n
-    corners = [0, nx - 1, nx * (ny - 1), nx * ny - 1, nx * ny * (nz - 1), nx * ny * nz - 1]
-    rng = synth.rng(seed)
-    rest = rng.choice(nx * ny * nz, size=count, replace=False)
-    return np.unique(np.concatenate([np.asarray(corners, dtype=np.int64), rest.astype(np.int64)]))
-
-
-def _patched_state(oop, cells, func, background, seed, noise):
-    """Uniform `background` everywhere; oracle projection of func plus noise on
-    `cells` and their face neighbours."""
-    m = oop.mesh
-    nbs = m.nb[cells].reshape(-1)
-    need = np.unique(np.concatenate([cells, nbs[nbs >= 0]]))
-    U = torch.empty(5, m.n_cells, oop.N, dtype=torch.float64)
-    U[:] = torch.as_tensor(background, dtype=torch.float64)[:, None, None]
-    P = initial.l2_project(oop, func, cells=need).numpy()
-    U[:, need, :] = torch.as_tensor(synth.relative_noise(P, seed, noise))
-    return U
-
-
-def _low_mach_tol(oop, k):
-    """Tolerances (normwise, per field) of the low-Mach comparison on this mesh.
-
-    The 1e-12 / 1e-11 bounds hold on the 4^3 Taylor-Green mesh (h = pi/2).  The
-    cancellation they allow for grows as 1/h: each quadrature term of a momentum row
-    is of order p0 |J| |grad phi| ~ p0 h^2 while the row's result is of order
-    |L| h^3, so the rounding error relative to the result scales with
-    p0 / (h |L|).  Both evaluations (oracle and kernel) carry it."""
-    s = max(1.0, (math.pi / 2) / oop.mesh.h_min())
-    return tol_k(k) * s, 10 * tol_k(k) * s
+def _floor_sampled(oop, U, got, cells, what, n_ref, terms=None):
+    """Floor rule of tests/floor.py on the sampled cells: the oracle's float64 error and
+    the HIP result's accuracy are measured against the extended-precision evaluation on
+    the first n_ref sampled cells, parity against the oracle on all of them."""
+    sub = list(range(min(n_ref, len(cells))))
+    if terms is None:
+        ref = floor.reference(oop, U, [int(cells[i]) for i in sub], "L")
+        want = oop.apply(U, cells=cells)
+    else:
+        ref = floor.reference(oop, U, [int(cells[i]) for i in sub], "R", terms)
+        want = oop.residual(U, cells=cells, terms=terms)
+    return floor.check(got, want, ref, what, sub=sub)
 
 
 def _tgv_func(oop, mach):
@@ -83,18 +64,14 @@ def test_tgv_32cubed_k3_nq6_operator_sampled():
     cells = _sample_cells(n, 64, seed=11)
     U = _patched_state(oop, cells, _tgv_func(oop, 0.1), _rest_background(oop.fl, 0.1), seed=12, noise=1e-3)
     got = _gpu_apply_sampled(gop, U, cells)
-    want = oop.apply(U, cells=cells)
-    nt, ft = _low_mach_tol(oop, 3)
-    errs = _check_low_mach(got, want, "L 32^3 sample", norm_tol=nt, field_tol=ft)
-    print("per-field relative error on the sample:", errs, flush=True)
+    _floor_sampled(oop, U, got, cells, "L 32^3 sample", 16)
     # the residual before M^{-1}, each term on its own
     Ug = U.to("cuda").contiguous()
     for terms, mask in (("c", 1), ("v", 2)):
         R = gop.residual(Ug, terms=mask)
         torch.cuda.synchronize()
         Rs = R[:, torch.as_tensor(cells, device="cuda"), :].cpu()
-        _check_low_mach(Rs, oop.residual(U, cells=cells, terms=terms), "R_%s 32^3 sample" % terms, norm_tol=nt,
-                        field_tol=ft)
+        _floor_sampled(oop, U, Rs, cells, "R_%s 32^3 sample" % terms, 16, terms=terms)
 
 
 def test_tgv_64cubed_k3_nq6_operator_sampled():
@@ -106,8 +83,7 @@ def test_tgv_64cubed_k3_nq6_operator_sampled():
     cells = _sample_cells(n, 48, seed=13)
     U = _patched_state(oop, cells, _tgv_func(oop, 0.1), _rest_background(oop.fl, 0.1), seed=14, noise=1e-3)
     got = _gpu_apply_sampled(gop, U, cells)
-    nt, ft = _low_mach_tol(oop, 3)
-    _check_low_mach(got, oop.apply(U, cells=cells), "L 64^3 sample", norm_tol=nt, field_tol=ft)
+    _floor_sampled(oop, U, got, cells, "L 64^3 sample", 16)
 
 
 def test_tgv_32cubed_fp32_error_sampled():
@@ -192,10 +168,11 @@ def test_channel_16cubed_k4_nq7_sampled():
     U = _patched_state(oop, cells, lambda x: initial.channel_laminar(x, fl, umax=umax, mach=mach), back,
                        seed=22, noise=1e-2)
     got = _gpu_apply_sampled(gop, U, cells)
-    want = oop.apply(U, cells=cells)
-    nt, ft = _low_mach_tol(oop, 4)
-    errs = _check_low_mach(got, want, "L channel 16^3 sample", norm_tol=nt, field_tol=ft)
-    print("per-field relative error on the sample:", errs, flush=True)
+    # the extended reference on the wall columns first (they lead the sorted sample at j = 0)
+    order = np.argsort([0 if (c // 16) % 16 in (0, 15) else 1 for c in cells], kind="stable")
+    cells = cells[order]
+    got = got[:, torch.as_tensor(order)]
+    _floor_sampled(oop, U, got, cells, "L channel 16^3 sample", 12)
 
 
 @pytest.mark.parametrize("n1,k,nq", [(16, 7, 11), (24, 5, 8)])
@@ -207,9 +184,7 @@ def test_precision_study_sizes_sampled(n1, k, nq):
     U = _patched_state(oop, cells, _tgv_func(oop, 0.1), _rest_background(oop.fl, 0.1), seed=32, noise=1e-3)
     want = oop.apply(U, cells=cells)
     got = _gpu_apply_sampled(g64, U, cells)
-    nt, ft = _low_mach_tol(oop, k)
-    errs = _check_low_mach(got, want, "L fp64 sample", norm_tol=nt, field_tol=ft)
-    print("fp64 per-field relative error on the sample:", errs, flush=True)
+    _floor_sampled(oop, U, got, cells, "L fp64 %d^3 k=%d sample" % (n1, k), 3 if k >= 7 else 5)
     del g64
     _, g32 = make_pair(n, k, nq, precision="fp32")
     e32 = rel_err_fields(_gpu_apply_sampled(g32, U, cells), want)
