@@ -283,10 +283,10 @@ def precision_study(steps):
         ops = {p: taylor_green(k, ne, n_q=nq, precision=p) for p in ("fp64", "fp32")}
         U0 = ops["fp64"].project_ic("taylor_green", [1.0, 1.0, 0.1, 1.0])
         dt = ops["fp64"].compute_dt(CR_STUDY, 0.02, 1.5, 3.0, 1.0, 0.1)
-        L64, L32 = ops["fp64"].apply(U0), ops["fp32"].apply(U0)
+        e0 = fp32_error(ops["fp64"], ops["fp32"], U0)
         row = {"workload": "taylor_green_%dcubed_k%d_nq%d" % (ne, k, nq), "n_dof": ops["fp64"].n_dof,
-               "steps": steps, "dt": dt,
-               "L0_rel_err": float(torch.linalg.norm(L32 - L64) / torch.linalg.norm(L64))}
+               "steps": steps, "dt": dt, "L0_rel_err": e0["whole_vector"], "L0_rel_err_per_field": e0["per_field"],
+               "L0_rate_rel_err": e0["dissipation_rate"]}
         res = {}
         for p, op in ops.items():
             U = U0.clone()
@@ -307,34 +307,81 @@ def precision_study(steps):
     return out
 
 
-def cpu_baseline(ne, k, nq, n_sample):
-    """The oracle, as it stands, on a sample of cells of the same workload."""
+def _cpu_model():
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
+def _oracle_eval(ne, k, nq, n_sample, threads):
+    """Seconds for one oracle evaluation of L on n_sample cells (all cells if n_sample is None)
+    of the Taylor-Green workload, with `threads` torch CPU threads; DoFs evaluated."""
     import numpy as np
     import torch
     from oracle import initial, mesh, operator, physics
     fl = physics.Fluid.from_reynolds(1600.0, 0.71)
     m = mesh.BoxMesh((ne,) * 3, (-math.pi,) * 3, (math.pi,) * 3, k)
     op = operator.DGOperator(m, fl, nq)
-    cells = np.linspace(0, m.n_cells - 1, n_sample).astype(np.int64)
+    if n_sample is None or n_sample >= m.n_cells:
+        cells = np.arange(m.n_cells, dtype=np.int64)
+    else:
+        cells = np.linspace(0, m.n_cells - 1, n_sample).astype(np.int64)
     need = np.unique(np.concatenate([cells, m.nb[cells].reshape(-1)]))
     U = torch.zeros(5, m.n_cells, (k + 1) ** 3, dtype=torch.float64)
     U[:, need, :] = initial.l2_project(op, lambda x: initial.taylor_green(x, fl), cells=need)
     op.tau_of(need)
-    t0 = time.perf_counter()
-    op.apply(U, cells=cells)
-    el = time.perf_counter() - t0
-    cpu = "unknown"
+    old = torch.get_num_threads()
+    torch.set_num_threads(threads)
     try:
-        for line in open("/proc/cpuinfo"):
-            if line.startswith("model name"):
-                cpu = line.split(":", 1)[1].strip()
-                break
-    except OSError:
-        pass
-    dofs = n_sample * 5 * (k + 1) ** 3
-    return {"value": dofs / el, "unit": "DoF/s", "cores": torch.get_num_threads(), "kind": "oracle",
-            "sample": "one evaluation of L on %d of %d cells (%d DoFs) of the same workload, %.2f s, %s"
-                      % (n_sample, m.n_cells, dofs, el, cpu)}
+        op.apply(U, cells=cells[: min(len(cells), 8)])      # warm the geometry code paths
+        t0 = time.perf_counter()
+        op.apply(U, cells=cells)
+        el = time.perf_counter() - t0
+    finally:
+        torch.set_num_threads(old)
+    return el, len(cells) * 5 * (k + 1) ** 3, len(cells), m.n_cells
+
+
+def cpu_baseline(ne, k, nq, n_sample, n_sample_1core):
+    """The oracle, as it stands, timed on the host: one evaluation of L on the full 4^3
+    Taylor-Green mesh (k=3, n_q=6) and on a sample of cells of the headline workload,
+    each with all the threads torch uses here and with one thread.  value is the
+    headline-workload sample with all threads."""
+    import torch
+    threads = torch.get_num_threads()
+    runs = []
+    for name, (e, kk, q), sample in (("taylor_green_4cubed_k3_nq6", (4, 3, 6), None),
+                                      ("taylor_green_%dcubed_k%d_nq%d" % (ne, k, nq), (ne, k, nq), n_sample)):
+        for th in (threads, 1):
+            smp = sample if th == threads or sample is None else n_sample_1core
+            el, dofs, nc, ntot = _oracle_eval(e, kk, q, smp, th)
+            runs.append({"workload": name, "threads": th, "cells": nc, "of_cells": ntot, "seconds": el,
+                         "dofs_per_s": dofs / el})
+            log("cpu baseline %s, %d thread(s), %d of %d cells: %.2f s, %.3e DoF/s" % (name, th, nc, ntot, el,
+                                                                                          dofs / el))
+    head = runs[2]
+    return {"value": head["dofs_per_s"], "unit": "DoF/s", "cores": threads, "kind": "oracle",
+            "sample": "one evaluation of L on %d of %d cells of the same workload (%d threads, %.2f s); "
+                      "host %s with %d logical CPUs" % (head["cells"], head["of_cells"], threads, head["seconds"],
+                                                       _cpu_model(), os.cpu_count() or 0),
+            "runs": runs}
+
+
+def fp32_error(op64, op32, U):
+    """Float32 operator against float64 on the same state: relative error per conserved
+    field and over the whole vector, and of the exact -de_k/dt computed from each L."""
+    import torch
+    L64, L32 = op64.apply(U), op32.apply(U)
+    per = [float(torch.linalg.norm(L32[c] - L64[c]) / torch.linalg.norm(L64[c])) for c in range(5)]
+    r64 = op64.diagnostics(U, L64)["rate"]
+    r32 = op64.diagnostics(U, L32)["rate"]
+    return {"per_field": dict(zip(("rho", "rho_u", "rho_v", "rho_w", "rho_E"), per)),
+            "whole_vector": float(torch.linalg.norm(L32 - L64) / torch.linalg.norm(L64)),
+            "dissipation_rate": abs(r32 - r64) / abs(r64)}
 
 
 def main():
@@ -347,6 +394,7 @@ def main():
     ap.add_argument("--nq", type=int, default=6)
     ap.add_argument("--op-calls", type=int, default=200)
     ap.add_argument("--cpu-sample-cells", type=int, default=12288)
+    ap.add_argument("--cpu-sample-cells-1core", type=int, default=1024)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-fp32", action="store_true")
     ap.add_argument("--op-only", type=int, default=0, metavar="CALLS",
@@ -466,21 +514,21 @@ def main():
         U32 = U0.clone()
         t32, _ = time_rk(op32, U32, work, dt, args.steps, args.warmup)
         t_op32 = time_operator(op32, U0, L, args.op_calls)
-        L64 = op.apply(U0)
-        L32 = op32.apply(U0)
-        r64 = op.diagnostics(U0, L64)["rate"]
-        r32 = op.diagnostics(U0, L32)["rate"]
-        res = float(torch.linalg.norm(L32 - L64) / torch.linalg.norm(L64))
+        e0 = fp32_error(op, op32, U0)
         out["fp32"] = {"value": ndof * 5 * args.steps / t32, "speedup_vs_fp64": t64 / t32,
                        "operator_dofs_per_s": ndof / t_op32, "operator_speedup_vs_fp64": t_op / t_op32,
-                       "residual_rel_err": res, "dissipation_rate_rel_err": abs(r32 - r64) / abs(r64)}
-        log("fp32: %.3e DoF/s (x%.2f), operator x%.2f, |L32-L64|/|L64| = %.2e"
-            % (out["fp32"]["value"], t64 / t32, t_op / t_op32, res))
+                       "residual_rel_err": e0["whole_vector"], "residual_rel_err_per_field": e0["per_field"],
+                       "dissipation_rate_rel_err": e0["dissipation_rate"],
+                       "error_state": "projected Taylor-Green initial state (smooth, Mach 0.1)"}
+        log("fp32: %.3e DoF/s (x%.2f), operator x%.2f, |L32-L64|/|L64| = %.2e, per field %s, rate %.2e"
+            % (out["fp32"]["value"], t64 / t32, t_op / t_op32, e0["whole_vector"],
+               " ".join("%.1e" % v for v in e0["per_field"].values()), e0["dissipation_rate"]))
         del op32
 
     if not args.no_cpu_baseline:
-        log("cpu baseline: oracle on %d sample cells" % args.cpu_sample_cells)
-        out["cpu_baseline"] = cpu_baseline(ne, k, nq, args.cpu_sample_cells)
+        log("cpu baseline: oracle on the 4^3 mesh and on %d / %d sample cells" % (args.cpu_sample_cells,
+                                                                               args.cpu_sample_cells_1core))
+        out["cpu_baseline"] = cpu_baseline(ne, k, nq, args.cpu_sample_cells, args.cpu_sample_cells_1core)
     print(json.dumps(out), flush=True)
 
 
