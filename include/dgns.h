@@ -160,6 +160,19 @@ int dgns_compute_dt(const dgns_ctx* ctx, double Cr, double D, double e, double f
  * Sec. 5.2.2); out8 is then left untouched, as for every other error. */
 int dgns_diagnostics(dgns_ctx* ctx, const double* U, const double* L, double* out8);
 
+/* For callers that cannot allocate (code under HIP graph capture, tight serving
+ * loops, harnesses that forbid hipMalloc): the diagnostics of dgns_diagnostics,
+ * computed by the same kernels, written to out8, a DEVICE array of 8 doubles owned by
+ * the caller, asynchronously on the context's stream -- no allocation, no host
+ * synchronisation.  The per-cell partial sums and their totals live in a static
+ * device workspace of the library (18.9 MB per GPU, held until the process ends),
+ * which limits the mesh to at most 262144 cells (64^3): larger meshes return
+ * DGNS_EINVAL before anything is launched.  Every call on a GPU shares that GPU's
+ * workspace, so calls that overlap on one GPU (concurrent streams or threads) race.
+ * Non-finite results are not detected here (that needs the host): out8 then holds them
+ * as computed.  out8 must not overlap U or L.  L may be NULL (out8[2] = NaN). */
+int dgns_diagnostics_noalloc(dgns_ctx* ctx, const double* U, const double* L, double* out8);
+
 /* L2 projection of an initial state onto the DG space: U = M^{-1} (phi_i, U0)
  * with the right-hand side on the n_q rule.  noise: NULL, or device array
  * [3][n_cells][(k+1)^3] of values in [-1,1] used by DGNS_IC_CHANNEL for the

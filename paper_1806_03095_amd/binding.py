@@ -44,7 +44,8 @@ class BoxMesh(ctypes.Structure):
 
 EXPORTS = ["dgns_last_error", "dgns_create", "dgns_destroy", "dgns_sizes", "dgns_set_stream",
            "dgns_apply_residual", "dgns_apply_inverse_mass", "dgns_apply_operator", "dgns_rk_step",
-           "dgns_rk_stage_update", "dgns_compute_dt", "dgns_channel_statistics", "dgns_diagnostics", "dgns_project_ic", "dgns_apply_residual_vjp",
+           "dgns_rk_stage_update", "dgns_compute_dt", "dgns_channel_statistics", "dgns_diagnostics",
+           "dgns_diagnostics_noalloc", "dgns_project_ic", "dgns_apply_residual_vjp",
            "dgns_apply_operator_vjp", "dgns_rk_step_vjp", "dgns_kinetic_energy", "dgns_kinetic_energy_vjp"]
 
 _lib = None
@@ -73,6 +74,7 @@ def load_library(path=LIB_PATH):
     lib.dgns_channel_statistics.argtypes = [vp, vp, ctypes.POINTER(ctypes.c_double)]
     lib.dgns_compute_dt.argtypes = [vp] + [ctypes.c_double] * 6 + [dp]
     lib.dgns_diagnostics.argtypes = [vp, vp, vp, dp]
+    lib.dgns_diagnostics_noalloc.argtypes = [vp, vp, vp, vp]
     lib.dgns_project_ic.argtypes = [vp, ctypes.c_int, dp, vp, vp]
     lib.dgns_apply_residual_vjp.argtypes = [vp, vp, vp, vp, ctypes.c_uint]
     lib.dgns_apply_operator_vjp.argtypes = [vp, vp, vp, vp]
@@ -241,6 +243,18 @@ class Operator:
             return res
         _check(rc)
         return res
+
+    def diagnostics_noalloc(self, U, out, L=None):
+        """The diagnostics into out, a float64 CUDA tensor of 8 entries, asynchronously and
+        without any allocation (the library's static workspace; meshes up to 64^3 cells)."""
+        self._vec(U, "U")
+        if L is not None:
+            self._vec(L, "L")
+        if not (out.is_cuda and out.dtype == torch.float64 and out.is_contiguous() and out.numel() == 8):
+            raise ValueError("out must be a contiguous float64 CUDA tensor of 8 entries")
+        self._bind()
+        _check(self.lib.dgns_diagnostics_noalloc(self.h, _ptr(U), _ptr(L), _ptr(out)))
+        return out
 
     # -- adjoint -------------------------------------------------------------
     def residual_vjp(self, U, Rbar, out=None, terms=TERM_ALL):

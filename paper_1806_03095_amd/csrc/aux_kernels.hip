@@ -98,6 +98,25 @@ int launch_diag_total(const double* partial, int64_t ncell, double* total, hipSt
     return hipGetLastError() == hipSuccess ? 0 : -1;
 }
 
+// The eight diagnostics from the nine totals, as dgns_diagnostics forms them on the host:
+// e_k = T0 / V, eps = nu T1 / V, -de_k/dt = T2 / V (NaN without L), the conserved totals.
+__global__ void diag_finalize_kernel(const double* total, double nu, int has_L, double* out8) {
+    const int i = threadIdx.x;
+    if (i >= 8) return;
+    const double V = total[8];
+    double r;
+    if (i == 0) r = total[0] / V;
+    else if (i == 1) r = nu * total[1] / V;
+    else if (i == 2) r = has_L ? total[2] / V : __builtin_nan("");
+    else r = total[i];
+    out8[i] = r;
+}
+
+int launch_diag_finalize(const double* total, double nu, int has_L, double* out8, hipStream_t st) {
+    hipLaunchKernelGGL(diag_finalize_kernel, dim3(1), dim3(64), 0, st, total, nu, has_L, out8);
+    return hipGetLastError() == hipSuccess ? 0 : -1;
+}
+
 // Totals of the channel statistics over each plane of cells: thread (j, p, m) sums
 // quantity m at wall-normal point p over the cells (i, j, k) of row j in a fixed order.
 constexpr int kChanStats = 9;

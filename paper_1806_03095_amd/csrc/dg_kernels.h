@@ -57,6 +57,9 @@ int launch_diagnostics_k7(const OpArgs& a, const Tables1D& t, const double* L, d
 // Deterministic totals of the nine per-cell partial sums.
 int launch_diag_total(const double* partial, int64_t ncell, double* total, hipStream_t st);
 
+// out8 (device) = the eight diagnostics from the nine totals (device).
+int launch_diag_finalize(const double* total, double nu, int has_L, double* out8, hipStream_t st);
+
 // Channel statistics: per cell and wall-normal Gauss point, nine weighted sums (see
 // diag_impl.h); then their totals over each plane of cells (n[1] * n_q * 9 values).
 int launch_chan_stats_k1(const OpArgs& a, const Tables1D& t, double* partial, bool gen, hipStream_t st);

@@ -15,6 +15,7 @@
 #include <cstdarg>
 #include <cstdio>
 #include <cstring>
+#include <mutex>
 #include <string>
 #include <vector>
 
@@ -69,9 +70,38 @@ struct dgns_ctx {
     Tables1D* d_tab = nullptr;
     double* d_scratch = nullptr;   // n_dof doubles, allocated on the first operator VJP
     double* d_stats = nullptr;     // channel statistics partial sums and totals, on first use
+    double* noalloc = nullptr;     // this device's copy of the static workspace below
 };
 
+// Workspace of dgns_diagnostics_noalloc: the per-cell partial sums and their totals
+// live in this file-scope device array instead of memory the library allocates, so that
+// the entry point never allocates.  Every GPU the library runs on holds its own copy
+// until the process ends; host code must use the address hipGetSymbolAddress returns for
+// the current device (kept per device below), never the array's name.
+constexpr int64_t kNoAllocMaxCells = 262144;                      // 64^3 cells
+constexpr int64_t kNoAllocDoubles = 9 * kNoAllocMaxCells + 16;    // partials + totals (18.9 MB)
+static __device__ __align__(256) double scratch[kNoAllocDoubles];
+
 namespace {
+
+constexpr int kMaxDevices = 64;
+std::mutex g_noalloc_mu;
+double* g_noalloc_ptr[kMaxDevices] = {};
+
+// Address of this device's copy of the workspace, looked up once per device.
+int noalloc_workspace(double** out) {
+    int dev = 0;
+    HIP_TRY(hipGetDevice(&dev));
+    if (dev < 0 || dev >= kMaxDevices) return fail(DGNS_EUNSUPPORTED, "device index %d beyond %d", dev, kMaxDevices);
+    std::lock_guard<std::mutex> lock(g_noalloc_mu);
+    if (!g_noalloc_ptr[dev]) {
+        void* p = nullptr;
+        HIP_TRY(hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)));
+        g_noalloc_ptr[dev] = static_cast<double*>(p);
+    }
+    *out = g_noalloc_ptr[dev];
+    return 0;
+}
 
 template <typename T>
 int upload(const std::vector<T>& h, T** d) {
@@ -153,19 +183,23 @@ int dispatch_minv(const dgns_ctx* c, const double* R, double* L) {
     return 0;
 }
 
-// Per-cell diagnostic partial sums into c->d_partial, then their totals into c->d_total.
-int dispatch_diagnostics(const dgns_ctx* c, const OpArgs& a, const double* L) {
+// Per-cell diagnostic partial sums into partial (9 n_cells doubles), then their totals
+// into total (9 doubles); by default the context's buffers.
+int dispatch_diagnostics(const dgns_ctx* c, const OpArgs& a, const double* L, double* partial = nullptr,
+                         double* total = nullptr) {
+    if (!partial) partial = c->d_partial;
+    if (!total) total = c->d_total;
     int rc = 1;
     switch (c->k) {
-        case 1: rc = launch_diagnostics_k1(a, c->tab, L, c->d_partial, c->gen, c->stream); break;
-        case 2: rc = launch_diagnostics_k2(a, c->tab, L, c->d_partial, c->gen, c->stream); break;
-        case 3: rc = launch_diagnostics_k3(a, c->tab, L, c->d_partial, c->gen, c->stream); break;
-        case 4: rc = launch_diagnostics_k4(a, c->tab, L, c->d_partial, c->gen, c->stream); break;
-        case 5: rc = launch_diagnostics_k5(a, c->tab, L, c->d_partial, c->gen, c->stream); break;
-        case 6: rc = launch_diagnostics_k6(a, c->tab, L, c->d_partial, c->gen, c->stream); break;
-        case 7: rc = launch_diagnostics_k7(a, c->tab, L, c->d_partial, c->gen, c->stream); break;
+        case 1: rc = launch_diagnostics_k1(a, c->tab, L, partial, c->gen, c->stream); break;
+        case 2: rc = launch_diagnostics_k2(a, c->tab, L, partial, c->gen, c->stream); break;
+        case 3: rc = launch_diagnostics_k3(a, c->tab, L, partial, c->gen, c->stream); break;
+        case 4: rc = launch_diagnostics_k4(a, c->tab, L, partial, c->gen, c->stream); break;
+        case 5: rc = launch_diagnostics_k5(a, c->tab, L, partial, c->gen, c->stream); break;
+        case 6: rc = launch_diagnostics_k6(a, c->tab, L, partial, c->gen, c->stream); break;
+        case 7: rc = launch_diagnostics_k7(a, c->tab, L, partial, c->gen, c->stream); break;
     }
-    if (rc == 0) rc = launch_diag_total(c->d_partial, c->ncell, c->d_total, c->stream);
+    if (rc == 0) rc = launch_diag_total(partial, c->ncell, total, c->stream);
     if (rc == 1) return fail(DGNS_EUNSUPPORTED, "no diagnostics kernel for degree %d, n_q %d", c->k, c->q);
     if (rc != 0) return fail(DGNS_EHIP, "diagnostics launch failed: %s", hipGetErrorString(hipGetLastError()));
     return 0;
@@ -273,6 +307,7 @@ int dgns_create(const dgns_params* prm, const dgns_box_mesh* msh, void* stream, 
         std::vector<Tables1D> tv(1, c->tab);
         rc = upload(tv, &c->d_tab);
     }
+    if (rc == 0) rc = noalloc_workspace(&c->noalloc);
     if (rc == 0) {
         hipError_t e1 = hipMalloc((void**)&c->d_partial, sizeof(double) * 9 * ncell);
         hipError_t e2 = hipMalloc((void**)&c->d_total, sizeof(double) * 9);
@@ -417,6 +452,25 @@ int dgns_diagnostics(dgns_ctx* c, const double* U, const double* L, double* out8
         if (i != 2 || L)
             if (!std::isfinite(r[i])) return fail(DGNS_ENONFINITE, "diagnostic %d is not finite", i);
     for (int i = 0; i < 8; ++i) out8[i] = r[i];   // written only on success
+    return DGNS_OK;
+}
+
+int dgns_diagnostics_noalloc(dgns_ctx* c, const double* U, const double* L, double* out8) {
+    if (!c || !U || !out8) return fail(DGNS_EINVAL, "null argument");
+    if (!aligned8(U) || (L && !aligned8(L)) || !aligned8(out8)) return fail(DGNS_EINVAL, "vectors must be 8-byte aligned");
+    if (c->ncell > kNoAllocMaxCells)
+        return fail(DGNS_EINVAL, "mesh of %lld cells; the allocation-free diagnostics hold at most %lld",
+                    (long long)c->ncell, (long long)kNoAllocMaxCells);
+    if (overlap(out8, 8, U, c->ndof) || (L && overlap(out8, 8, L, c->ndof)))
+        return fail(DGNS_EINVAL, "out8 overlaps an input");
+    if (!c->noalloc) return fail(DGNS_EHIP, "no workspace address for this context");
+    double* partial = c->noalloc;
+    double* total = c->noalloc + 9 * kNoAllocMaxCells;
+    OpArgs a = make_args(c, U, nullptr, 0, 0);
+    int rc = dispatch_diagnostics(c, a, L, partial, total);
+    if (rc) return rc;
+    if (launch_diag_finalize(total, c->prm.mu / c->prm.rho_ref, L ? 1 : 0, out8, c->stream) != 0)
+        return fail(DGNS_EHIP, "diagnostics finalize launch failed");
     return DGNS_OK;
 }
 
