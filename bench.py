@@ -4,7 +4,9 @@ Workload (default): Taylor-Green vortex on [-pi, pi]^3, 32^3 affine cells,
 degree k = 3 (LGL nodes), n_q = 6 Gauss points per direction (over-integration),
 10,485,760 float64 DoFs, Ma = 0.1, Re = 1600, Pr = 0.71.  One step = one time step
 of the five-stage 2N Runge-Kutta scheme: five evaluations of L = M^{-1}(-F_c - F_v)
-(one fused cell+face+inverse-mass kernel each) and five stage updates.
+(each a face kernel that evaluates every face once and lifts both sides, then the cell
+kernel: cell terms, the gathered face terms, inverse mass matrix, and in stages 1-4 the
+stage update) and the fifth stage's update.
 The reported value is DoFs processed per second per operator evaluation,
 N_dof * stages * steps / time, with the inputs resident in HBM.
 
@@ -478,9 +480,12 @@ def main():
     t_op = time_operator(op, U0, L, args.op_calls)
     log("fp64 operator kernel: %.1f us per launch, %.3e DoF/s" % (1e6 * t_op, ndof / t_op))
 
+    # The roofline object covers one evaluation of L: its two launches (face kernel, then
+    # cell kernel) back to back on the library's stream, timed together by HIP events on
+    # that stream; the per-kernel split is in the rocprofv3 kernel trace under profiles/.
     flop = FLOP_PER_DOF.get((k, nq))
     roof = {"bound": "alu", "achieved": None, "peak": PEAK_FP64_VALU / 1e12, "unit": "TFLOP/s", "frac": None,
-            "traffic": None}
+            "traffic": None, "kernels": "dg_face_kernel + dg_operator_kernel (one evaluation of L)"}
     if flop is not None:
         ach = flop * ndof / t_op
         roof.update(achieved=round(ach / 1e12, 3), frac=round(ach / PEAK_FP64_VALU, 4))

@@ -91,6 +91,10 @@ struct OpArgs {
     unsigned terms;
     int fuse_minv;
     RkStage rk;   // dU == nullptr: write L (or R) to out
+    // face buffer of the kernels that evaluate each face once (a separate face kernel
+    // lifts both sides' face terms; the cell kernel gathers its six): per cell and face
+    // slot d + 3 s, [2][5][(k+1)^2] values in the operator's working precision
+    void* fw;
 };
 
 template <typename Real>

@@ -71,6 +71,7 @@ struct dgns_ctx {
     double* d_scratch = nullptr;   // n_dof doubles, allocated on the first operator VJP
     double* d_stats = nullptr;     // channel statistics partial sums and totals, on first use
     double* noalloc = nullptr;     // this device's copy of the static workspace below
+    double* d_fw = nullptr;        // face buffer of the split evaluation (six lifted blocks per cell)
 };
 
 // Workspace of dgns_diagnostics_noalloc: the per-cell partial sums and their totals
@@ -122,6 +123,7 @@ void free_ctx(dgns_ctx* c) {
     hipFree(c->d_tab);
     hipFree(c->d_scratch);
     hipFree(c->d_stats);
+    hipFree(c->d_fw);
 }
 
 OpArgs make_args(const dgns_ctx* c, const double* U, double* out, unsigned terms, int fuse) {
@@ -146,6 +148,7 @@ OpArgs make_args(const dgns_ctx* c, const double* U, double* out, unsigned terms
     a.wall_T = c->prm.wall_T;
     a.terms = terms;
     a.fuse_minv = fuse;
+    a.fw = c->d_fw;
     return a;
 }
 
@@ -308,6 +311,15 @@ int dgns_create(const dgns_params* prm, const dgns_box_mesh* msh, void* stream, 
         rc = upload(tv, &c->d_tab);
     }
     if (rc == 0) rc = noalloc_workspace(&c->noalloc);
+    if (rc == 0) {
+        // the face buffer of the kernels that evaluate each face once: six blocks of
+        // 2 x 5 (k+1)^2 values per cell (float64 size, which also covers float32)
+        const int64_t nfw = ncell * 6 * 10 * (int64_t)c->n * c->n;
+        if (hipMalloc((void**)&c->d_fw, sizeof(double) * nfw) != hipSuccess) {
+            c->d_fw = nullptr;
+            rc = fail(DGNS_ENOMEM, "face buffer (%lld doubles)", (long long)nfw);
+        }
+    }
     if (rc == 0) {
         hipError_t e1 = hipMalloc((void**)&c->d_partial, sizeof(double) * 9 * ncell);
         hipError_t e2 = hipMalloc((void**)&c->d_total, sizeof(double) * 9);

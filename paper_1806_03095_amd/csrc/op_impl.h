@@ -92,15 +92,18 @@ struct ChooseP {
 //    and the face-point phase still gains: 3 ceil(n_q^2 / B) passes at w1 waves per
 //    SIMD against ceil(3 n_q^2 / B) passes at w3 waves;
 //  - else one face per group only when three faces leave no room for the tables.
-template <int N, int Q, int B, int RS, bool FUSED = (N <= 4)>
+template <int N, int Q, int B, int RS, bool FUSED = (N <= 4), bool SPLIT = false>
 struct OpSizes {
     static constexpr int N3 = N * N * N, Q2 = Q * Q;
     static constexpr int TABLES = 2 * Q * N + Q + 4 * N + 2 * N * N + N;   // KTab + MTab entries
     static constexpr int LDS_MAX = 160 * 1024;
     static constexpr int TARGET = LDS_MAX / (8 * 64 / B);   // LDS per workgroup at eight waves per CU
     static constexpr int cell(int p) { return 10 * Q * N * N + 15 * p * Q * (N + Q); }
+    // the face phases, or with the face terms in a kernel of their own (SPLIT) the staging
+    // of the cell's six lifted face blocks
     static constexpr int face(int nf) {
-        return nf == 3 ? FaceSizes<N, Q, B, 3, FUSED>::TOTAL : FaceSizes<N, Q, B, 1, FUSED>::TOTAL;
+        return SPLIT ? 6 * 2 * 5 * N * N
+                     : (nf == 3 ? FaceSizes<N, Q, B, 3, FUSED>::TOTAL : FaceSizes<N, Q, B, 1, FUSED>::TOTAL);
     }
     static constexpr int work(int nf, int p) {
         return cell(p) > face(nf) ? (cell(p) > 10 * N3 ? cell(p) : 10 * N3) : (face(nf) > 10 * N3 ? face(nf) : 10 * N3);
@@ -111,13 +114,13 @@ struct OpSizes {
     static constexpr int waves(int bytes) {
         return (LDS_MAX / bytes) * (B / 64) / 4 < 2 ? (LDS_MAX / bytes) * (B / 64) / 4 : 2;
     }
-    static constexpr int P0 = ChooseP<N, Q>::v;
+    static constexpr int P0 = SPLIT ? Q : ChooseP<N, Q>::v;
     static constexpr bool REACH3 = lds(3, fewer(3, P0)) <= TARGET;
     static constexpr bool REACH1 = B == 256 && lds(1, fewer(1, P0)) <= TARGET &&
                                    3 * ((Q2 + B - 1) / B) * waves(lds(3, P0)) <
                                        ((3 * Q2 + B - 1) / B) * waves(lds(1, fewer(1, P0)));
     static constexpr int NF = REACH3 ? 3 : (REACH1 ? 1 : (lds(3, P0) <= LDS_MAX ? 3 : 1));
-    static constexpr int P = lds(NF, fewer(NF, P0)) <= TARGET ? fewer(NF, P0) : P0;
+    static constexpr int P = SPLIT || lds(NF, fewer(NF, P0)) <= TARGET ? fewer(NF, P0) : P0;
     static constexpr int CELL = cell(P);
     static constexpr int WORK = work(NF, P);
     static constexpr bool LDS_TAB = lds(NF, P) <= LDS_MAX;
@@ -132,16 +135,49 @@ struct OpSizes {
 // the larger (N, n_q) whose LDS footprint allows fewer workgroups (unless the 1D
 // tables do not fit in LDS: that kernel spills, and more waves of it only add spill
 // traffic).
+// The face kernel (each face once, both sides lifted): one workgroup per cell for its
+// three faces xi_d = 1 (and its wall faces xi_d = 0), one face point per thread --
+// 64 threads for n_q <= 4, else 128 or 256 as 3 n_q^2 requires.  The face terms move to
+// this kernel (SPLIT) for every (N, n_q, precision) where one pass covers the points
+// of the three faces and the plan fits a compute unit.
+template <int N, int Q, typename Real>
+struct FaceBlock {
+    static constexpr int threads = Q <= 4 ? 64 : (3 * Q * Q <= 128 ? 128 : 256);
+    static constexpr bool fused = N <= 4;
+    using FS = FaceSizes<N, Q, threads, 3, fused>;
+    using FS1 = FaceSizes<N, Q, threads, 1, fused>;
+    static constexpr bool one_pass = 3 * Q * Q <= threads;
+    static constexpr int lds = (FS::TOTAL + 5 * N * N * N + 2 * Q * N + Q + 4 * N) * (int)sizeof(Real) + 1024;
+    static_assert(FS1::TOTAL <= FS::TOTAL, "single-face layout inside the three-face layout");
+};
+
+// Measured on MI355X (about 10M DoFs per mesh, DoF/s of one evaluation with and without the
+// face kernel): the split is 2-22% faster for k >= 2 except k=5 n_q=6 float32 (9% slower)
+// and k=7 n_q=8 float64 (17% slower), and 5-8% slower for k = 1 except k=1 n_q=3 float32;
+// those keep the element-centric faces.
+template <int N, int Q, typename Real>
+constexpr bool split_measured_slower() {
+    constexpr bool fp64 = sizeof(Real) == sizeof(double);
+    return (N == 2 && (fp64 || Q == 2)) || (N == 6 && Q == 6 && !fp64) || (N == 8 && Q == 8 && fp64);
+}
+
+template <int N, int Q, typename Real>
+struct FaceSplit {
+    static constexpr bool value = FaceBlock<N, Q, Real>::one_pass && FaceBlock<N, Q, Real>::lds <= 160 * 1024 &&
+                                  !split_measured_slower<N, Q, Real>();
+};
+
 template <int N, int Q, typename Real>
 struct OpBlock {
-    using S128 = OpSizes<N, Q, 128, (int)sizeof(Real), (N <= 4)>;
-    using S128F = OpSizes<N, Q, 128, (int)sizeof(Real), true>;
+    static constexpr bool split = FaceSplit<N, Q, Real>::value;
+    using S128 = OpSizes<N, Q, 128, (int)sizeof(Real), (N <= 4), split>;
+    using S128F = OpSizes<N, Q, 128, (int)sizeof(Real), true, split>;
     static constexpr int lds128 = (S128::WORK + 10 * N * N * N + S128::TABLES) * (int)sizeof(Real) + 1024;
     static constexpr int lds128f = (S128F::WORK + 10 * N * N * N + S128F::TABLES) * (int)sizeof(Real) + 1024;
     // traces fused into the t0 sweep: always for N <= 4; for larger N only where dropping
     // their LDS area is what admits 128-thread workgroups (for N >= 5 the separate trace
     // phase is otherwise faster: more items per phase)
-    static constexpr bool fused = N <= 4 || (lds128 > 40 * 1024 && lds128f <= 40 * 1024 && S128F::LDS_TAB);
+    static constexpr bool fused = N <= 4 || (!split && lds128 > 40 * 1024 && lds128f <= 40 * 1024 && S128F::LDS_TAB);
     static constexpr int threads =
         Q <= 4 ? 64 : (((fused ? lds128f : lds128) <= 40 * 1024 || !S128::LDS_TAB) ? 128 : 256);
 };
@@ -266,6 +302,46 @@ struct FaceInfo {
     int wall[6];
 };
 
+// Fills fi, the penalties sTau and, on affine meshes, the per-direction unit normals
+// and permuted metric rows (sFn, sJr) of cell e's six faces (threads 0..5; the caller syncs).
+template <typename Real, bool GEN>
+__device__ __forceinline__ void face_info_setup(const OpArgs& a, int64_t e, FaceInfo& fi, Real* sTau, Real* sFn,
+                                                Real* sJr) {
+    for (int f = threadIdx.x; f < 6; f += blockDim.x) {
+        const int i0 = (int)(e % a.n[0]), i1 = (int)((e / a.n[0]) % a.n[1]), i2 = (int)(e / ((int64_t)a.n[0] * a.n[1]));
+        const int d = f % 3, s = f / 3;
+        const int nd = d == 0 ? a.n[0] : (d == 1 ? a.n[1] : a.n[2]);
+        const int per = d == 0 ? a.periodic[0] : (d == 1 ? a.periodic[1] : a.periodic[2]);
+        const int id = d == 0 ? i0 : (d == 1 ? i1 : i2);
+        // tangential indices (t0 < t1) and the extent of t0
+        const int it0 = d == 0 ? i1 : i0, it1 = d == 2 ? i1 : i2;
+        const int nt0 = d == 0 ? a.n[1] : a.n[0];
+        int jd = id + (s ? 1 : -1);
+        int wall = 0;
+        if (jd < 0 || jd >= nd) {
+            if (per) jd = (jd + nd) % nd;
+            else wall = 1;
+        }
+        const int j0 = d == 0 ? jd : i0, j1 = d == 1 ? jd : i1, j2 = d == 2 ? jd : i2;
+        fi.enb[f] = wall ? e : j0 + (int64_t)a.n[0] * (j1 + (int64_t)a.n[1] * j2);
+        fi.fid[f] = (id + s) + (int64_t)(nd + 1) * (it0 + (int64_t)nt0 * it1);
+        fi.wall[f] = wall;
+        const double* tf = d == 0 ? a.tau_face[0] : (d == 1 ? a.tau_face[1] : a.tau_face[2]);
+        sTau[f] = (Real)tf[fi.fid[f]];
+        if (!GEN && s == 0) {
+            const double* row = a.cell_metric + e * 10 + 3 * d;
+            const double l = sqrt(row[0] * row[0] + row[1] * row[1] + row[2] * row[2]);
+            sFn[4 * d + 0] = (Real)(row[0] / l);
+            sFn[4 * d + 1] = (Real)(row[1] / l);
+            sFn[4 * d + 2] = (Real)(row[2] / l);
+            sFn[4 * d + 3] = (Real)l;
+            const int rows[3] = {d == 0 ? 1 : 0, d == 2 ? 1 : 2, d};
+            for (int r = 0; r < 3; ++r)
+                for (int j = 0; j < 3; ++j) sJr[9 * d + 3 * r + j] = (Real)a.cell_metric[e * 10 + 3 * rows[r] + j];
+        }
+    }
+}
+
 // Value and physical gradient of one side at face point (q0, q1): the sweep along
 // t1 of the t0-swept traces A[3][c][N][Q] (value, t0-derivative, normal derivative).
 template <int N, int Q, typename Real>
@@ -319,18 +395,20 @@ __device__ __forceinline__ void load_face_point_rows(const KTab<N, Q, Real>& tb,
     }
 }
 
-// Test integration of the face-point coefficients r2 [f][val, g_t0, g_t1, g_n][c][q1][q0]
-// of the NF faces xi_d = s, d = d0 .. d0 + NF - 1, against the cell's basis functions,
-// accumulated into sR: value part through phi_i, gradient part through grad_xi phi_i.
-template <int N, int Q, typename Real, int NF = 3>
-__device__ __forceinline__ void face_test_accumulate(const KTab<N, Q, Real>& tb, int s, int d0, Real* r1, Real* r2,
-                                                     Real* sR) {
-    constexpr int N2 = N * N, N3 = N2 * N, Q2 = Q * Q;
+// Test integration of the face-point coefficients out [f][val, g_t0, g_t1, g_n][c][q1][q0]
+// of NF faces against the face-local tensor basis (a along t0, b along t1): the value
+// part and the tangential gradient parts through phi_a(t0) phi_b(t1), the normal part
+// separately, giving per face W0 (to be multiplied by l_m(s) of the normal direction)
+// and W1 (by l_m'(s)), [2][c][b][a] at wb(f) (wb(f) == nullptr: face skipped).  Two
+// cooperative phases through t1 [f][3][c][N][Q]; the caller syncs after the second.
+template <int N, int Q, typename Real, int NF, typename WB>
+__device__ __forceinline__ void face_lift(const KTab<N, Q, Real>& tb, const Real* out, Real* t1, WB wb) {
+    constexpr int N2 = N * N, Q2 = Q * Q;
     const int tid = threadIdx.x, nth = blockDim.x;
-    // transposed along t1: P0 = S^T val + D^T g_t1, P1 = S^T g_t0, Pn = S^T g_n    r1 [f][3][c][b][q0]
+    // transposed along t1: P0 = S^T val + D^T g_t1, P1 = S^T g_t0, Pn = S^T g_n    t1 [f][3][c][b][q0]
     for (int it = tid; it < NF * 5 * N * Q; it += nth) {
         const int q0 = it % Q, ib = (it / Q) % N, c = (it / (Q * N)) % 5, d = it / (5 * Q * N);
-        const Real* o = r2 + d * 4 * 5 * Q2 + c * Q2 + q0;
+        const Real* o = out + d * 4 * 5 * Q2 + c * Q2 + q0;
         Real p0 = 0, p1 = 0, pn = 0;
 #pragma unroll
         for (int q1 = 0; q1 < Q; ++q1) {
@@ -338,60 +416,80 @@ __device__ __forceinline__ void face_test_accumulate(const KTab<N, Q, Real>& tb,
             p1 += tb.S[q1][ib] * o[1 * 5 * Q2 + q1 * Q];
             pn += tb.S[q1][ib] * o[3 * 5 * Q2 + q1 * Q];
         }
-        Real* t = r1 + d * 3 * 5 * N * Q + c * N * Q + ib * Q + q0;
+        Real* t = t1 + d * 3 * 5 * N * Q + c * N * Q + ib * Q + q0;
         t[0] = p0;
         t[5 * N * Q] = p1;
         t[2 * 5 * N * Q] = pn;
     }
     __syncthreads();
 
-    // transposed along t0: W0 = S^T P0 + D^T P1, W1 = S^T Pn    r2 [f][2][c][b][a]
+    // transposed along t0: W0 = S^T P0 + D^T P1, W1 = S^T Pn    [2][c][b][a]
     for (int it = tid; it < NF * 5 * N2; it += nth) {
         const int ia = it % N, ib = (it / N) % N, c = (it / N2) % 5, d = it / (5 * N2);
-        const Real* t = r1 + d * 3 * 5 * N * Q + c * N * Q + ib * Q;
+        Real* w = wb(d);
+        if (!w) continue;
+        const Real* t = t1 + d * 3 * 5 * N * Q + c * N * Q + ib * Q;
         Real w0 = 0, w1 = 0;
 #pragma unroll
         for (int q0 = 0; q0 < Q; ++q0) {
             w0 += tb.S[q0][ia] * t[q0] + tb.D[q0][ia] * t[5 * N * Q + q0];
             w1 += tb.S[q0][ia] * t[2 * 5 * N * Q + q0];
         }
-        Real* w = r2 + d * 2 * 5 * N2 + c * N2 + ib * N + ia;
-        w[0] = w0;
-        w[5 * N2] = w1;
+        w[c * N2 + ib * N + ia] = w0;
+        w[5 * N2 + c * N2 + ib * N + ia] = w1;
     }
-    __syncthreads();
+}
 
-    // R[c](a, b, m) += sum_f W0_f(a, b) l_m(s) + W1_f(a, b) l'_m(s)
-    for (int it = tid; it < 5 * N3; it += nth) {
+// R[c](a, b, m) += sum_f W0_f(a, b) l_m(s) + W1_f(a, b) l'_m(s) over the NF faces xi_d = s,
+// d = d0 .. d0 + NF - 1, whose lifted blocks W_f [2][c][b][a] follow each other at w.
+template <int N, typename Real, int NF, typename Tab>
+__device__ __forceinline__ void face_accumulate(const Tab& tb, int s, int d0, const Real* w, Real* sR) {
+    constexpr int N2 = N * N, N3 = N2 * N;
+    for (int it = threadIdx.x; it < 5 * N3; it += blockDim.x) {
         const int c = it / N3, r = it % N3;
         const int x0 = r % N, x1 = (r / N) % N, x2 = r / N2;
-        const Real* w = r2 + c * N2;
+        const Real* wc = w + c * N2;
         Real acc;
         if constexpr (NF == 3) {
             // face d = 0: (a, b, m) = (x1, x2, x0); d = 1: (x0, x2, x1); d = 2: (x0, x1, x2)
-            acc = w[0 * 2 * 5 * N2 + x2 * N + x1] * tb.fv[s][x0] + w[(0 * 2 + 1) * 5 * N2 + x2 * N + x1] * tb.fd[s][x0];
-            acc += w[1 * 2 * 5 * N2 + x2 * N + x0] * tb.fv[s][x1] + w[(1 * 2 + 1) * 5 * N2 + x2 * N + x0] * tb.fd[s][x1];
-            acc += w[2 * 2 * 5 * N2 + x1 * N + x0] * tb.fv[s][x2] + w[(2 * 2 + 1) * 5 * N2 + x1 * N + x0] * tb.fd[s][x2];
+            acc = wc[0 * 2 * 5 * N2 + x2 * N + x1] * tb.fv[s][x0] + wc[(0 * 2 + 1) * 5 * N2 + x2 * N + x1] * tb.fd[s][x0];
+            acc += wc[1 * 2 * 5 * N2 + x2 * N + x0] * tb.fv[s][x1] + wc[(1 * 2 + 1) * 5 * N2 + x2 * N + x0] * tb.fd[s][x1];
+            acc += wc[2 * 2 * 5 * N2 + x1 * N + x0] * tb.fv[s][x2] + wc[(2 * 2 + 1) * 5 * N2 + x1 * N + x0] * tb.fd[s][x2];
         } else {
             // the single face d0 (uniform over the workgroup)
             const int ab = d0 == 0 ? x2 * N + x1 : (d0 == 1 ? x2 * N + x0 : x1 * N + x0);
             const int m = d0 == 0 ? x0 : (d0 == 1 ? x1 : x2);
-            acc = w[ab] * tb.fv[s][m] + w[5 * N2 + ab] * tb.fd[s][m];
+            acc = wc[ab] * tb.fv[s][m] + wc[5 * N2 + ab] * tb.fd[s][m];
         }
         sR[it] += acc;
     }
+}
+
+// Test integration of one face group into sR: face_lift into the W area (r2), then
+// face_accumulate.
+template <int N, int Q, typename Real, int NF = 3>
+__device__ __forceinline__ void face_test_accumulate(const KTab<N, Q, Real>& tb, int s, int d0, Real* r1, Real* r2,
+                                                     Real* sR) {
+    constexpr int N2 = N * N;
+    face_lift<N, Q, Real, NF>(tb, r2, r1, [r2](int f) { return r2 + f * 2 * 5 * N2; });
+    __syncthreads();
+    face_accumulate<N, Real, NF>(tb, s, d0, r2, sR);
     __syncthreads();
 }
 
 // One face point it = f * n_q^2 + q0 + n_q q1 of the group of faces xi_d = s,
 // d = d0 + f: the t1 contraction of both sides' t0-swept traces A (layout
 // [f][side][3][c][N][Q]), the numerical fluxes, and the reference-space test
-// coefficients res[kind * 5 + c], kind = value, g_t0, g_t1, g_n.
-template <int N, int Q, typename Real, bool GEN>
+// coefficients res[kind * 5 + c], kind = value, g_t0, g_t1, g_n, of the own side.
+// TWO: also those of the other side (not at walls), whose value part is the negative
+// of the own side's (the numerical flux is single-valued and the normals opposite):
+// res1[(kind - 1) * 5 + c] for the three gradient kinds, with the other side's state
+// in the symmetry term and its own metric rows.
+template <int N, int Q, typename Real, bool GEN, bool TWO = false>
 __device__ __forceinline__ void face_point(const OpArgs& a, const KTab<N, Q, Real>& lt, const Phys<Real>& ph, bool conv,
                                            bool visc, int s, int d0, const FaceInfo& fi, const Real* sTau,
                                            const Real* sFn, const Real* sJr, Real detJ, const Real* r1, int it,
-                                           Real (&res)[20]) {
+                                           Real (&res)[20], Real (&res1)[15]) {
     constexpr int Q2 = Q * Q;
     const int f = it / Q2, d = d0 + f, pt = it % Q2, q0 = pt % Q, q1 = pt / Q;
     const int fslot = d + 3 * s;
@@ -399,7 +497,7 @@ __device__ __forceinline__ void face_point(const OpArgs& a, const KTab<N, Q, Rea
     // reference axes of the face: tangential t0 < t1, normal d; rows[r] is the
     // row of J^{-1} that multiplies the derivative along the face's axis r
     const int rows[3] = {d == 0 ? 1 : 0, d == 2 ? 1 : 2, d};
-    Real Jm[9], nrm[3], dAw;
+    Real Jm[9], Jp[9], nrm[3], dAw;
     const double* fdp = nullptr;
     if constexpr (GEN) {
         fdp = a.face_data[d] + fi.fid[fslot] * 22 * Q2 + pt;
@@ -426,7 +524,7 @@ __device__ __forceinline__ void face_point(const OpArgs& a, const KTab<N, Q, Rea
     // physical gradient, F_c.n and F_v.n go straight into the point's coefficient
     //   val = -1/2 (F_c^- + F_c^+).n + 1/2 (F_v^- + F_v^+).n - (Lambda/2 + tau)(U^- - U^+)
     Real Um[5], Up[5], val[5], lam_m = 0, lam_p = 0;
-    Prim<Real> sm;
+    Prim<Real> sm, sp;
     {
         Real G[5][3], Fn[5];
         load_face_point_rows<N, Q, Real>(lt, r1 + (f * 2 + 0) * 3 * 5 * N * Q, q0, q1, Jm, Um, G);
@@ -446,7 +544,6 @@ __device__ __forceinline__ void face_point(const OpArgs& a, const KTab<N, Q, Rea
         if (wall) {
             wall_mirror(Um, sm, ph, Up);   // the exterior gradient is the interior one: G is kept
         } else {
-            Real Jp[9];
             if constexpr (GEN) {
                 const int oth = s ? 13 : 4;
 #pragma unroll
@@ -462,7 +559,7 @@ __device__ __forceinline__ void face_point(const OpArgs& a, const KTab<N, Q, Rea
             }
             load_face_point_rows<N, Q, Real>(lt, r1 + (f * 2 + 1) * 3 * 5 * N * Q, q0, q1, Jp, Up, G);
         }
-        const Prim<Real> sp = primitives(Up, ph);
+        sp = primitives(Up, ph);
         if (conv) {
             lam_p = convective_normal(Up, sp, nrm, ph, Fn);
 #pragma unroll
@@ -502,23 +599,34 @@ __device__ __forceinline__ void face_point(const OpArgs& a, const KTab<N, Q, Rea
             res[(1 + r) * 5 + c] =
                 (Jm[r * 3] * gphys[c][0] + Jm[r * 3 + 1] * gphys[c][1] + Jm[r * 3 + 2] * gphys[c][2]) * half_dAw;
     }
+    if constexpr (TWO) {
+        // the other side: F_v(U^+, [[U]]) with the same jump tensor (U^- - U^+) (x) n^-,
+        // projected on the other cell's metric rows
+        if (visc && !wall) {
+            viscous_flux_rank1(sp, jump, nrm, ph, gphys);
+#pragma unroll
+            for (int c = 0; c < 5; ++c)
+#pragma unroll
+                for (int r = 0; r < 3; ++r)
+                    res1[r * 5 + c] =
+                        (Jp[r * 3] * gphys[c][0] + Jp[r * 3 + 1] * gphys[c][1] + Jp[r * 3 + 2] * gphys[c][2]) * half_dAw;
+        } else {
+#pragma unroll
+            for (int m = 0; m < 15; ++m) res1[m] = 0;
+        }
+    }
 }
 
-// The three faces xi_d = s (d = 0, 1, 2) of the cell: traces, fluxes, test
-// integration, accumulated into sR.  NF = 3 processes the faces of all three
-// directions together (d0 = 0); NF = 1 the single face xi_{d0} = s.
-template <int N, int Q, typename Real, bool GEN, int NF>
-__device__ __forceinline__ void face_group(const OpArgs& a, const KTab<N, Q, Real>& lt, const Phys<Real>& ph, bool conv,
-                                           bool visc, int s, int d0, const FaceInfo& fi, const Real* sTau,
-                                           const Real* sFn, const Real* sJr, Real detJ, const Real* sU, Real* sR,
-                                           Real* sW) {
-    using FS = FaceSizes<N, Q, OpBlock<N, Q, Real>::threads, NF, OpBlock<N, Q, Real>::fused>;
-    constexpr int N2 = N * N, N3 = N2 * N, Q2 = Q * Q;
-    // work regions: SW (swept traces, read by the point phase), TR (traces), OUT
-    // (point results), T1 (t1-transposed), W (lifted): see FaceSizes
+// Traces of U and of its normal derivative on both sides of the NF faces xi_d = s,
+// d = d0 .. d0 + NF - 1 (own side from sU, the neighbour's from its coefficients in
+// global memory, nothing for the exterior side of a wall), swept along t0:
+// SW = sW [f][side][3][c][N][Q] (value, t0-derivative, normal derivative), using the
+// TR area of the layout FS for unfused traces.  Ends with a barrier.
+template <int N, int Q, typename Real, int NF, typename FS>
+__device__ __forceinline__ void face_traces_sweep(const OpArgs& a, const KTab<N, Q, Real>& lt, int s, int d0,
+                                                  const FaceInfo& fi, const Real* sU, Real* sW) {
+    constexpr int N2 = N * N, N3 = N2 * N;
     Real* r1 = sW;                 // SW
-    Real* r2 = sW + FS::OUT_OFF;   // OUT, later W
-    Real* rt1 = sW + FS::T1_OFF;   // T1
     const int tid = threadIdx.x, nth = blockDim.x;
     const int64_t cstride = a.ncell * N3;
 
@@ -642,14 +750,35 @@ __device__ __forceinline__ void face_group(const OpArgs& a, const KTab<N, Q, Rea
         __syncthreads();
     }
 
+}
+
+// The three faces xi_d = s (d = 0, 1, 2) of the cell: traces, fluxes, test
+// integration, accumulated into sR.  NF = 3 processes the faces of all three
+// directions together (d0 = 0); NF = 1 the single face xi_{d0} = s.
+template <int N, int Q, typename Real, bool GEN, int NF>
+__device__ __forceinline__ void face_group(const OpArgs& a, const KTab<N, Q, Real>& lt, const Phys<Real>& ph, bool conv,
+                                           bool visc, int s, int d0, const FaceInfo& fi, const Real* sTau,
+                                           const Real* sFn, const Real* sJr, Real detJ, const Real* sU, Real* sR,
+                                           Real* sW) {
+    using FS = FaceSizes<N, Q, OpBlock<N, Q, Real>::threads, NF, OpBlock<N, Q, Real>::fused>;
+    constexpr int Q2 = Q * Q;
+    // work regions: SW (swept traces, read by the point phase), TR (traces), OUT
+    // (point results), T1 (t1-transposed), W (lifted): see FaceSizes
+    Real* r1 = sW;                 // SW
+    Real* r2 = sW + FS::OUT_OFF;   // OUT, later W
+    Real* rt1 = sW + FS::T1_OFF;   // T1
+    const int tid = threadIdx.x, nth = blockDim.x;
+
+    face_traces_sweep<N, Q, Real, NF, FS>(a, lt, s, d0, fi, sU, sW);
+
     // pointwise: numerical fluxes and reference-space test coefficients at every
     // face point, stored as OUT [f][kind: val, g_t0, g_t1, g_n][c][q1][q0].  When one
     // pass of the workgroup covers all face points, the results wait in registers
     // across a barrier and overwrite the swept traces (smaller LDS footprint).
     if constexpr (FS::ALIAS) {
-        Real res[20];
+        Real res[20], res1[15];
         const bool act = tid < NF * Q2;
-        if (act) face_point<N, Q, Real, GEN>(a, lt, ph, conv, visc, s, d0, fi, sTau, sFn, sJr, detJ, r1, tid, res);
+        if (act) face_point<N, Q, Real, GEN>(a, lt, ph, conv, visc, s, d0, fi, sTau, sFn, sJr, detJ, r1, tid, res, res1);
         __syncthreads();
         if (act) {
             Real* o = r2 + (tid / Q2) * 4 * 5 * Q2 + tid % Q2;
@@ -658,8 +787,8 @@ __device__ __forceinline__ void face_group(const OpArgs& a, const KTab<N, Q, Rea
         }
     } else {
         for (int it = tid; it < NF * Q2; it += nth) {
-            Real res[20];
-            face_point<N, Q, Real, GEN>(a, lt, ph, conv, visc, s, d0, fi, sTau, sFn, sJr, detJ, r1, it, res);
+            Real res[20], res1[15];
+            face_point<N, Q, Real, GEN>(a, lt, ph, conv, visc, s, d0, fi, sTau, sFn, sJr, detJ, r1, it, res, res1);
             Real* o = r2 + (it / Q2) * 4 * 5 * Q2 + it % Q2;
 #pragma unroll
             for (int m = 0; m < 20; ++m) o[m * Q2] = res[m];
@@ -675,7 +804,8 @@ __device__ __forceinline__ void face_group(const OpArgs& a, const KTab<N, Q, Rea
 template <int N, int Q, typename Real, bool GEN>
 __global__ void __launch_bounds__((OpBlock<N, Q, Real>::threads)) __attribute__((amdgpu_waves_per_eu(N <= 2 ? 3 : 2)))
 dg_operator_kernel(OpArgs a, KTab<N, Q, Real> tb, MTab<N, Real> mt) {
-    using Sz = OpSizes<N, Q, OpBlock<N, Q, Real>::threads, (int)sizeof(Real), OpBlock<N, Q, Real>::fused>;
+    constexpr bool SPLIT = OpBlock<N, Q, Real>::split;
+    using Sz = OpSizes<N, Q, OpBlock<N, Q, Real>::threads, (int)sizeof(Real), OpBlock<N, Q, Real>::fused, SPLIT>;
     constexpr int P = Sz::P;
     constexpr int N2 = N * N, N3 = N2 * N, Q2 = Q * Q, Q3 = Q2 * Q;
     constexpr int ZS = CellSizes<N, Q, P>::Z, YS = CellSizes<N, Q, P>::Y;
@@ -699,6 +829,21 @@ dg_operator_kernel(OpArgs a, KTab<N, Q, Real> tb, MTab<N, Real> mt) {
         const int c = i / N3, j = i % N3;
         sU[i] = (Real)a.U[c * cstride + e * N3 + j];
         sR[i] = Real(0);
+    }
+    // face terms lifted by the face kernel: the cell's six blocks [slot][2][5][N^2], loaded
+    // into registers now so that their latency overlaps the cell term, and added to the
+    // residual after it
+    constexpr int FWB = 2 * 5 * N2;
+    constexpr int FWV = SPLIT ? (6 * FWB + OpBlock<N, Q, Real>::threads - 1) / OpBlock<N, Q, Real>::threads : 1;
+    const bool gather = SPLIT && (conv || visc);
+    Real fwr[FWV];
+    if (gather) {
+        const Real* fw = static_cast<const Real*>(a.fw) + e * 6 * FWB;
+#pragma unroll
+        for (int v = 0; v < FWV; ++v) {
+            const int i = tid + v * OpBlock<N, Q, Real>::threads;
+            fwr[v] = i < 6 * FWB ? fw[i] : Real(0);
+        }
     }
     // Fused Runge-Kutta stage: in the 128-thread float64 kernels (k <= 3), whose register
     // budget has the room for a thread's share of the cell's dU (at most three values),
@@ -737,39 +882,7 @@ dg_operator_kernel(OpArgs a, KTab<N, Q, Real> tb, MTab<N, Real> mt) {
     const MTab<N, Real>& lm = *lmp;
     const KTab<N, Q, Real>& lt = *ltp;
     for (int i = tid; i < N; i += nth) lwm[i] = mt.wm[i];
-    for (int f = tid; f < 6; f += nth) {
-        const int i0 = (int)(e % a.n[0]), i1 = (int)((e / a.n[0]) % a.n[1]), i2 = (int)(e / ((int64_t)a.n[0] * a.n[1]));
-        const int d = f % 3, s = f / 3;
-        const int nd = d == 0 ? a.n[0] : (d == 1 ? a.n[1] : a.n[2]);
-        const int per = d == 0 ? a.periodic[0] : (d == 1 ? a.periodic[1] : a.periodic[2]);
-        const int id = d == 0 ? i0 : (d == 1 ? i1 : i2);
-        // tangential indices (t0 < t1) and the extent of t0
-        const int it0 = d == 0 ? i1 : i0, it1 = d == 2 ? i1 : i2;
-        const int nt0 = d == 0 ? a.n[1] : a.n[0];
-        int jd = id + (s ? 1 : -1);
-        int wall = 0;
-        if (jd < 0 || jd >= nd) {
-            if (per) jd = (jd + nd) % nd;
-            else wall = 1;
-        }
-        const int j0 = d == 0 ? jd : i0, j1 = d == 1 ? jd : i1, j2 = d == 2 ? jd : i2;
-        fi.enb[f] = wall ? e : j0 + (int64_t)a.n[0] * (j1 + (int64_t)a.n[1] * j2);
-        fi.fid[f] = (id + s) + (int64_t)(nd + 1) * (it0 + (int64_t)nt0 * it1);
-        fi.wall[f] = wall;
-        const double* tf = d == 0 ? a.tau_face[0] : (d == 1 ? a.tau_face[1] : a.tau_face[2]);
-        sTau[f] = (Real)tf[fi.fid[f]];
-        if (!GEN && s == 0) {
-            const double* row = a.cell_metric + e * 10 + 3 * d;
-            const double l = sqrt(row[0] * row[0] + row[1] * row[1] + row[2] * row[2]);
-            sFn[4 * d + 0] = (Real)(row[0] / l);
-            sFn[4 * d + 1] = (Real)(row[1] / l);
-            sFn[4 * d + 2] = (Real)(row[2] / l);
-            sFn[4 * d + 3] = (Real)l;
-            const int rows[3] = {d == 0 ? 1 : 0, d == 2 ? 1 : 2, d};
-            for (int r = 0; r < 3; ++r)
-                for (int j = 0; j < 3; ++j) sJr[9 * d + 3 * r + j] = (Real)a.cell_metric[e * 10 + 3 * rows[r] + j];
-        }
-    }
+    if constexpr (!SPLIT) face_info_setup<Real, GEN>(a, e, fi, sTau, sFn, sJr);
 
     // cell-constant metric (affine)
     Real Ji[9], detJ = Real(1);
@@ -779,6 +892,7 @@ dg_operator_kernel(OpArgs a, KTab<N, Q, Real> tb, MTab<N, Real> mt) {
         detJ = (Real)a.cell_metric[e * 10 + 9];
     }
     __syncthreads();
+
 
     if (conv || visc) {
         // ------------------------------------------------------------ cell term
@@ -955,7 +1069,19 @@ dg_operator_kernel(OpArgs a, KTab<N, Q, Real> tb, MTab<N, Real> mt) {
         }
 
         // ------------------------------------------------------------ face terms
-        if constexpr (Sz::NF == 3) {
+        if constexpr (SPLIT) {
+            // the face kernel's lifted blocks, held in registers since the start: staged in
+            // the work area, then R += the six faces: slots 0..2 (xi_d = 0), 3..5 (xi_d = 1)
+#pragma unroll
+            for (int v = 0; v < FWV; ++v) {
+                const int i = tid + v * B;
+                if (i < 6 * FWB) sW[i] = fwr[v];
+            }
+            __syncthreads();
+            face_accumulate<N, Real, 3>(lt, 0, 0, sW, sR);
+            face_accumulate<N, Real, 3>(lt, 1, 0, sW + 3 * FWB, sR);
+            __syncthreads();
+        } else if constexpr (Sz::NF == 3) {
             face_group<N, Q, Real, GEN, 3>(a, lt, ph, conv, visc, 0, 0, fi, sTau, sFn, sJr, detJ, sU, sR, sW);
             face_group<N, Q, Real, GEN, 3>(a, lt, ph, conv, visc, 1, 0, fi, sTau, sFn, sJr, detJ, sU, sR, sW);
         } else {
@@ -1034,6 +1160,92 @@ dg_operator_kernel(OpArgs a, KTab<N, Q, Real> tb, MTab<N, Real> mt) {
             const int c = i / N3, j = i % N3;
             a.out[c * cstride + e * N3 + j] = (double)sR[i];
         }
+    }
+}
+
+// Face kernel: every face of the mesh once, both sides (face-centric), for the cells
+// whose operator kernel gathers its face terms instead of computing them (SPLIT).  One
+// workgroup per cell e takes its three faces xi_d = 1, shared with the upper neighbour
+// across each (or with the exterior mirror state at a wall), and any wall face xi_d = 0.
+// For each face it forms the traces of both sides, the numerical fluxes at the n_q^2
+// points (one point per thread; the coefficients wait in registers across barriers),
+// and lifts both sides' terms onto the face-local tensor basis; the lifted blocks
+// [2][5][N^2] go to the face buffer slot of the cell that owns that side: e's slot
+// d + 3 for its own side, the neighbour's slot d for the other.  Each slot is written by
+// exactly one workgroup, so the buffer needs no clearing and no atomics.
+template <int N, int Q, typename Real, bool GEN>
+__global__ void __launch_bounds__((FaceBlock<N, Q, Real>::threads)) __attribute__((amdgpu_waves_per_eu(2)))
+dg_face_kernel(OpArgs a, KTab<N, Q, Real> tb) {
+    using FB = FaceBlock<N, Q, Real>;
+    using FS = typename FB::FS;
+    using FS1 = typename FB::FS1;
+    constexpr int N2 = N * N, N3 = N2 * N, Q2 = Q * Q, FWB = 2 * 5 * N2;
+    static_assert(FB::one_pass && FS::ALIAS && FS1::ALIAS, "one face point per thread");
+    __shared__ Real sU[5 * N3];
+    __shared__ Real sW[FS::TOTAL];
+    __shared__ FaceInfo fi;
+    __shared__ Real sTau[6];
+    __shared__ Real sFn[12];
+    __shared__ Real sJr[GEN ? 1 : 27];
+    __shared__ KTab<N, Q, Real> lt;
+
+    const int64_t e = blockIdx.x;
+    const int tid = threadIdx.x;
+    const Phys<Real> ph = make_phys<Real>(a);
+    const bool conv = (a.terms & 1u) != 0;
+    const bool visc = (a.terms & 2u) != 0;
+    const int64_t cstride = a.ncell * N3;
+    Real* fw = static_cast<Real*>(a.fw);
+
+    for (int i = tid; i < 5 * N3; i += blockDim.x) sU[i] = (Real)a.U[(i / N3) * cstride + e * N3 + i % N3];
+    copy_table<KTab<N, Q, Real>, Real>(tb, lt);
+    face_info_setup<Real, GEN>(a, e, fi, sTau, sFn, sJr);
+    Real detJ = Real(1);
+    if constexpr (!GEN) detJ = (Real)a.cell_metric[e * 10 + 9];
+    __syncthreads();
+
+    // the three faces xi_d = 1, both sides
+    face_traces_sweep<N, Q, Real, 3, FS>(a, lt, 1, 0, fi, sU, sW);
+    Real res[20], res1[15];
+    const bool act = tid < 3 * Q2;
+    if (act) face_point<N, Q, Real, GEN, true>(a, lt, ph, conv, visc, 1, 0, fi, sTau, sFn, sJr, detJ, sW, tid, res, res1);
+    __syncthreads();
+    Real* out = sW + FS::OUT_OFF;
+    Real* t1 = sW + FS::T1_OFF;
+    Real* o = out + (tid / Q2) * 4 * 5 * Q2 + tid % Q2;
+    if (act) {
+#pragma unroll
+        for (int m = 0; m < 20; ++m) o[m * Q2] = res[m];
+    }
+    __syncthreads();
+    face_lift<N, Q, Real, 3>(lt, out, t1, [&](int f) { return fw + (e * 6 + 3 + f) * FWB; });
+    // the other side's coefficients replace the own side's (its lift above has read them):
+    // value part negated, gradient parts from res1
+    if (act) {
+#pragma unroll
+        for (int c = 0; c < 5; ++c) o[c * Q2] = -res[c];
+#pragma unroll
+        for (int m = 0; m < 15; ++m) o[(5 + m) * Q2] = res1[m];
+    }
+    __syncthreads();
+    face_lift<N, Q, Real, 3>(lt, out, t1, [&](int f) { return fi.wall[3 + f] ? nullptr : fw + (fi.enb[3 + f] * 6 + f) * FWB; });
+    __syncthreads();
+
+    // wall faces xi_d = 0 (the lower end of a direction with walls): the own side only
+    for (int d = 0; d < 3; ++d) {
+        if (!fi.wall[d]) continue;   // uniform over the workgroup
+        face_traces_sweep<N, Q, Real, 1, FS1>(a, lt, 0, d, fi, sU, sW);
+        const bool act1 = tid < Q2;
+        if (act1) face_point<N, Q, Real, GEN>(a, lt, ph, conv, visc, 0, d, fi, sTau, sFn, sJr, detJ, sW, tid, res, res1);
+        __syncthreads();
+        Real* out1 = sW + FS1::OUT_OFF;
+        if (act1) {
+#pragma unroll
+            for (int m = 0; m < 20; ++m) out1[m * Q2 + tid] = res[m];
+        }
+        __syncthreads();
+        face_lift<N, Q, Real, 1>(lt, out1, sW + FS1::T1_OFF, [&](int) { return fw + (e * 6 + d) * FWB; });
+        __syncthreads();
     }
 }
 
@@ -1167,16 +1379,34 @@ inline void fill_tables(const Tables1D& t, KTab<N, Q, Real>& kt, MTab<N, Real>& 
     }
 }
 
+// One evaluation: with the face terms in their own kernel (SPLIT) the face kernel runs
+// first and the operator kernel gathers its output from a.fw (both on stream st).
 template <int N, int Q, typename Real, bool GEN>
 inline int launch_op_t(const OpArgs& a, const Tables1D& t, hipStream_t st) {
     KTab<N, Q, Real> kt;
     MTab<N, Real> mt;
     fill_tables<N, Q, Real>(t, kt, mt);
     constexpr int B = OpBlock<N, Q, Real>::threads;
-    static_assert((OpSizes<N, Q, B, (int)sizeof(Real), OpBlock<N, Q, Real>::fused>::WORK + 10 * N * N * N) *
+    constexpr bool SPLIT = OpBlock<N, Q, Real>::split;
+    static_assert((OpSizes<N, Q, B, (int)sizeof(Real), OpBlock<N, Q, Real>::fused, SPLIT>::WORK + 10 * N * N * N) *
                           sizeof(Real) <= 160 * 1024, "LDS budget");
+    if constexpr (SPLIT) {
+        if ((a.terms & 3u) != 0) {
+            if (!a.fw) return -1;
+            hipLaunchKernelGGL((dg_face_kernel<N, Q, Real, GEN>), dim3((unsigned)a.ncell),
+                               dim3(FaceBlock<N, Q, Real>::threads), 0, st, a, kt);
+            if (hipGetLastError() != hipSuccess) return -1;
+        }
+    }
     hipLaunchKernelGGL((dg_operator_kernel<N, Q, Real, GEN>), dim3((unsigned)a.ncell), dim3(B), 0, st, a, kt, mt);
     return hipGetLastError() == hipSuccess ? 0 : -1;
+}
+
+// Bytes of the face buffer a context needs for (N, n_q, precision): six lifted blocks
+// [2][5][N^2] per cell when the face terms have a kernel of their own, else none.
+template <int N, int Q, typename Real>
+constexpr int64_t face_buffer_bytes_per_cell() {
+    return OpBlock<N, Q, Real>::split ? (int64_t)6 * 2 * 5 * N * N * (int64_t)sizeof(Real) : 0;
 }
 
 template <int N, typename Real, bool GEN>

@@ -71,6 +71,9 @@ int main(int argc, char** argv) {
     const int64_t ndof = 5 * hs.ncell * hs.n3;
     const int64_t nout = fuse == 4 ? hs.ncell * prm.n_q * kStats : ndof;
     std::vector<double> U(ndof), out(nout, -12345.0), Rb;
+    // face buffer of the split evaluation: six lifted blocks [2][5][N^2] per cell (sized
+    // for float64, enough for float32); filled with a value that would show if read unwritten
+    std::vector<double> fw(hs.ncell * 6 * 10 * (prm.degree + 1) * (prm.degree + 1), 1e300);
     if ((int64_t)std::fread(U.data(), 8, ndof, f) != ndof) return 6;
     if (fuse == 2) {
         Rb.resize(ndof);
@@ -98,6 +101,7 @@ int main(int argc, char** argv) {
     a.wall_T = prm.wall_T;
     a.terms = terms;
     a.fuse_minv = fuse == 1 ? 1 : 0;
+    a.fw = fw.data();
     const int k = prm.degree, q = prm.n_q, fp32 = prm.precision, gen = hs.gen ? 1 : 0;
     rc = -4;
 #define EMU_CASE(K, Q_) \

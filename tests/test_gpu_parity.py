@@ -111,11 +111,14 @@ def test_operator_parity_range(case):
     _floor_L_and_R(oop, U, L_gpu, R_gpu, "n=%s k=%d nq=%d %s" % (n, k, nq, kind), sub_max=4 if k >= 6 else None)
 
 
-def test_channel_walls_force_k4():
-    announce("channel 2x4x2 k=4 nq=7 walls+force")
+@pytest.mark.parametrize("k,nq", [(4, 7), (3, 5), (4, 5), (2, 3)])
+def test_channel_walls_force(k, nq):
+    # the workload's k=4, n_q=7, and kernels with fused face traces (k <= 3) and
+    # one-wave workgroups (n_q <= 4): walls at both ends of x2 and the body force
+    announce("channel 2x4x2 k=%d nq=%d walls+force" % (k, nq))
     fl = tgv_fluid(mu=1.0 / 180.0)
     T0 = (18.3 / 0.1) ** 2 / (1.4 * 287.0)
-    oop, gop = make_pair((2, 4, 2), 4, 7, lo=(0, -1, 0), hi=(2 * math.pi, 1, math.pi), periodic=(1, 0, 1),
+    oop, gop = make_pair((2, 4, 2), k, nq, lo=(0, -1, 0), hi=(2 * math.pi, 1, math.pi), periodic=(1, 0, 1),
                          kind="channel", fluid=fl, force=(1.0, 0.0, 0.0), wall_T=T0)
     U = channel_input(oop)
     cells = list(range(oop.mesh.n_cells))

@@ -58,17 +58,20 @@ def test_emulated_residual_per_term(n, k, nq, kind, amp, basis):
     floor.check(L, oop.apply(U), L_ext, "emulated L")
 
 
-def test_emulated_channel_walls_and_force():
+# walls and body force for kernels with unfused (k=4, n_q=7) and fused (k=3, n_q=6) face
+# traces, and k=4, n_q=5 (both face terms once per face in the face kernel)
+@pytest.mark.parametrize("k,nq", [(4, 7), (3, 6), (4, 5)])
+def test_emulated_channel_walls_and_force(k, nq):
     fl = tgv_fluid(mu=1.0 / 180.0)
     T0 = (18.3 / 0.1) ** 2 / (1.4 * 287.0)
     lo, hi = (0, -1, 0), (2 * math.pi, 1, math.pi)
-    om = omesh.BoxMesh((2, 4, 1), lo, hi, 4, periodic=(True, False, True), kind=omesh.CHANNEL)
-    oop = ooperator.DGOperator(om, fl, 7, body_force=(1.0, 0.0, 0.0), wall_T=T0)
+    om = omesh.BoxMesh((2, 4, 1), lo, hi, k, periodic=(True, False, True), kind=omesh.CHANNEL)
+    oop = ooperator.DGOperator(om, fl, nq, body_force=(1.0, 0.0, 0.0), wall_T=T0)
     U = channel_input(oop)
     ext = floor.extended_for(oop)
     cells = list(range(oop.mesh.n_cells))
     for mask, t in ((1, "c"), (2, "v"), (4, "f"), (7, "cvf")):
-        R = ed.run(U.numpy(), 4, 7, (2, 4, 1), lo, hi, periodic=(1, 0, 1), kind=1, mu=fl.mu, lam=fl.lam,
+        R = ed.run(U.numpy(), k, nq, (2, 4, 1), lo, hi, periodic=(1, 0, 1), kind=1, mu=fl.mu, lam=fl.lam,
                    force=(1.0, 0, 0), wall_T=T0, terms=mask)
         Ro = oop.residual(U, terms=t)
         floor.check(R, Ro, ext.residual(U.numpy(), cells, t), "emulated channel R_" + t,
