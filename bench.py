@@ -34,16 +34,16 @@ PEAK_HBM = 8.0e12               # MI355X HBM3E, B/s
 # ~700 per face point; and the compulsory traffic, read U + write L.
 FLOP_PER_DOF = {(3, 6): 1197.0, (3, 5): 769.0, (3, 4): 474.0, (4, 7): 1049.0, (5, 8): 976.0, (7, 11): 1178.0}
 BYTES_PER_DOF = 16.0
-# HBM bytes per launch of the dominant kernel from two rocprofv3 --pmc runs
-# (FETCH_SIZE, WRITE_SIZE), scaled by what the counters read for a plain copy of
-# known size; valid only for the kernel source they were taken on.
+# HBM bytes of one evaluation of L (its face-kernel and cell-kernel launches) from two
+# rocprofv3 --pmc runs (FETCH_SIZE, WRITE_SIZE), scaled by what the counters read for a
+# plain copy of known size; valid only for the kernel source they were taken on.
 # Courant numbers of the time step (eq. TimeStepRestrictions_Compressible, e = 1.5):
 # about 2/3 of the largest value for which 400 steps of the 5-stage scheme stay
 # finite on these Taylor-Green meshes (measured: 0.40-0.45 at k=3 and k=5,
 # 0.35-0.40 at k=7).
 CR = 0.3
 CR_STUDY = 0.25
-MEASURED_TRAFFIC = {"fingerprint": "7c699f972971fad4", "workload": (32, 3, 6), "bytes": 356200533.9}
+MEASURED_TRAFFIC = {"fingerprint": "59f5ca1614a8f36c", "workload": (32, 3, 6), "bytes": 862676276.6}
 
 
 def kernel_fingerprint():
