@@ -37,11 +37,16 @@ BYTES_PER_DOF = 16.0
 # HBM bytes of one evaluation of L (its face-kernel and cell-kernel launches) from two
 # rocprofv3 --pmc runs (FETCH_SIZE, WRITE_SIZE), scaled by what the counters read for a
 # plain copy of known size; valid only for the kernel source they were taken on.
-# Courant numbers of the time step (eq. TimeStepRestrictions_Compressible, e = 1.5):
-# about 2/3 of the largest value for which 400 steps of the 5-stage scheme stay
-# finite on these Taylor-Green meshes (measured: 0.40-0.45 at k=3 and k=5,
-# 0.35-0.40 at k=7).
-CR = 0.3
+# Critical Courant and diffusion numbers of the five-stage scheme (eq.
+# TimeStepRestrictions_Compressible with e = 1.5, f = 3), measured on MI355X with
+# `bench.py --critical-cfl` the way Sec. 5.2.2 determines them (largest stable value, Taylor-
+# Green at effective resolution 60^3 / 64^3, Re = 1600 to t_f = 20 for Cr, Re = 1 to t_f = 1
+# for D; resolution 0.02 and 0.002): k -> (Cr stable, D stable).
+CRITICAL = {2: (0.36, 0.018), 3: (0.40, 0.020), 5: (0.42, 0.020), 7: (0.40, 0.018)}
+# The runs use the paper's ratio of the Courant number to the critical one (Cr = 0.5
+# against 0.74 at k = 3 for its scheme, 0.68): 0.68 x 0.40 = 0.27 at k = 3; the precision
+# study at k = 5 and 7 uses 0.25 (0.6 of the critical 0.42 / 0.40).
+CR = 0.27
 CR_STUDY = 0.25
 MEASURED_TRAFFIC = {"fingerprint": "59f5ca1614a8f36c", "workload": (32, 3, 6), "bytes": 862676276.6}
 
@@ -309,6 +314,69 @@ def precision_study(steps):
     return out
 
 
+def _stays_stable(op, U0, dt, t_final, check_every=50):
+    """True if the run from U0 with the fixed step dt reaches t_final with finite diagnostics
+    and a kinetic energy that never exceeds 1.5 times the initial one (blow-up criterion)."""
+    import torch
+    U = U0.clone()
+    work = torch.empty(2 * op.n_dof, dtype=torch.float64, device="cuda")
+    ek0 = op.diagnostics(U)["e_k"]
+    n = int(math.ceil(t_final / dt))
+    for s in range(n):
+        op.rk_step(U, work, s * dt, dt)
+        if (s + 1) % check_every == 0 or s + 1 == n:
+            d = op.diagnostics(U)
+            if d.get("nonfinite") or not d["e_k"] <= 1.5 * ek0:
+                return False
+    return True
+
+
+def critical_numbers(res_cr=0.02, res_d=0.002):
+    """Critical Courant and diffusion numbers of the time-step formula (eq.
+    TimeStepRestrictions_Compressible with e = 1.5, f = 3) for the Runge-Kutta scheme in use,
+    determined the way Sec. 5.2.2 (Table 2) does: Taylor-Green vortex at an effective
+    resolution of 60^3 / 64^3 (k = 2, 3, 5, 7 on 20^3, 16^3, 10^3, 8^3 cells, n_q by the 3/2
+    rule); Cr from the convection-dominated Re = 1600 case run to t_f = 20 with D not
+    binding, D from the viscous Re = 1 case run to t_f = 1 with Cr not binding.  Each
+    value is bracketed by bisection to res_cr / res_d (stable, unstable)."""
+    from paper_1806_03095_amd import taylor_green
+    rows = []
+    for k, ne in ((2, 20), (3, 16), (5, 10), (7, 8)):
+        nq = (3 * k + 2) // 2
+        row = {"k": k, "cells": ne ** 3, "n_q": nq}
+        for which, Re, t_f, lo, hi, res in (("Cr", 1600.0, 20.0, 0.1, 1.3, res_cr), ("D", 1.0, 1.0, 0.005, 0.1, res_d)):
+            op = taylor_green(k, ne, n_q=nq, Re=Re)
+            U0 = op.project_ic("taylor_green", [1.0, 1.0, 0.1, 1.0])
+            stages = len(op.rk_scheme()[0])
+
+            def dt_of(x):
+                if which == "Cr":
+                    return op.compute_dt(x, 1e3, 1.5, 3.0, 1.0, 0.1)
+                return op.compute_dt(1e3, x, 1.5, 3.0, 1.0, 0.1)
+
+            t0 = time.perf_counter()
+            runs = 0
+            while hi - lo > res * 1.0001:
+                mid = round((lo + hi) / 2 / res) * res
+                if mid <= lo or mid >= hi:
+                    mid = lo + res
+                runs += 1
+                if _stays_stable(op, U0, dt_of(mid), t_f):
+                    lo = mid
+                else:
+                    hi = mid
+            row[which + "_stable"] = round(lo, 6)
+            row[which + "_unstable"] = round(hi, 6)
+            row[which + "_stable_per_stage"] = round(lo / stages, 6)
+            row["dt_" + which + "_stable"] = dt_of(lo)
+            log("k=%d %d^3 n_q=%d: %s stable %.3f, unstable %.3f (%d runs, %.0f s)" % (k, ne, nq, which, lo, hi, runs,
+                                                                                   time.perf_counter() - t0))
+            op.close()
+        row["stages"] = stages
+        rows.append(row)
+    return rows
+
+
 def _cpu_model():
     try:
         for line in open("/proc/cpuinfo"):
@@ -410,6 +478,8 @@ def main():
                     help="skip the operation breakdown, copy bandwidth and channel figures")
     ap.add_argument("--sweep", action="store_true",
                     help="study mode: operator throughput over every compiled (k, n_q); one JSON line")
+    ap.add_argument("--critical-cfl", action="store_true",
+                    help="study mode: critical Courant and diffusion numbers per degree (Sec. 5.2.2 method); one JSON line")
     ap.add_argument("--precision-study", type=int, default=0, metavar="STEPS",
                     help="study mode: float32 vs float64 over STEPS RK steps (16^3 k=7, 24^3 k=5); one JSON line")
     args = ap.parse_args()
@@ -433,6 +503,9 @@ def main():
 
     if args.sweep:
         print(json.dumps({"degree_sweep": degree_sweep()}), flush=True)
+        return
+    if args.critical_cfl:
+        print(json.dumps({"critical_numbers": critical_numbers()}), flush=True)
         return
     if args.precision_study:
         print(json.dumps({"precision_study": precision_study(args.precision_study)}), flush=True)

@@ -128,20 +128,33 @@ int dgns_apply_inverse_mass(dgns_ctx* ctx, const double* R, double* L);
  * t is accepted for time-dependent right-hand sides (none at present). */
 int dgns_apply_operator(dgns_ctx* ctx, const double* U, double* L, double t);
 
-/* One step of the five-stage, fourth-order 2N-storage Runge-Kutta scheme
- * (Carpenter & Kennedy 1994) in Williamson form, one L per stage:
- *   dU <- A_i dU + dt L(U, t + c_i dt);  U <- U + B_i dU.
+/* The explicit low-storage Runge-Kutta scheme of dgns_rk_step, dgns_rk_stage_update and
+ * dgns_rk_step_vjp (Sec. 2.4: an s-stage scheme, one L per stage), in the 2N-storage
+ * Williamson form  dU <- A_i dU + dt L(U, t + c_i dt);  U <- U + B_i dU,  i = 0..s-1.
+ * Default (and after dgns_set_rk_scheme(ctx, 0, NULL, NULL, NULL)): the five-stage,
+ * fourth-order scheme of Carpenter & Kennedy (1994).  A, B, c: HOST arrays of `stages`
+ * doubles (1 <= stages <= 16), copied; A[0] must be 0; c may be NULL (then computed from
+ * A and B).  The paper's own scheme (seven stages, third order) can be set this way
+ * when its published coefficients are at hand.  DGNS_EINVAL for a bad argument. */
+int dgns_set_rk_scheme(dgns_ctx* ctx, int stages, const double* A, const double* B, const double* c);
+
+/* The scheme in use: *stages, and A, B, c into host arrays of at least *stages doubles
+ * (each may be NULL). */
+int dgns_get_rk_scheme(const dgns_ctx* ctx, int* stages, double* A, double* B, double* c);
+
+/* One step of the context's 2N Runge-Kutta scheme (dgns_set_rk_scheme), one L per stage.
  * U is updated in place.  work: device scratch of at least 2*n_dof doubles owned
  * by the caller (contents on return are unspecified): dU and a second copy of the
- * state, since stages 1-4 fuse the update into the operator kernel and write the
- * new state into the other buffer (U -> work[n_dof:] -> U -> work[n_dof:] -> U). */
+ * state, since stages 1..s-1 fuse the update into the operator kernels and write the
+ * new state into the other buffer (U -> work[n_dof:] -> U -> ...; after an odd number
+ * of fused stages the result is copied back into U). */
 int dgns_rk_step(dgns_ctx* ctx, double* U, double* work, double t, double dt);
 
 /* The vector update of one stage of that scheme on its own (Sec. 2.4; the paper's
  * "RK update" operation): dU <- A_i dU + dt L, then U <- U + B_i dU, for stage
- * i = 0..4 (the first stage does not read dU).  U, dU, L: device, n_dof doubles
+ * i = 0..s-1 (the first stage does not read dU).  U, dU, L: device, n_dof doubles
  * each, pairwise non-overlapping; U and dU are updated in place.  Returns
- * DGNS_EINVAL for a stage outside 0..4, a non-finite dt or overlapping vectors. */
+ * DGNS_EINVAL for a stage outside 0..s-1, a non-finite dt or overlapping vectors. */
 int dgns_rk_stage_update(dgns_ctx* ctx, double* U, double* dU, const double* L, int stage, double dt);
 
 /* The time step of eq. (TimeStepRestrictions_Compressible):
@@ -196,8 +209,9 @@ int dgns_apply_residual_vjp(dgns_ctx* ctx, const double* U, const double* Rbar, 
 int dgns_apply_operator_vjp(dgns_ctx* ctx, const double* U, const double* Lbar, double* Ubar);
 
 /* Reverse of one dgns_rk_step from U_n: Ubar_n = (dU_{n+1}/dU_n)^T Ubar_np1.
- * The five stage states are recomputed from U_n.  work: device scratch of at
- * least 9*n_dof doubles owned by the caller.  Ubar_n may equal Ubar_np1 (in
+ * The stage states are recomputed from U_n.  work: device scratch of at least
+ * (s + 4)*n_dof doubles owned by the caller, s the scheme's number of stages (9*n_dof
+ * for the default scheme).  Ubar_n may equal Ubar_np1 (in
  * place) but must not otherwise overlap any argument. */
 int dgns_rk_step_vjp(dgns_ctx* ctx, const double* U_n, double t, double dt, const double* Ubar_np1,
                      double* Ubar_n, double* work);
@@ -214,6 +228,30 @@ int dgns_rk_step_vjp(dgns_ctx* ctx, const double* U_n, double t, double dt, cons
  * DGNS_ENOMEM if the first call cannot allocate its 9*n_q*(n_cells + n[1]) doubles of
  * device buffer (kept for later calls); DGNS_ENONFINITE for a non-finite average. */
 int dgns_channel_statistics(dgns_ctx* ctx, const double* U, double* out);
+
+/* Mean wall shear stress of a channel (Sec. 5.3: u_tau = sqrt(tau_w / rho)) over both
+ * walls in x_2: at the n_q^2 points of every wall face, mu du_1/dn with n the wall normal
+ * into the fluid, from the wall cell's polynomial (du_1/dx_2 = (d(rho u_1)/dx_2 -
+ * u_1 drho/dx_2)/rho), averaged with the face weights dA w.  out3: HOST array
+ * {tau_w, rho_w (the wall density, same average), wall area}.  Synchronous.  Needs walls
+ * in direction 1 (periodic[1] = 0) on an affine or channel mesh, else DGNS_EUNSUPPORTED;
+ * DGNS_ENOMEM if the first call cannot allocate its 6 n[0] n[2] doubles (kept). */
+int dgns_channel_wall_shear(dgns_ctx* ctx, const double* U, double* out3);
+
+/* Time-averaged channel statistics (Sec. 5.3: averages over x, z and time, sampled by the
+ * caller, e.g. every 10th step).  _reset clears the running sums of the context;
+ * _sample(U) adds the plane averages of dgns_channel_statistics and the wall shear of
+ * dgns_channel_wall_shear of U; _result writes, from the time averages <.> over the
+ * samples, u_tau = sqrt(<tau_w> / <rho_w>) and per wall-normal Gauss point (n[1] * n_q rows,
+ * ordered as in dgns_channel_statistics) the row
+ *   [y, y+ = (y - lo[1]) u_tau / nu, u+ = <u> / u_tau, rms(u)+, rms(v)+, rms(w)+,
+ *    <u'v'>+ = (<uv> - <u><v>) / u_tau^2, <rho>],   rms(u) = sqrt(<uu> - <u>^2),
+ * into profiles (HOST, n[1] * n_q * 8 doubles), and {u_tau, <tau_w>, <rho_w>, samples}
+ * into scalars (HOST, 4 doubles).  _result: DGNS_EINVAL without samples, DGNS_ENONFINITE if
+ * the mean wall shear is not positive. */
+int dgns_channel_stats_reset(dgns_ctx* ctx);
+int dgns_channel_stats_sample(dgns_ctx* ctx, const double* U);
+int dgns_channel_stats_result(dgns_ctx* ctx, double* profiles, double* scalars);
 
 /* K = int |u|^2/2 over the domain (n_q rule, u = (rho u)/rho), returned to the
  * host (synchronises the stream); DGNS_ENONFINITE if not finite (ke untouched). */

@@ -79,3 +79,42 @@ def channel_statistics(op, U):
             ws = w[:, sel]
             out[j * q + p] = [float((f[:, sel] * ws).sum() / ws.sum()) for f in fields]
     return out
+
+
+def channel_wall_shear(op, U):
+    """Mean wall shear stress over both walls in x2 (Sec. 5.3, u_tau = sqrt(tau_w / rho)):
+    at the face points of every wall face, mu du_1/dn with n the wall normal into the fluid
+    (+x2 at the lower wall, -x2 at the upper), averaged with the face weights dA.
+    Returns (tau_w, rho_w, wall area), rho_w the same average of the density."""
+    m, fl = op.mesh, op.fl
+    tot = np.zeros(3)
+    for s, sign in ((0, 1.0), (1, -1.0)):
+        cells = np.nonzero(m.nb[:, 1, s] < 0)[0]
+        pts, wf, P, dP = op.face[1, s]
+        _, Jinv, detJ = op._geometry(cells, pts)
+        _, dA = op._face_measure(Jinv, detJ, wf, 1, s)
+        Uq, Gx = op._values(U[:, cells, :], P, dP, Jinv)
+        gu = ph.velocity_gradient(Uq, Gx)                    # [e, p, a, j] = du_a / dx_j
+        tau = fl.mu * gu[..., 0, 1] * sign
+        tot += [float((tau * dA).sum()), float((Uq[..., 0] * dA).sum()), float(dA.sum())]
+    return tot[0] / tot[2], tot[1] / tot[2], tot[2]
+
+
+def channel_plus_statistics(profiles, walls, nu, y_lo):
+    """Time averages over the samples (Sec. 5.3) in wall units.  profiles: list of the
+    (rows, 9) plane averages [y, rho, u, v, w, uu, vv, ww, uv] of channel_statistics, walls:
+    list of (tau_w, rho_w, area) of channel_wall_shear, one per sample.  u_tau =
+    sqrt(<tau_w> / <rho_w>); rows [y, y+ = (y - y_lo) u_tau / nu, <u>/u_tau, rms u_i / u_tau
+    (rms u = sqrt(<uu> - <u>^2)), (<uv> - <u><v>) / u_tau^2, <rho>].  Returns (rows, u_tau)."""
+    A = np.mean(np.stack(profiles), axis=0)
+    tau = np.mean([w[0] for w in walls])
+    rho_w = np.mean([w[1] for w in walls])
+    u_tau = np.sqrt(tau / rho_w)
+    y, rho, u, v, w, uu, vv, ww, uv = A.T
+    out = np.stack([y, (y - y_lo) * u_tau / nu, u / u_tau,
+                    np.sqrt(np.maximum(uu - u * u, 0.0)) / u_tau,
+                    np.sqrt(np.maximum(vv - v * v, 0.0)) / u_tau,
+                    np.sqrt(np.maximum(ww - w * w, 0.0)) / u_tau,
+                    (uv - u * v) / u_tau ** 2, rho], axis=1)
+    return out, u_tau
+

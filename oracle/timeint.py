@@ -29,6 +29,12 @@ CK54_C = [Fr(0), Fr(1432997174477, 9575080441755), Fr(2526269341429, 68203639628
           Fr(2006345519317, 3224310063776), Fr(2802321613138, 2924317926251)]
 
 
+# Williamson (1980), three stages, third order, 2N storage: a second published scheme,
+# used to exercise a scheme other than the default (the library takes its table at run time).
+WS33_A = [Fr(0), Fr(-5, 9), Fr(-153, 128)]
+WS33_B = [Fr(1, 3), Fr(15, 16), Fr(8, 15)]
+
+
 def butcher_from_2n(A, B):
     """Butcher (a, b, c) of a 2N scheme with the exact arithmetic of its inputs.
 

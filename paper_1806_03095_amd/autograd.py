@@ -32,7 +32,7 @@ class RKRollout(torch.autograd.Function):
         op, dt = ctx.op, ctx.dt
         Ub = Ubar.detach().contiguous().clone()
         work = torch.empty(2 * op.n_dof, dtype=torch.float64, device=Ub.device)
-        work9 = torch.empty(9 * op.n_dof, dtype=torch.float64, device=Ub.device)
+        work9 = torch.empty((len(op.rk_scheme()[0]) + 4) * op.n_dof, dtype=torch.float64, device=Ub.device)
         starts = sorted(ctx.ckpts)
         for i in reversed(range(len(starts))):
             s0 = starts[i]

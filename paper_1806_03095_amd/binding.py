@@ -46,7 +46,9 @@ EXPORTS = ["dgns_last_error", "dgns_create", "dgns_destroy", "dgns_sizes", "dgns
            "dgns_apply_residual", "dgns_apply_inverse_mass", "dgns_apply_operator", "dgns_rk_step",
            "dgns_rk_stage_update", "dgns_compute_dt", "dgns_channel_statistics", "dgns_diagnostics",
            "dgns_diagnostics_noalloc", "dgns_project_ic", "dgns_apply_residual_vjp",
-           "dgns_apply_operator_vjp", "dgns_rk_step_vjp", "dgns_kinetic_energy", "dgns_kinetic_energy_vjp"]
+           "dgns_apply_operator_vjp", "dgns_rk_step_vjp", "dgns_kinetic_energy", "dgns_kinetic_energy_vjp",
+           "dgns_set_rk_scheme", "dgns_get_rk_scheme", "dgns_channel_wall_shear", "dgns_channel_stats_reset",
+           "dgns_channel_stats_sample", "dgns_channel_stats_result"]
 
 _lib = None
 
@@ -81,6 +83,12 @@ def load_library(path=LIB_PATH):
     lib.dgns_rk_step_vjp.argtypes = [vp, vp, ctypes.c_double, ctypes.c_double, vp, vp, vp]
     lib.dgns_kinetic_energy.argtypes = [vp, vp, dp]
     lib.dgns_kinetic_energy_vjp.argtypes = [vp, vp, vp]
+    lib.dgns_set_rk_scheme.argtypes = [vp, ctypes.c_int, dp, dp, dp]
+    lib.dgns_channel_wall_shear.argtypes = [vp, vp, dp]
+    lib.dgns_channel_stats_reset.argtypes = [vp]
+    lib.dgns_channel_stats_sample.argtypes = [vp, vp]
+    lib.dgns_channel_stats_result.argtypes = [vp, dp, dp]
+    lib.dgns_get_rk_scheme.argtypes = [vp, ctypes.POINTER(ctypes.c_int), dp, dp, dp]
     for name in EXPORTS:
         if name != "dgns_last_error":
             getattr(lib, name).restype = ctypes.c_int
@@ -187,6 +195,24 @@ class Operator:
         _check(self.lib.dgns_rk_step(self.h, _ptr(U), _ptr(work), t, dt))
         return U
 
+    def set_rk_scheme(self, A=None, B=None, c=None):
+        """Sets the 2N Runge-Kutta scheme (Williamson form; A[0] = 0) used by rk_step and its
+        adjoint; no arguments restore the default five-stage fourth-order scheme."""
+        if A is None and B is None:
+            _check(self.lib.dgns_set_rk_scheme(self.h, 0, None, None, None))
+            return
+        s = len(A)
+        arr = lambda v: (ctypes.c_double * s)(*[float(x) for x in v])
+        _check(self.lib.dgns_set_rk_scheme(self.h, s, arr(A), arr(B), None if c is None else arr(c)))
+
+    def rk_scheme(self):
+        """(A, B, c) of the scheme in use."""
+        s = ctypes.c_int()
+        A, B, c = ((ctypes.c_double * 16)() for _ in range(3))
+        _check(self.lib.dgns_get_rk_scheme(self.h, ctypes.byref(s), A, B, c))
+        n = s.value
+        return list(A)[:n], list(B)[:n], list(c)[:n]
+
     def channel_statistics(self, U):
         """Plane averages at the wall-normal Gauss points: a (n[1] * n_q, 9) numpy array with
         columns y, rho, u, v, w, uu, vv, ww, uv (rows by cell row, then point)."""
@@ -196,6 +222,43 @@ class Operator:
         out = np.empty((self.n[1] * self.n_q, 9), dtype=np.float64)
         _check(self.lib.dgns_channel_statistics(self.h, _ptr(U), out.ctypes.data_as(ctypes.POINTER(ctypes.c_double))))
         return out
+
+    def channel_wall_shear(self, U):
+        """(tau_w, rho_w, wall area): the mean wall shear stress over both walls in x2."""
+        self._vec(U, "U")
+        self._bind()
+        out = (ctypes.c_double * 3)()
+        _check(self.lib.dgns_channel_wall_shear(self.h, _ptr(U), out))
+        return tuple(out)
+
+    def channel_stats_reset(self):
+        _check(self.lib.dgns_channel_stats_reset(self.h))
+
+    def channel_stats_sample(self, U):
+        self._vec(U, "U")
+        self._bind()
+        _check(self.lib.dgns_channel_stats_sample(self.h, _ptr(U)))
+
+    def channel_stats_result(self):
+        """Time-averaged profiles: a (n[1] * n_q, 8) numpy array with columns y, y+, u+, rms u+,
+        rms v+, rms w+, <u'v'>+, <rho>, and dict(u_tau, tau_w, rho_w, samples)."""
+        import numpy as np
+        prof = np.empty((self.n[1] * self.n_q, 8), dtype=np.float64)
+        sc = (ctypes.c_double * 4)()
+        _check(self.lib.dgns_channel_stats_result(self.h, prof.ctypes.data_as(ctypes.POINTER(ctypes.c_double)), sc))
+        return prof, dict(u_tau=sc[0], tau_w=sc[1], rho_w=sc[2], samples=int(sc[3]))
+
+    def run_channel_statistics(self, U, work, dt, steps, every=10, t0=0.0):
+        """Advances U by `steps` RK steps and samples the channel statistics every `every`-th
+        step (Sec. 5.3 samples every 10th); returns channel_stats_result()."""
+        self.channel_stats_reset()
+        t = t0
+        for s in range(1, steps + 1):
+            self.rk_step(U, work, t, dt)
+            t += dt
+            if s % every == 0:
+                self.channel_stats_sample(U)
+        return self.channel_stats_result()
 
     def rk_graph(self, U, work, dt, steps=1):
         """Captures `steps` rk_step calls on U (in place, work as in rk_step) into a HIP
@@ -280,10 +343,11 @@ class Operator:
         self._vec(U_n, "U_n")
         self._vec(Ubar_np1, "Ubar_np1")
         out = self.empty() if out is None else self._vec(out, "out")
+        nw = (len(self.rk_scheme()[0]) + 4) * self.n_dof
         if work is None:
-            work = torch.empty(9 * self.n_dof, dtype=torch.float64, device="cuda")
-        elif not (work.is_cuda and work.dtype == torch.float64 and work.is_contiguous() and work.numel() >= 9 * self.n_dof):
-            raise ValueError("work must be a contiguous float64 CUDA tensor of >= 9 n_dof entries")
+            work = torch.empty(nw, dtype=torch.float64, device="cuda")
+        elif not (work.is_cuda and work.dtype == torch.float64 and work.is_contiguous() and work.numel() >= nw):
+            raise ValueError("work must be a contiguous float64 CUDA tensor of >= (stages + 4) n_dof entries")
         self._bind()
         _check(self.lib.dgns_rk_step_vjp(self.h, _ptr(U_n), t, dt, _ptr(Ubar_np1), _ptr(out), _ptr(work)))
         return out

@@ -71,6 +71,16 @@ int launch_chan_stats_k6(const OpArgs& a, const Tables1D& t, double* partial, bo
 int launch_chan_stats_k7(const OpArgs& a, const Tables1D& t, double* partial, bool gen, hipStream_t st);
 int launch_chan_stats_total(const double* partial, const int n[3], int q, double* total, hipStream_t st);
 
+// Wall shear of the channel: per wall cell (lower row, then upper row) the dA w weighted
+// sums of mu du_1/dn, rho and 1 over its wall face (3 per wall cell).
+int launch_wall_shear_k1(const OpArgs& a, const Tables1D& t, double* partial, bool gen, hipStream_t st);
+int launch_wall_shear_k2(const OpArgs& a, const Tables1D& t, double* partial, bool gen, hipStream_t st);
+int launch_wall_shear_k3(const OpArgs& a, const Tables1D& t, double* partial, bool gen, hipStream_t st);
+int launch_wall_shear_k4(const OpArgs& a, const Tables1D& t, double* partial, bool gen, hipStream_t st);
+int launch_wall_shear_k5(const OpArgs& a, const Tables1D& t, double* partial, bool gen, hipStream_t st);
+int launch_wall_shear_k6(const OpArgs& a, const Tables1D& t, double* partial, bool gen, hipStream_t st);
+int launch_wall_shear_k7(const OpArgs& a, const Tables1D& t, double* partial, bool gen, hipStream_t st);
+
 // L2 projection right-hand side of an analytic initial state, U_rhs = (phi_i, U0).
 int launch_ic_rhs(const OpArgs& a, const Tables1D& t, const Tables1D* t_dev, const double* geo_nodes, int ic,
                   const double* icp, double* out, bool gen, hipStream_t st);

@@ -49,6 +49,9 @@ int fail(int code, const char* fmt, ...) {
 }  // namespace
 
 // ---------------------------------------------------------------- context
+constexpr int kMaxRkStages = 16;
+constexpr int kWallSumsHost = 3;   // per wall cell: dA w (mu du_1/dn, rho, 1)
+
 struct dgns_ctx {
     dgns_params prm;
     dgns_box_mesh msh;
@@ -70,8 +73,16 @@ struct dgns_ctx {
     Tables1D* d_tab = nullptr;
     double* d_scratch = nullptr;   // n_dof doubles, allocated on the first operator VJP
     double* d_stats = nullptr;     // channel statistics partial sums and totals, on first use
+    double* d_wall = nullptr;      // wall-shear partial sums, on first use
+    // running sums of the time-averaged channel statistics (dgns_channel_stats_*)
+    int64_t stats_samples = 0;
+    std::vector<double> stats_sum;  // n[1] * n_q rows of [y, rho, u, v, w, uu, vv, ww, uv]
+    double tau_sum = 0, rho_w_sum = 0;
     double* noalloc = nullptr;     // this device's copy of the static workspace below
     double* d_fw = nullptr;        // face buffer of the split evaluation (six lifted blocks per cell)
+    // 2N-storage Runge-Kutta scheme of dgns_rk_step (Williamson form), default below
+    int rk_s = 0;
+    double rk_A[kMaxRkStages], rk_B[kMaxRkStages], rk_c[kMaxRkStages];
 };
 
 // Workspace of dgns_diagnostics_noalloc: the per-cell partial sums and their totals
@@ -123,6 +134,7 @@ void free_ctx(dgns_ctx* c) {
     hipFree(c->d_tab);
     hipFree(c->d_scratch);
     hipFree(c->d_stats);
+    hipFree(c->d_wall);
     hipFree(c->d_fw);
 }
 
@@ -247,6 +259,8 @@ bool overlap(const double* a, int64_t na, const double* b, int64_t nb) { return 
 
 }  // namespace
 
+static void rk_default(dgns_ctx* c);
+
 // ---------------------------------------------------------------- C ABI
 extern "C" {
 
@@ -275,6 +289,7 @@ int dgns_create(const dgns_params* prm, const dgns_box_mesh* msh, void* stream, 
     if (!ok) return fail(DGNS_EUNSUPPORTED, "no kernel for degree %d with n_q %d", prm->degree, prm->n_q);
 
     dgns_ctx* c = new dgns_ctx();
+    rk_default(c);
     c->prm = *prm;
     c->msh = *msh;
     c->stream = (hipStream_t)stream;
@@ -379,12 +394,74 @@ int dgns_apply_operator(dgns_ctx* c, const double* U, double* L, double t) {
     return dispatch_operator(c, make_args(c, U, L, DGNS_TERM_ALL, 1));
 }
 
-// Carpenter & Kennedy (1994), five stages, fourth order, 2N storage.
+// Carpenter & Kennedy (1994), five stages, fourth order, 2N storage: the default scheme.
 static const double kRkA[5] = {0.0, -567301805773.0 / 1357537059087.0, -2404267990393.0 / 2016746695238.0,
                                -3550918686646.0 / 2091501179385.0, -1275806237668.0 / 842570457699.0};
 static const double kRkB[5] = {1432997174477.0 / 9575080441755.0, 5161836677717.0 / 13612068292357.0,
                                1720146321549.0 / 2090206949498.0, 3134564353537.0 / 4481467310338.0,
                                2277821191437.0 / 14882151754819.0};
+
+// Stage times of a 2N scheme: stage i evaluates L at U_0 + sum_{l < i} B_l dU_l with
+// dU_l = sum_{j <= l} (prod_{m = j+1..l} A_m) dt k_j, so c_i = sum_{l < i} B_l sum_{j <= l} prod A.
+static void rk_stage_times(int s, const double* A, const double* B, double* cc) {
+    for (int i = 0; i < s; ++i) {
+        double ci = 0;
+        for (int l = 0; l < i; ++l) {
+            double w = 0;
+            for (int j = 0; j <= l; ++j) {
+                double p = 1;
+                for (int m = j + 1; m <= l; ++m) p *= A[m];
+                w += p;
+            }
+            ci += B[l] * w;
+        }
+        cc[i] = ci;
+    }
+}
+
+static void rk_default(dgns_ctx* c) {
+    c->rk_s = 5;
+    for (int i = 0; i < 5; ++i) {
+        c->rk_A[i] = kRkA[i];
+        c->rk_B[i] = kRkB[i];
+    }
+    rk_stage_times(5, c->rk_A, c->rk_B, c->rk_c);
+}
+
+int dgns_set_rk_scheme(dgns_ctx* c, int stages, const double* A, const double* B, const double* cc) {
+    if (!c) return fail(DGNS_EINVAL, "null context");
+    if (stages == 0 && !A && !B && !cc) {
+        rk_default(c);
+        return DGNS_OK;
+    }
+    if (!A || !B) return fail(DGNS_EINVAL, "null coefficient array");
+    if (stages < 1 || stages > kMaxRkStages) return fail(DGNS_EINVAL, "stages %d outside 1..%d", stages, kMaxRkStages);
+    if (A[0] != 0.0) return fail(DGNS_EINVAL, "A[0] must be 0 (the first stage does not read dU)");
+    for (int i = 0; i < stages; ++i)
+        if (!std::isfinite(A[i]) || !std::isfinite(B[i]) || (cc && !std::isfinite(cc[i])))
+            return fail(DGNS_EINVAL, "coefficient %d is not finite", i);
+    c->rk_s = stages;
+    for (int i = 0; i < stages; ++i) {
+        c->rk_A[i] = A[i];
+        c->rk_B[i] = B[i];
+    }
+    if (cc)
+        for (int i = 0; i < stages; ++i) c->rk_c[i] = cc[i];
+    else
+        rk_stage_times(stages, c->rk_A, c->rk_B, c->rk_c);
+    return DGNS_OK;
+}
+
+int dgns_get_rk_scheme(const dgns_ctx* c, int* stages, double* A, double* B, double* cc) {
+    if (!c || !stages) return fail(DGNS_EINVAL, "null argument");
+    *stages = c->rk_s;
+    for (int i = 0; i < c->rk_s; ++i) {
+        if (A) A[i] = c->rk_A[i];
+        if (B) B[i] = c->rk_B[i];
+        if (cc) cc[i] = c->rk_c[i];
+    }
+    return DGNS_OK;
+}
 
 int dgns_rk_step(dgns_ctx* c, double* U, double* work, double t, double dt) {
     (void)t;
@@ -394,17 +471,20 @@ int dgns_rk_step(dgns_ctx* c, double* U, double* work, double t, double dt) {
     if (!std::isfinite(dt)) return fail(DGNS_EINVAL, "dt is not finite");
     double* dU = work;
     double* U2 = work + c->ndof;
-    // Stages 1-4 fuse the update into the operator kernel, alternating the state
+    const int s = c->rk_s;
+    // Stages 1..s-1 fuse the update into the operator kernel, alternating the state
     // between U and U2 (a stage cannot overwrite the U its neighbours still read):
-    // U -> U2 -> U -> U2 -> U.  Stage 5 writes L into U2 and updates U in place.
+    // U -> U2 -> U -> ...  The last stage writes L into the other buffer and updates
+    // the state in place; after an odd number of fused stages the state ends in U2 and
+    // is copied back.
     const double* src = U;
     double* dst = U2;
-    for (int i = 0; i < 4; ++i) {
+    for (int i = 0; i < s - 1; ++i) {
         OpArgs a = make_args(c, src, nullptr, DGNS_TERM_ALL, 1);
         a.rk.dU = dU;
         a.rk.U_out = dst;
-        a.rk.A = kRkA[i];
-        a.rk.B = kRkB[i];
+        a.rk.A = c->rk_A[i];
+        a.rk.B = c->rk_B[i];
         a.rk.dt = dt;
         int rc = dispatch_operator(c, a);
         if (rc) return rc;
@@ -412,22 +492,24 @@ int dgns_rk_step(dgns_ctx* c, double* U, double* work, double t, double dt) {
         src = dst;
         dst = next;
     }
-    int rc = dispatch_operator(c, make_args(c, U, U2, DGNS_TERM_ALL, 1));
+    double* state = const_cast<double*>(src);
+    int rc = dispatch_operator(c, make_args(c, state, dst, DGNS_TERM_ALL, 1));
     if (rc) return rc;
-    if (launch_rk_update(U, dU, U2, c->ndof, kRkA[4], kRkB[4], dt, c->stream) != 0)
+    if (launch_rk_update(state, dU, dst, c->ndof, c->rk_A[s - 1], c->rk_B[s - 1], dt, c->stream) != 0)
         return fail(DGNS_EHIP, "rk update launch failed");
+    if (state != U) HIP_TRY(hipMemcpyAsync(U, state, sizeof(double) * c->ndof, hipMemcpyDeviceToDevice, c->stream));
     return DGNS_OK;
 }
 
 int dgns_rk_stage_update(dgns_ctx* c, double* U, double* dU, const double* L, int stage, double dt) {
     if (!c || !U || !dU || !L) return fail(DGNS_EINVAL, "null argument");
-    if (stage < 0 || stage > 4) return fail(DGNS_EINVAL, "stage %d outside 0..4", stage);
+    if (stage < 0 || stage >= c->rk_s) return fail(DGNS_EINVAL, "stage %d outside 0..%d", stage, c->rk_s - 1);
     if (!std::isfinite(dt)) return fail(DGNS_EINVAL, "dt is not finite");
     if (!aligned8(U) || !aligned8(dU) || !aligned8(L)) return fail(DGNS_EINVAL, "vectors must be 8-byte aligned");
     const int64_t n = c->ndof;
     if (overlap(U, n, dU, n) || overlap(U, n, L, n) || overlap(dU, n, L, n))
         return fail(DGNS_EINVAL, "U, dU and L must not overlap");
-    if (launch_rk_update(U, dU, L, n, kRkA[stage], kRkB[stage], dt, c->stream) != 0)
+    if (launch_rk_update(U, dU, L, n, c->rk_A[stage], c->rk_B[stage], dt, c->stream) != 0)
         return fail(DGNS_EHIP, "rk update launch failed");
     return DGNS_OK;
 }
@@ -495,9 +577,89 @@ int dgns_apply_residual_vjp(dgns_ctx* c, const double* U, const double* Rbar, do
     return dispatch_adjoint(c, make_args(c, U, Ubar, term_mask, 0), Rbar);
 }
 
+static int channel_profiles(dgns_ctx* c, const double* U, std::vector<double>& res);
+static int channel_wall_shear(dgns_ctx* c, const double* U, double out3[3]);
+
 int dgns_channel_statistics(dgns_ctx* c, const double* U, double* out) {
     if (!c || !U || !out) return fail(DGNS_EINVAL, "null argument");
     if (!aligned8(U)) return fail(DGNS_EINVAL, "U must be 8-byte aligned");
+    std::vector<double> res;
+    int rc = channel_profiles(c, U, res);
+    if (rc) return rc;
+    std::copy(res.begin(), res.end(), out);   // written only on success
+    return DGNS_OK;
+}
+
+int dgns_channel_wall_shear(dgns_ctx* c, const double* U, double* out3) {
+    if (!c || !U || !out3) return fail(DGNS_EINVAL, "null argument");
+    if (!aligned8(U)) return fail(DGNS_EINVAL, "U must be 8-byte aligned");
+    double r[3];
+    int rc = channel_wall_shear(c, U, r);
+    if (rc) return rc;
+    for (int m = 0; m < 3; ++m) out3[m] = r[m];
+    return DGNS_OK;
+}
+
+int dgns_channel_stats_reset(dgns_ctx* c) {
+    if (!c) return fail(DGNS_EINVAL, "null context");
+    c->stats_samples = 0;
+    c->stats_sum.clear();
+    c->tau_sum = c->rho_w_sum = 0;
+    return DGNS_OK;
+}
+
+int dgns_channel_stats_sample(dgns_ctx* c, const double* U) {
+    if (!c || !U) return fail(DGNS_EINVAL, "null argument");
+    if (!aligned8(U)) return fail(DGNS_EINVAL, "U must be 8-byte aligned");
+    std::vector<double> res;
+    double w[3];
+    int rc = channel_profiles(c, U, res);
+    if (!rc) rc = channel_wall_shear(c, U, w);
+    if (rc) return rc;
+    if (c->stats_sum.empty()) c->stats_sum.assign(res.size(), 0.0);
+    for (size_t m = 0; m < res.size(); ++m) c->stats_sum[m] += res[m];
+    c->tau_sum += w[0];
+    c->rho_w_sum += w[1];
+    ++c->stats_samples;
+    return DGNS_OK;
+}
+
+int dgns_channel_stats_result(dgns_ctx* c, double* profiles, double* scalars) {
+    if (!c || !profiles || !scalars) return fail(DGNS_EINVAL, "null argument");
+    if (c->stats_samples < 1) return fail(DGNS_EINVAL, "no samples");
+    const double ns = (double)c->stats_samples;
+    const double tau = c->tau_sum / ns, rho_w = c->rho_w_sum / ns;
+    if (!(tau > 0) || !(rho_w > 0)) return fail(DGNS_ENONFINITE, "mean wall shear %g is not positive", tau);
+    const double u_tau = std::sqrt(tau / rho_w), nu = c->prm.mu / c->prm.rho_ref;
+    const int64_t rows = (int64_t)c->stats_sum.size() / 9;
+    std::vector<double> out(rows * 8);
+    const double ylo = c->msh.lo[1];
+    for (int64_t r = 0; r < rows; ++r) {
+        const double* a = c->stats_sum.data() + r * 9;
+        const double y = a[0] / ns, rho = a[1] / ns, u = a[2] / ns, v = a[3] / ns, w = a[4] / ns;
+        const double uu = a[5] / ns, vv = a[6] / ns, ww = a[7] / ns, uv = a[8] / ns;
+        double* o = out.data() + r * 8;
+        o[0] = y;
+        o[1] = (y - ylo) * u_tau / nu;
+        o[2] = u / u_tau;
+        o[3] = std::sqrt(std::max(uu - u * u, 0.0)) / u_tau;
+        o[4] = std::sqrt(std::max(vv - v * v, 0.0)) / u_tau;
+        o[5] = std::sqrt(std::max(ww - w * w, 0.0)) / u_tau;
+        o[6] = (uv - u * v) / (u_tau * u_tau);
+        o[7] = rho;
+    }
+    std::copy(out.begin(), out.end(), profiles);
+    scalars[0] = u_tau;
+    scalars[1] = tau;
+    scalars[2] = rho_w;
+    scalars[3] = ns;
+    return DGNS_OK;
+}
+
+}  // extern "C"
+
+// Plane averages at the wall-normal Gauss points (see dgns_channel_statistics), on the host.
+static int channel_profiles(dgns_ctx* c, const double* U, std::vector<double>& res_out) {
     if (c->msh.kind == DGNS_MESH_CURVED)
         return fail(DGNS_EUNSUPPORTED, "channel statistics need planes of constant y (affine or channel mesh)");
     const int q = c->q, n1 = c->msh.n[1];
@@ -541,9 +703,48 @@ int dgns_channel_statistics(dgns_ctx* c, const double* U, double* out) {
                 if (!std::isfinite(o[m])) return fail(DGNS_ENONFINITE, "statistic %d at row %d, point %d is not finite", m, j, p);
         }
     }
-    std::copy(res.begin(), res.end(), out);   // written only on success
+    res_out.swap(res);
     return DGNS_OK;
 }
+
+// Mean wall shear over both walls in x_2: {tau_w, rho_w, wall area} (area-weighted means).
+static int channel_wall_shear(dgns_ctx* c, const double* U, double out3[3]) {
+    if (c->msh.periodic[1]) return fail(DGNS_EUNSUPPORTED, "the wall shear needs walls in direction 1");
+    if (c->msh.kind == DGNS_MESH_CURVED)
+        return fail(DGNS_EUNSUPPORTED, "the wall shear needs planar walls of constant x_2 (affine or channel mesh)");
+    const int64_t nw = 2 * (int64_t)c->msh.n[0] * c->msh.n[2];
+    if (!c->d_wall && hipMalloc((void**)&c->d_wall, sizeof(double) * kWallSumsHost * nw) != hipSuccess) {
+        c->d_wall = nullptr;
+        return fail(DGNS_ENOMEM, "wall shear buffer");
+    }
+    OpArgs a = make_args(c, U, nullptr, 0, 0);
+    int rc = 1;
+    switch (c->k) {
+        case 1: rc = launch_wall_shear_k1(a, c->tab, c->d_wall, c->gen, c->stream); break;
+        case 2: rc = launch_wall_shear_k2(a, c->tab, c->d_wall, c->gen, c->stream); break;
+        case 3: rc = launch_wall_shear_k3(a, c->tab, c->d_wall, c->gen, c->stream); break;
+        case 4: rc = launch_wall_shear_k4(a, c->tab, c->d_wall, c->gen, c->stream); break;
+        case 5: rc = launch_wall_shear_k5(a, c->tab, c->d_wall, c->gen, c->stream); break;
+        case 6: rc = launch_wall_shear_k6(a, c->tab, c->d_wall, c->gen, c->stream); break;
+        case 7: rc = launch_wall_shear_k7(a, c->tab, c->d_wall, c->gen, c->stream); break;
+    }
+    if (rc == 1) return fail(DGNS_EUNSUPPORTED, "no wall-shear kernel for degree %d, n_q %d", c->k, c->q);
+    if (rc != 0) return fail(DGNS_EHIP, "wall shear launch failed");
+    std::vector<double> part(kWallSumsHost * nw);
+    HIP_TRY(hipMemcpyAsync(part.data(), c->d_wall, sizeof(double) * part.size(), hipMemcpyDeviceToHost, c->stream));
+    HIP_TRY(hipStreamSynchronize(c->stream));
+    double t[3] = {0, 0, 0};
+    for (int64_t w = 0; w < nw; ++w)
+        for (int m = 0; m < 3; ++m) t[m] += part[w * kWallSumsHost + m];   // fixed order: deterministic
+    out3[0] = t[0] / t[2];
+    out3[1] = t[1] / t[2];
+    out3[2] = t[2];
+    for (int m = 0; m < 3; ++m)
+        if (!std::isfinite(out3[m])) return fail(DGNS_ENONFINITE, "wall shear sum %d is not finite", m);
+    return DGNS_OK;
+}
+
+extern "C" {
 
 static int ensure_scratch(dgns_ctx* c) {
     if (c->d_scratch) return 0;
@@ -574,34 +775,36 @@ int dgns_rk_step_vjp(dgns_ctx* c, const double* U_n, double t, double dt, const 
     if (!aligned8(U_n) || !aligned8(Ubar_np1) || !aligned8(Ubar_n) || !aligned8(work))
         return fail(DGNS_EINVAL, "vectors must be 8-byte aligned");
     const int64_t n = c->ndof;
-    if (overlap(work, 9 * n, U_n, n) || overlap(work, 9 * n, Ubar_np1, n) || overlap(work, 9 * n, Ubar_n, n) ||
+    const int s = c->rk_s;
+    const int64_t nw = (int64_t)(s + 4) * n;
+    if (overlap(work, nw, U_n, n) || overlap(work, nw, Ubar_np1, n) || overlap(work, nw, Ubar_n, n) ||
         overlap(Ubar_n, n, U_n, n) || (Ubar_n != Ubar_np1 && overlap(Ubar_n, n, Ubar_np1, n)))
         return fail(DGNS_EINVAL, "overlapping arguments");
     if (!std::isfinite(dt)) return fail(DGNS_EINVAL, "dt is not finite");
-    double* X = work;               // stage inputs U_1..U_4 (U_0 = U_n)
-    double* dU = work + 4 * n;
-    double* L = work + 5 * n;
-    double* dUb = work + 6 * n;
-    double* Rb = work + 7 * n;
-    double* T = work + 8 * n;
+    double* X = work;               // stage inputs U_1..U_{s-1} (U_0 = U_n)
+    double* dU = work + (int64_t)(s - 1) * n;
+    double* L = dU + n;
+    double* dUb = L + n;
+    double* Rb = dUb + n;
+    double* T = Rb + n;
     // forward recomputation of the stage inputs
-    for (int i = 0; i < 4; ++i) {
+    for (int i = 0; i < s - 1; ++i) {
         const double* src = i == 0 ? U_n : X + (int64_t)(i - 1) * n;
         double* Ui = X + (int64_t)i * n;
         HIP_TRY(hipMemcpyAsync(Ui, src, sizeof(double) * n, hipMemcpyDeviceToDevice, c->stream));
         int rc = dispatch_operator(c, make_args(c, src, L, DGNS_TERM_ALL, 1));
         if (rc) return rc;
-        if (launch_rk_update(Ui, dU, L, n, kRkA[i], kRkB[i], dt, c->stream) != 0)
+        if (launch_rk_update(Ui, dU, L, n, c->rk_A[i], c->rk_B[i], dt, c->stream) != 0)
             return fail(DGNS_EHIP, "rk update launch failed");
     }
-    // reverse sweep over the five stages
+    // reverse sweep over the stages
     if (Ubar_n != Ubar_np1)
         HIP_TRY(hipMemcpyAsync(Ubar_n, Ubar_np1, sizeof(double) * n, hipMemcpyDeviceToDevice, c->stream));
     if (launch_fill(dUb, n, 0.0, c->stream) != 0) return fail(DGNS_EHIP, "fill launch failed");
-    for (int i = 4; i >= 0; --i) {
+    for (int i = s - 1; i >= 0; --i) {
         const double* Xi = i == 0 ? U_n : X + (int64_t)(i - 1) * n;
         // U_i = U_{i-1} + B_i dU_i  ->  dUbar_i += B_i Ubar_i
-        if (launch_axpby(dUb, Ubar_n, n, 1.0, kRkB[i], c->stream) != 0) return fail(DGNS_EHIP, "axpby launch failed");
+        if (launch_axpby(dUb, Ubar_n, n, 1.0, c->rk_B[i], c->stream) != 0) return fail(DGNS_EHIP, "axpby launch failed");
         // K_i = L(U_{i-1}), dU_i = A_i dU_{i-1} + dt K_i  ->  Ubar_{i-1} += dt (dL/dU)^T dUbar_i
         int rc = dispatch_minv(c, dUb, Rb);
         if (rc) return rc;
@@ -609,7 +812,7 @@ int dgns_rk_step_vjp(dgns_ctx* c, const double* U_n, double t, double dt, const 
         if (rc) return rc;
         if (launch_axpby(Ubar_n, T, n, 1.0, dt, c->stream) != 0) return fail(DGNS_EHIP, "axpby launch failed");
         //  dUbar_{i-1} = A_i dUbar_i
-        if (launch_axpby(dUb, dUb, n, kRkA[i], 0.0, c->stream) != 0) return fail(DGNS_EHIP, "axpby launch failed");
+        if (launch_axpby(dUb, dUb, n, c->rk_A[i], 0.0, c->stream) != 0) return fail(DGNS_EHIP, "axpby launch failed");
     }
     return DGNS_OK;
 }

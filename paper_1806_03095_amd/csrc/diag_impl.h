@@ -394,6 +394,88 @@ chan_stats_kernel(OpArgs a, double* partial, KTab<N, Q, double> tb) {
     }
 }
 
+// Wall shear stress of the channel (Sec. 5.3, u_tau = sqrt(tau_w / rho)).  Workgroup w
+// takes the wall cell w of [the cells (i, k) of row j = 0, whose face xi_1 = 0 is the lower
+// wall | the cells of row j = n1 - 1, face xi_1 = 1 the upper wall] and sums over its wall
+// face's n_q^2 points, weighted by dA w, the shear mu du_1/dn with n the wall normal into
+// the fluid (+x_2 at the lower wall, -x_2 at the upper), the density and 1:
+// partial[3 w + {0, 1, 2}].  du_1/dx_2 = (d(rho u_1)/dx_2 - u_1 drho/dx_2)/rho from the
+// cell's polynomial, the physical derivative through the cell's J^{-1} at the face point.
+constexpr int kWallSums = 3;
+
+template <int N, int Q, bool GEN>
+__global__ void __launch_bounds__(64) chan_wall_shear_kernel(OpArgs a, double* partial, KTab<N, Q, double> tb) {
+    constexpr int N2 = N * N, N3 = N2 * N, Q2 = Q * Q;
+    __shared__ double sX[2 * N3];   // rho, rho u_1
+    __shared__ double red[kWallSums * 64];
+    const int n0 = a.n[0], n1 = a.n[1], n2 = a.n[2];
+    const int w = blockIdx.x, tid = threadIdx.x;
+    const int top = w >= n0 * n2 ? 1 : 0;
+    const int wl = w - top * n0 * n2, i = wl % n0, kk = wl / n0, j = top ? n1 - 1 : 0;
+    const int64_t e = i + (int64_t)n0 * (j + (int64_t)n1 * kk);
+    const int64_t cs = a.ncell * N3;
+    for (int m = tid; m < 2 * N3; m += blockDim.x) sX[m] = a.U[(m / N3) * cs + e * N3 + m % N3];
+    __syncthreads();
+    const int s = top;
+    // face point number r = q0 + Q q2 (tangential axes x_0, x_2); face id of the wall face
+    const int64_t fid = (j + s) + (int64_t)(n1 + 1) * (i + (int64_t)n0 * kk);
+    double acc[kWallSums] = {0, 0, 0};
+    for (int r = tid; r < Q2; r += blockDim.x) {
+        const int q0 = r % Q, q2 = r / Q;
+        double v[2] = {0, 0}, g[2][3] = {{0, 0, 0}, {0, 0, 0}};
+        for (int a2 = 0; a2 < N; ++a2)
+            for (int a1 = 0; a1 < N; ++a1)
+                for (int a0 = 0; a0 < N; ++a0) {
+                    const double p0 = tb.S[q0][a0], p1 = tb.fv[s][a1], p2 = tb.S[q2][a2];
+                    const double d0 = tb.D[q0][a0], d1 = tb.fd[s][a1], d2 = tb.D[q2][a2];
+                    for (int c = 0; c < 2; ++c) {
+                        const double x = sX[c * N3 + a0 + N * (a1 + N * a2)];
+                        v[c] += p0 * p1 * p2 * x;
+                        g[c][0] += d0 * p1 * p2 * x;
+                        g[c][1] += p0 * d1 * p2 * x;
+                        g[c][2] += p0 * p1 * d2 * x;
+                    }
+                }
+        double Ji[9], dAw;
+        if constexpr (GEN) {
+            const double* fd = a.face_data[1] + fid * 22 * Q2 + r;
+            dAw = fd[3 * Q2];
+            const int own = s ? 4 : 13;   // the cell is the lower side of the upper wall face
+            for (int m = 0; m < 9; ++m) Ji[m] = fd[(own + m) * Q2];
+        } else {
+            const double* cm = a.cell_metric + e * 10;
+            for (int m = 0; m < 9; ++m) Ji[m] = cm[m];
+            const double l = sqrt(cm[3] * cm[3] + cm[4] * cm[4] + cm[5] * cm[5]);
+            dAw = cm[9] * l * tb.w[q0] * tb.w[q2];
+        }
+        // d/dx_2 = sum_d (dxi_d / dx_2) d/dxi_d
+        const double drho = Ji[1] * g[0][0] + Ji[4] * g[0][1] + Ji[7] * g[0][2];
+        const double dm = Ji[1] * g[1][0] + Ji[4] * g[1][1] + Ji[7] * g[1][2];
+        const double u = v[1] / v[0];
+        const double dudy = (dm - u * drho) / v[0];
+        acc[0] += dAw * a.mu * (s ? -dudy : dudy);
+        acc[1] += dAw * v[0];
+        acc[2] += dAw;
+    }
+    for (int m = 0; m < kWallSums; ++m) red[m * 64 + tid] = acc[m];
+    __syncthreads();
+    if (tid < kWallSums) {
+        double t = 0;
+        for (int l = 0; l < 64; ++l) t += red[tid * 64 + l];
+        partial[(int64_t)w * kWallSums + tid] = t;
+    }
+}
+
+template <int N, int Q, bool GEN>
+inline int launch_wall_shear_t(const OpArgs& a, const Tables1D& t, double* partial, hipStream_t st) {
+    KTab<N, Q, double> kt;
+    MTab<N, double> mt;
+    fill_tables<N, Q, double>(t, kt, mt);
+    hipLaunchKernelGGL((chan_wall_shear_kernel<N, Q, GEN>), dim3((unsigned)(2 * a.n[0] * a.n[2])), dim3(64), 0, st, a,
+                       partial, kt);
+    return hipGetLastError() == hipSuccess ? 0 : -1;
+}
+
 template <int N, int Q, bool GEN>
 inline int launch_chan_stats_t(const OpArgs& a, const Tables1D& t, double* partial, hipStream_t st) {
     KTab<N, Q, double> kt;

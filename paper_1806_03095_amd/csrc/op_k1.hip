@@ -47,6 +47,14 @@ int launch_chan_stats_k1(const OpArgs& a, const Tables1D& t, double* partial, bo
     }
 }
 
+int launch_wall_shear_k1(const OpArgs& a, const Tables1D& t, double* partial, bool gen, hipStream_t st) {
+    switch (t.q) {
+        case 2: return gen ? launch_wall_shear_t<2, 2, true>(a, t, partial, st) : launch_wall_shear_t<2, 2, false>(a, t, partial, st);
+        case 3: return gen ? launch_wall_shear_t<2, 3, true>(a, t, partial, st) : launch_wall_shear_t<2, 3, false>(a, t, partial, st);
+        default: return 1;
+    }
+}
+
 int launch_ke_vjp_k1(const OpArgs& a, const Tables1D& t, double* Ub, bool gen, hipStream_t st) {
     switch (t.q) {
         case 2: return gen ? launch_ke_vjp_t<2, 2, true>(a, t, Ub, st) : launch_ke_vjp_t<2, 2, false>(a, t, Ub, st);

@@ -52,6 +52,15 @@ int launch_chan_stats_k2(const OpArgs& a, const Tables1D& t, double* partial, bo
     }
 }
 
+int launch_wall_shear_k2(const OpArgs& a, const Tables1D& t, double* partial, bool gen, hipStream_t st) {
+    switch (t.q) {
+        case 3: return gen ? launch_wall_shear_t<3, 3, true>(a, t, partial, st) : launch_wall_shear_t<3, 3, false>(a, t, partial, st);
+        case 4: return gen ? launch_wall_shear_t<3, 4, true>(a, t, partial, st) : launch_wall_shear_t<3, 4, false>(a, t, partial, st);
+        case 5: return gen ? launch_wall_shear_t<3, 5, true>(a, t, partial, st) : launch_wall_shear_t<3, 5, false>(a, t, partial, st);
+        default: return 1;
+    }
+}
+
 int launch_ke_vjp_k2(const OpArgs& a, const Tables1D& t, double* Ub, bool gen, hipStream_t st) {
     switch (t.q) {
         case 3: return gen ? launch_ke_vjp_t<3, 3, true>(a, t, Ub, st) : launch_ke_vjp_t<3, 3, false>(a, t, Ub, st);

@@ -57,6 +57,16 @@ int launch_chan_stats_k3(const OpArgs& a, const Tables1D& t, double* partial, bo
     }
 }
 
+int launch_wall_shear_k3(const OpArgs& a, const Tables1D& t, double* partial, bool gen, hipStream_t st) {
+    switch (t.q) {
+        case 4: return gen ? launch_wall_shear_t<4, 4, true>(a, t, partial, st) : launch_wall_shear_t<4, 4, false>(a, t, partial, st);
+        case 5: return gen ? launch_wall_shear_t<4, 5, true>(a, t, partial, st) : launch_wall_shear_t<4, 5, false>(a, t, partial, st);
+        case 6: return gen ? launch_wall_shear_t<4, 6, true>(a, t, partial, st) : launch_wall_shear_t<4, 6, false>(a, t, partial, st);
+        case 7: return gen ? launch_wall_shear_t<4, 7, true>(a, t, partial, st) : launch_wall_shear_t<4, 7, false>(a, t, partial, st);
+        default: return 1;
+    }
+}
+
 int launch_ke_vjp_k3(const OpArgs& a, const Tables1D& t, double* Ub, bool gen, hipStream_t st) {
     switch (t.q) {
         case 4: return gen ? launch_ke_vjp_t<4, 4, true>(a, t, Ub, st) : launch_ke_vjp_t<4, 4, false>(a, t, Ub, st);

@@ -47,6 +47,14 @@ int launch_chan_stats_k5(const OpArgs& a, const Tables1D& t, double* partial, bo
     }
 }
 
+int launch_wall_shear_k5(const OpArgs& a, const Tables1D& t, double* partial, bool gen, hipStream_t st) {
+    switch (t.q) {
+        case 6: return gen ? launch_wall_shear_t<6, 6, true>(a, t, partial, st) : launch_wall_shear_t<6, 6, false>(a, t, partial, st);
+        case 8: return gen ? launch_wall_shear_t<6, 8, true>(a, t, partial, st) : launch_wall_shear_t<6, 8, false>(a, t, partial, st);
+        default: return 1;
+    }
+}
+
 int launch_ke_vjp_k5(const OpArgs& a, const Tables1D& t, double* Ub, bool gen, hipStream_t st) {
     switch (t.q) {
         case 6: return gen ? launch_ke_vjp_t<6, 6, true>(a, t, Ub, st) : launch_ke_vjp_t<6, 6, false>(a, t, Ub, st);

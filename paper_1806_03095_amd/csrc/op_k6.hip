@@ -42,6 +42,14 @@ int launch_chan_stats_k6(const OpArgs& a, const Tables1D& t, double* partial, bo
     }
 }
 
+int launch_wall_shear_k6(const OpArgs& a, const Tables1D& t, double* partial, bool gen, hipStream_t st) {
+    switch (t.q) {
+        case 7: return gen ? launch_wall_shear_t<7, 7, true>(a, t, partial, st) : launch_wall_shear_t<7, 7, false>(a, t, partial, st);
+        case 10: return gen ? launch_wall_shear_t<7, 10, true>(a, t, partial, st) : launch_wall_shear_t<7, 10, false>(a, t, partial, st);
+        default: return 1;
+    }
+}
+
 int launch_ke_vjp_k6(const OpArgs& a, const Tables1D& t, double* Ub, bool gen, hipStream_t st) {
     switch (t.q) {
         case 7: return gen ? launch_ke_vjp_t<7, 7, true>(a, t, Ub, st) : launch_ke_vjp_t<7, 7, false>(a, t, Ub, st);

@@ -42,6 +42,14 @@ int launch_chan_stats_k7(const OpArgs& a, const Tables1D& t, double* partial, bo
     }
 }
 
+int launch_wall_shear_k7(const OpArgs& a, const Tables1D& t, double* partial, bool gen, hipStream_t st) {
+    switch (t.q) {
+        case 8: return gen ? launch_wall_shear_t<8, 8, true>(a, t, partial, st) : launch_wall_shear_t<8, 8, false>(a, t, partial, st);
+        case 11: return gen ? launch_wall_shear_t<8, 11, true>(a, t, partial, st) : launch_wall_shear_t<8, 11, false>(a, t, partial, st);
+        default: return 1;
+    }
+}
+
 int launch_ke_vjp_k7(const OpArgs& a, const Tables1D& t, double* Ub, bool gen, hipStream_t st) {
     switch (t.q) {
         case 8: return gen ? launch_ke_vjp_t<8, 8, true>(a, t, Ub, st) : launch_ke_vjp_t<8, 8, false>(a, t, Ub, st);

@@ -6,8 +6,10 @@
 //   in.bin : dgns_params, dgns_box_mesh, uint32 terms, int32 mode, then U (n_dof float64)
 //            and, for mode 2, Rbar (n_dof float64)
 //   mode   : 0 residual R, 1 operator L = M^{-1} R, 2 residual adjoint Ubar = (dR/dU)^T Rbar,
-//            3 standalone inverse mass M^{-1} U, 4 channel-statistics partial sums
-//   out.bin: R, L, Ubar or M^{-1} U (n_dof float64); mode 4: n_cells * n_q * 9 float64
+//            3 standalone inverse mass M^{-1} U, 4 channel-statistics partial sums,
+//            5 wall-shear partial sums
+//   out.bin: R, L, Ubar or M^{-1} U (n_dof float64); mode 4: n_cells * n_q * 9 float64;
+//            mode 5: 2 n0 n2 * 3 float64 (lower-wall cells, then upper)
 #include <cstdio>
 #include <string>
 #include <vector>
@@ -35,6 +37,11 @@ int run(const OpArgs& a, const Tables1D& t, int fp32, int gen) {
 template <int N, int Q>
 int run_stats(const OpArgs& a, const Tables1D& t, int gen) {
     return gen ? launch_chan_stats_t<N, Q, true>(a, t, a.out, nullptr) : launch_chan_stats_t<N, Q, false>(a, t, a.out, nullptr);
+}
+
+template <int N, int Q>
+int run_wall(const OpArgs& a, const Tables1D& t, int gen) {
+    return gen ? launch_wall_shear_t<N, Q, true>(a, t, a.out, nullptr) : launch_wall_shear_t<N, Q, false>(a, t, a.out, nullptr);
 }
 
 template <int N>
@@ -69,7 +76,8 @@ int main(int argc, char** argv) {
         return 5;
     }
     const int64_t ndof = 5 * hs.ncell * hs.n3;
-    const int64_t nout = fuse == 4 ? hs.ncell * prm.n_q * kStats : ndof;
+    const int64_t nout = fuse == 4 ? hs.ncell * prm.n_q * kStats
+                                   : (fuse == 5 ? (int64_t)2 * msh.n[0] * msh.n[2] * kWallSums : ndof);
     std::vector<double> U(ndof), out(nout, -12345.0), Rb;
     // face buffer of the split evaluation: six lifted blocks [2][5][N^2] per cell (sized
     // for float64, enough for float32); filled with a value that would show if read unwritten
@@ -108,7 +116,9 @@ int main(int argc, char** argv) {
     if (k == K && q == Q_)                                                                                   \
         rc = fuse == 2 ? run_adj<K + 1, Q_>(a, Rb.data(), hs.tab, gen)                                        \
                        : (fuse == 3 ? run_minv<K + 1>(a, hs.tab, fp32, gen)                                  \
-                                    : (fuse == 4 ? run_stats<K + 1, Q_>(a, hs.tab, gen) : run<K + 1, Q_>(a, hs.tab, fp32, gen)));
+                                    : (fuse == 4 ? run_stats<K + 1, Q_>(a, hs.tab, gen)                   \
+                                                 : (fuse == 5 ? run_wall<K + 1, Q_>(a, hs.tab, gen)          \
+                                                              : run<K + 1, Q_>(a, hs.tab, fp32, gen))));
     EMU_CASES
     if (rc != 0) {
         std::fprintf(stderr, "no emulated kernel for k=%d nq=%d\n", k, q);

@@ -55,7 +55,8 @@ class _Mesh(ctypes.Structure):
 def run(U, k, nq, n, lo, hi, periodic=(1, 1, 1), kind=0, basis=0, precision=0, gamma=1.4, R=287.0, mu=0.0,
         lam=0.0, rho_ref=1.0, force=(0, 0, 0), wall_T=0.0, amp=0.0, C=1.8, terms=7, fuse=0, Rbar=None):
     """fuse: 0 residual, 1 operator (with M^{-1}), 2 residual adjoint of Rbar, 3 standalone M^{-1} U,
-    4 channel-statistics partial sums (returned as [n_cells, n_q, 9])."""
+    4 channel-statistics partial sums (returned as [n_cells, n_q, 9]), 5 wall-shear partial sums
+    (returned as [2 n0 n2, 3])."""
     exe = build()
     p = _Params(k, nq, basis, precision, gamma, R, mu, lam, rho_ref, (ctypes.c_double * 3)(*force), wall_T)
     m = _Mesh((ctypes.c_int * 3)(*n), (ctypes.c_double * 3)(*lo), (ctypes.c_double * 3)(*hi),
@@ -75,4 +76,6 @@ def run(U, k, nq, n, lo, hi, periodic=(1, 1, 1), kind=0, basis=0, precision=0, g
         if r.returncode != 0:
             raise RuntimeError("emulated kernel failed (%d):\n%s" % (r.returncode, r.stderr[-4000:]))
         out = np.fromfile(fo, dtype=np.float64)
+        if fuse == 5:
+            return out.reshape(-1, 3)
         return out.reshape(-1, nq, 9) if fuse == 4 else out.reshape(U.shape)

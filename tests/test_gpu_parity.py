@@ -457,3 +457,62 @@ def test_misaligned_vectors_rejected_before_launch():
         assert call(bad) == binding.EINVAL, name
     torch.cuda.synchronize()
     assert float(buf.abs().max()) == 0.0   # nothing was written
+
+
+@pytest.mark.parametrize("scheme", ["williamson3", "four_stage"])
+def test_rk_step_with_another_scheme(scheme):
+    # dgns_set_rk_scheme: a three-stage third-order scheme (two fused stages) and a four-stage
+    # coefficient table (three fused stages: the state ends in the work buffer and is copied
+    # back) against the oracle's 2N recurrence with the same coefficients; then the default
+    # is restored and matches the five-stage scheme's stage times
+    announce("rk_step with the %s scheme" % scheme)
+    if scheme == "williamson3":
+        A = [float(v) for v in timeint.WS33_A]
+        B = [float(v) for v in timeint.WS33_B]
+    else:
+        A, B = [0.0, -0.41, -0.93, -1.17], [0.31, 0.52, 0.71, 0.23]
+    oop, gop = make_pair((3, 2, 2), 3, 5)
+    U0 = tgv_input(oop, seed=12, mach=0.3)
+    gop.set_rk_scheme(A, B)
+    got_A, got_B, got_c = gop.rk_scheme()
+    assert got_A == A and got_B == B
+    dt = gop.compute_dt(0.3, 0.02, 1.5, 3.0, 1.0, 0.3)
+    Ug = _cuda(U0.clone())
+    work = torch.empty(2 * gop.n_dof, dtype=torch.float64, device="cuda")
+    for s in range(2):
+        gop.rk_step(Ug, work, s * dt, dt)
+    torch.cuda.synchronize()
+    U = U0.clone()
+    for s in range(2):
+        U = timeint.lsrk_step(lambda V, t: oop.apply(V), U, s * dt, dt, A=A, B=B, C=got_c)
+    errs = rel_err_fields(Ug.cpu() - U0, U - U0)
+    print("%s: two steps, increment per field vs oracle %s" % (scheme, ["%.1e" % e for e in errs]), flush=True)
+    assert max(errs) < 1e-11, errs
+    # the stage update takes stage indices of this scheme only
+    from paper_1806_03095_amd.binding import DgnsError
+    with pytest.raises(DgnsError):
+        gop.rk_stage_update(_cuda(U0.clone()), torch.zeros_like(Ug), Ug, len(A), dt)
+    gop.set_rk_scheme()
+    A5, B5, c5 = gop.rk_scheme()
+    assert len(A5) == 5 and max(abs(x - float(y)) for x, y in zip(c5, timeint.CK54_C)) < 1e-15
+    with pytest.raises(DgnsError):
+        gop.set_rk_scheme([0.5, 0.1], [0.5, 0.5])     # A[0] must be 0
+
+
+def test_rk_step_vjp_with_another_scheme():
+    announce("rk_step_vjp with the three-stage scheme vs oracle autograd")
+    A = [float(v) for v in timeint.WS33_A]
+    B = [float(v) for v in timeint.WS33_B]
+    oop, gop = make_pair((2, 2, 2), 2, 4)
+    gop.set_rk_scheme(A, B)
+    U = tgv_input(oop, seed=13, mach=0.3)
+    dt = gop.compute_dt(0.3, 0.02, 1.5, 3.0, 1.0, 0.3)
+    Ub1 = torch.as_tensor(np.random.default_rng(5).standard_normal(tuple(U.shape)))
+    got = gop.rk_step_vjp(_cuda(U), 0.0, dt, _cuda(Ub1))
+    torch.cuda.synchronize()
+    V = U.clone().requires_grad_(True)
+    out = timeint.lsrk_step(lambda W, t: oop.apply(W), V, 0.0, dt, A=A, B=B, C=gop.rk_scheme()[2])
+    (want,) = torch.autograd.grad(out, V, grad_outputs=Ub1)
+    errs = rel_err_fields(got, want)
+    print("rk_step_vjp three-stage per field", ["%.1e" % e for e in errs], flush=True)
+    assert max(errs) < 1e-11, errs

@@ -174,6 +174,25 @@ def test_emulated_channel_statistics(n, k, nq, kind):
         assert np.abs(got - ref).max() <= 1e-12 * np.abs(ref).max(), j
 
 
+@pytest.mark.parametrize("k,nq,kind", [(3, 6, 0), (4, 7, 1)])
+def test_emulated_wall_shear(k, nq, kind):
+    # per-wall-cell sums of the wall-shear kernel, totalled here, against the oracle's
+    # mean wall shear, wall density and area
+    lo, hi = (0.0, -1.0, 0.0), (2 * math.pi, 1.0, math.pi)
+    fl = tgv_fluid(mu=1.0 / 180.0)
+    n = (2, 3, 2)
+    om = omesh.BoxMesh(n, lo, hi, k, periodic=(True, False, True), kind=kind)
+    oop = ooperator.DGOperator(om, fl, nq, wall_T=100.0)
+    U = channel_input(oop)
+    part = ed.run(U.numpy(), k, nq, n, lo, hi, periodic=(1, 0, 1), kind=kind, mu=fl.mu, lam=fl.lam, wall_T=100.0,
+                  fuse=5)
+    tot = part.sum(axis=0)
+    tau, rho_w, area = odiag.channel_wall_shear(oop, U)
+    assert abs(tot[0] / tot[2] - tau) <= 1e-12 * abs(tau)
+    assert abs(tot[1] / tot[2] - rho_w) <= 1e-13 * rho_w
+    assert abs(tot[2] - area) <= 1e-13 * area
+
+
 def test_lds_plan_layout():
     # every compiled (degree, n_q) in both precisions: the work area holds every phase,
     # regions used at once are disjoint, the fused trace items fill whole waves, and the

@@ -72,3 +72,57 @@ def test_channel_mesh_points_are_symmetric():
     y = odiag.channel_statistics(oop, U)[:, 0]
     assert np.abs(y + y[::-1]).max() < 1e-14
     assert np.all(np.diff(y) > 0) and -1.0 < y[0] and y[-1] < 1.0
+
+
+def _wall_box(k=2, nq=3):
+    m = omesh.BoxMesh((3, 2, 2), (0.0, -1.0, 0.0), (2 * math.pi, 1.0, math.pi), k, periodic=(True, False, True))
+    fl = ph.Fluid(gamma=1.4, R=287.0, mu=0.01, lam=0.0, rho_ref=1.0)
+    return ooperator.DGOperator(m, fl, nq, wall_T=300.0)
+
+
+def _state(op, ufun, p=1.0e5):
+    def f(x):
+        u = np.zeros(x.shape)
+        u[..., 0] = ufun(x[..., 1])
+        return ph.conserved_from_primitive(torch.ones(x.shape[:-1], dtype=torch.float64), torch.as_tensor(u),
+                                           torch.full(x.shape[:-1], p, dtype=torch.float64), op.fl)
+    return initial.l2_project(op, f)
+
+
+def _poiseuille_pin():
+    op = _wall_box()
+    tau, rho_w, area = odiag.channel_wall_shear(op, _state(op, lambda y: 3.0 * (1.0 - y ** 2)))
+    return op, tau, rho_w, area
+
+
+def test_wall_shear_of_poiseuille_and_couette_profiles():
+    # the k = 2 space holds u = a (1 - y^2) and u = b (y + 1) exactly on an affine box:
+    # Poiseuille has tau_w = 2 mu a at both walls, a linear (Couette) profile +mu b at the
+    # lower and -mu b at the upper wall (the normal into the fluid flips), mean 0
+    op, tau, rho_w, area = _poiseuille_pin()
+    assert abs(tau - 2 * op.fl.mu * 3.0) < 1e-12 and abs(rho_w - 1.0) < 1e-13
+    assert abs(area - 2 * (2 * math.pi) * math.pi) < 1e-12
+    tau, _, _ = odiag.channel_wall_shear(op, _state(op, lambda y: 2.0 * (y + 1.0)))
+    assert abs(tau) < 1e-13
+
+
+def test_wall_shear_pin_detects_a_transposed_velocity_gradient(monkeypatch):
+    # plant: du_j/dx_a in place of du_a/dx_j -- the shear then reads du_2/dx_1 = 0
+    orig = ph.velocity_gradient
+    monkeypatch.setattr(ph, "velocity_gradient", lambda U, G: orig(U, G).transpose(-1, -2))
+    op, tau, _, _ = _poiseuille_pin()
+    assert abs(tau - 2 * op.fl.mu * 3.0) > 0.5 * 2 * op.fl.mu * 3.0
+
+
+def test_plus_statistics_of_one_laminar_sample():
+    # one sample of the Poiseuille state: u_tau = sqrt(2 mu a), u+ = u / u_tau, no fluctuations
+    op = _wall_box(k=2, nq=4)
+    a = 3.0
+    U = _state(op, lambda y: a * (1.0 - y ** 2))
+    prof = odiag.channel_statistics(op, U)
+    rows, u_tau = odiag.channel_plus_statistics([prof], [odiag.channel_wall_shear(op, U)], op.fl.nu, -1.0)
+    assert abs(u_tau - math.sqrt(2 * op.fl.mu * a)) < 1e-12
+    y = rows[:, 0]
+    assert np.allclose(rows[:, 1], (y + 1.0) * u_tau / op.fl.nu, rtol=1e-13)
+    assert np.allclose(rows[:, 2], a * (1.0 - y ** 2) / u_tau, rtol=1e-12)
+    assert np.all(rows[:, 3:6] < 1e-5) and np.all(np.abs(rows[:, 6]) < 1e-10)

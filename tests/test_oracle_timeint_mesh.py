@@ -114,6 +114,19 @@ def test_rk_order_conditions_exact():
     assert abs(float(sb(lambda i: c[i] ** 4) - Fr(1, 5))) > 1e-6
 
 
+def test_williamson_scheme_is_third_order():
+    # the second 2N scheme the library is tested with: order conditions up to three hold
+    # exactly, the first fourth-order one does not
+    a, b, c = timeint.butcher_from_2n(timeint.WS33_A, timeint.WS33_B)
+    s = len(b)
+    sb = lambda f: sum(b[i] * f(i) for i in range(s))
+    assert sb(lambda i: 1) == 1
+    assert sb(lambda i: c[i]) == Fr(1, 2)
+    assert sb(lambda i: c[i] ** 2) == Fr(1, 3)
+    assert sb(lambda i: sum(a[i][j] * c[j] for j in range(s))) == Fr(1, 6)
+    assert sb(lambda i: c[i] ** 3) != Fr(1, 4)
+
+
 def test_rk_observed_order_nonautonomous():
     # y' = -y + sin(t) + t cos(t) ... exact solution y = t sin(t) + exp(-t) (y(0) = 1)
     f = lambda y, t: -y + np.sin(t) + t * np.cos(t) + t * np.sin(t)
