@@ -48,6 +48,9 @@ CRITICAL = {2: (0.36, 0.018), 3: (0.40, 0.020), 5: (0.42, 0.020), 7: (0.40, 0.01
 # study at k = 5 and 7 uses 0.25 (0.6 of the critical 0.42 / 0.40).
 CR = 0.27
 CR_STUDY = 0.25
+# diffusion number: the paper's ratio to the critical one (D = 0.02 against 0.036), 0.56 x 0.020;
+# at Re = 1600 the viscous restriction does not bind either way
+D_RUN = 0.011
 MEASURED_TRAFFIC = {"fingerprint": "59f5ca1614a8f36c", "workload": (32, 3, 6), "bytes": 862676276.6}
 
 
@@ -192,7 +195,7 @@ def graph_timing(steps=50):
         op = taylor_green(3, ne, 6)
         U = op.project_ic("taylor_green", [1.0, 1.0, 0.1, 1.0])
         work = torch.empty(2 * op.n_dof, dtype=torch.float64, device="cuda")
-        dt = op.compute_dt(CR, 0.02, 1.5, 3.0, 1.0, 0.1)
+        dt = op.compute_dt(CR, D_RUN, 1.5, 3.0, 1.0, 0.1)
         t_eager, _ = time_rk(op, U, work, dt, steps, 5)
         g = op.rk_graph(U, work, dt, steps)
         g.replay()
@@ -220,7 +223,7 @@ def adjoint_timing():
     from paper_1806_03095_amd.autograd import kinetic_energy, rk_rollout
     op = taylor_green(3, 16, n_q=6)
     U0 = op.project_ic("taylor_green", [1.0, 1.0, 0.1, 1.0])
-    dt = op.compute_dt(CR, 0.02, 1.5, 3.0, 1.0, 0.1)
+    dt = op.compute_dt(CR, D_RUN, 1.5, 3.0, 1.0, 0.1)
     L = torch.empty_like(U0)
     t_op = time_call(lambda: op.apply(U0, L), 20)
     Ub = torch.empty_like(U0)
@@ -265,17 +268,52 @@ def degree_sweep(target_dofs=10_000_000, calls=20):
                 tag = prec if mesh == "affine" else prec + "_deformed"
                 row[tag + "_L_dofs_per_s"] = op.n_dof / t
                 if prec == "fp64" and mesh == "affine":
-                    for name, mask in (("F_c", 1), ("F_v", 2)):
+                    for name, mask in (("F_c", 1), ("F_v", 2), ("F", 7)):
                         tt = time_call(lambda: op.residual(U, L, terms=mask), calls)
                         row["fp64_%s_dofs_per_s" % name] = op.n_dof / tt
                     tt = time_call(lambda: op.inverse_mass(U, L), calls)
                     row["fp64_M_inv_dofs_per_s"] = op.n_dof / tt
+                    Uc, dU = U.clone(), torch.zeros_like(U)
+                    tt = time_call(lambda: op.rk_stage_update(Uc, dU, L, 1, 1e-12), calls)
+                    row["fp64_rk_update_dofs_per_s"] = op.n_dof / tt
+                    del Uc, dU
                 op.close()
             log("k=%d n_q=%d %d^3: L fp64 %.3e fp32 %.3e, deformed fp64 %.3e fp32 %.3e DoF/s"
                 % (k, nq, ne, row["fp64_L_dofs_per_s"], row["fp32_L_dofs_per_s"],
                    row["fp64_deformed_L_dofs_per_s"], row["fp32_deformed_L_dofs_per_s"]))
             rows.append(row)
     return rows
+
+
+def memops_streamed(calls=20):
+    """The memory-bound operations with vectors far beyond the 256 MB last-level cache:
+    M^{-1} (16 B/DoF) and the stand-alone Runge-Kutta stage update (40 B/DoF) on Taylor-Green
+    meshes of about 80M DoFs (k = 3: 64^3 cells, 671 MB per vector; k = 4: 50^3; k = 5:
+    42^3), as fractions of the 8 TB/s HBM peak and of a measured device copy."""
+    import torch
+    from paper_1806_03095_amd import taylor_green
+    bw = copy_bandwidth(2048, 10)
+    rows = []
+    for k, ne in ((3, 64), (4, 50), (5, 42)):
+        op = taylor_green(k, ne)
+        U = torch.rand(op.shape, dtype=torch.float64, device="cuda") + 1.0
+        L = torch.empty_like(U)
+        t_m = time_call(lambda: op.inverse_mass(U, L), calls)
+        dU = torch.zeros_like(U)
+        t_u = time_call(lambda: op.rk_stage_update(U, dU, L, 1, 1e-12), calls)
+        row = {"k": k, "cells": ne ** 3, "n_dof": op.n_dof, "vector_MB": 8e-6 * op.n_dof,
+               "M_inv_us": 1e6 * t_m, "M_inv_hbm_frac": 16 * op.n_dof / t_m / PEAK_HBM,
+               "M_inv_frac_of_copy": 16 * op.n_dof / t_m / bw,
+               "rk_update_us": 1e6 * t_u, "rk_update_hbm_frac": 40 * op.n_dof / t_u / PEAK_HBM,
+               "rk_update_frac_of_copy": 40 * op.n_dof / t_u / bw}
+        log("streamed k=%d %d^3 (%.0f MB/vector): M^-1 %.1f us (%.0f%% of HBM peak), update %.1f us (%.0f%%)"
+            % (k, ne, row["vector_MB"], row["M_inv_us"], 100 * row["M_inv_hbm_frac"], row["rk_update_us"],
+               100 * row["rk_update_hbm_frac"]))
+        rows.append(row)
+        op.close()
+        del U, L, dU
+        torch.cuda.empty_cache()
+    return {"copy_bytes_per_s": bw, "rows": rows}
 
 
 def precision_study(steps):
@@ -289,7 +327,7 @@ def precision_study(steps):
     for ne, k, nq in ((16, 7, 11), (24, 5, 8)):
         ops = {p: taylor_green(k, ne, n_q=nq, precision=p) for p in ("fp64", "fp32")}
         U0 = ops["fp64"].project_ic("taylor_green", [1.0, 1.0, 0.1, 1.0])
-        dt = ops["fp64"].compute_dt(CR_STUDY, 0.02, 1.5, 3.0, 1.0, 0.1)
+        dt = ops["fp64"].compute_dt(CR_STUDY, D_RUN, 1.5, 3.0, 1.0, 0.1)
         e0 = fp32_error(ops["fp64"], ops["fp32"], U0)
         row = {"workload": "taylor_green_%dcubed_k%d_nq%d" % (ne, k, nq), "n_dof": ops["fp64"].n_dof,
                "steps": steps, "dt": dt, "L0_rel_err": e0["whole_vector"], "L0_rel_err_per_field": e0["per_field"],
@@ -478,6 +516,8 @@ def main():
                     help="skip the operation breakdown, copy bandwidth and channel figures")
     ap.add_argument("--sweep", action="store_true",
                     help="study mode: operator throughput over every compiled (k, n_q); one JSON line")
+    ap.add_argument("--memops-streamed", action="store_true",
+                    help="study mode: M^-1 and the RK update past the last-level cache (k = 3..5); one JSON line")
     ap.add_argument("--critical-cfl", action="store_true",
                     help="study mode: critical Courant and diffusion numbers per degree (Sec. 5.2.2 method); one JSON line")
     ap.add_argument("--precision-study", type=int, default=0, metavar="STEPS",
@@ -503,6 +543,9 @@ def main():
 
     if args.sweep:
         print(json.dumps({"degree_sweep": degree_sweep()}), flush=True)
+        return
+    if args.memops_streamed:
+        print(json.dumps({"memops_streamed": memops_streamed()}), flush=True)
         return
     if args.critical_cfl:
         print(json.dumps({"critical_numbers": critical_numbers()}), flush=True)
@@ -538,7 +581,7 @@ def main():
     op = taylor_green(k, ne, n_q=nq, precision="fp64")
     ndof = op.n_dof
     U0 = op.project_ic("taylor_green", [1.0, 1.0, 0.1, 1.0])
-    dt = op.compute_dt(CR, 0.02, 1.5, 3.0, 1.0, 0.1)
+    dt = op.compute_dt(CR, D_RUN, 1.5, 3.0, 1.0, 0.1)
     work = torch.empty(2 * ndof, dtype=torch.float64, device="cuda")
     U = U0.clone()
     log("fp64: %d warmup + %d timed RK steps, dt=%.4e" % (args.warmup, args.steps, dt))

@@ -42,6 +42,27 @@ struct KTab {
     Real fd[2][N];
 };
 
+// Even-odd form of an NO x NI matrix M on point sets symmetric about 1/2, for which
+// M[NO-1-p][NI-1-i] = sg M[p][i] (sg = +1 for the values S, -1 for the derivatives D):
+// E[p][i] = (M[p][i] + M[p][NI-1-i]) / 2, O[p][i] = (M[p][i] - M[p][NI-1-i]) / 2 for
+// p < (NO+1)/2, i < NI/2, and C[p] = M[p][NI/2] (the middle column, odd NI).  Then with
+// v_e = v_i + v_{NI-1-i}, v_o = v_i - v_{NI-1-i}:  e = E v_e + C v_mid, o = O v_o,
+// (M v)[p] = e + o and (M v)[NO-1-p] = sg (e - o): half the multiply-adds (Sec. 2.3).
+template <int NO, int NI, typename Real>
+struct EOMat {
+    static constexpr int HO = (NO + 1) / 2, HI = NI / 2 > 0 ? NI / 2 : 1;
+    Real E[HO][HI];
+    Real O[HO][HI];
+    Real C[HO];
+};
+
+// The even-odd forms of S and D (NO = n_q rows, NI = k+1 columns) and of their transposes.
+template <int N, int Q, typename Real>
+struct EOTab {
+    EOMat<Q, N, Real> S, D;
+    EOMat<N, Q, Real> St, Dt;
+};
+
 template <int N, typename Real>
 struct MTab {
     Real Sm[N][N];
