@@ -5,6 +5,8 @@
 Every translation unit is compiled with hipcc for gfx950 only; packed-FP32
 instructions are disabled for all device code.  Object files go to
 paper_1806_03095_amd/_build/, the library to paper_1806_03095_amd/libdgns.so.
+The compiler's per-kernel resource report (registers, spills, LDS) of each unit is
+kept beside its object file as <unit>.resources.txt.
 """
 
 import argparse
@@ -26,7 +28,7 @@ HIPCC = shutil.which("hipcc") or "/opt/rocm/bin/hipcc"
 FLAGS = ["--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC",
          "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
          "-I", os.path.join(ROOT, "include"), "-I", CSRC,
-         "-Wno-unused-command-line-argument"]
+         "-Wno-unused-command-line-argument", "-Rpass-analysis=kernel-resource-usage"]
 
 
 def _compile(src):
@@ -36,6 +38,8 @@ def _compile(src):
     r = subprocess.run(cmd, capture_output=True, text=True)
     if r.returncode != 0:
         raise RuntimeError("hipcc failed for %s:\n%s\n%s" % (src, " ".join(cmd), r.stderr[-6000:]))
+    with open(os.path.splitext(obj)[0] + ".resources.txt", "w") as f:
+        f.write(r.stderr)
     return obj
 
 

@@ -145,12 +145,16 @@ struct OpSizes {
 // of the three faces and the plan fits a compute unit.
 template <int N, int Q, typename Real>
 struct FaceBlock {
-    static constexpr int threads = Q <= 4 ? 64 : (3 * Q * Q <= 128 ? 128 : 256);
     static constexpr bool fused = N <= 4;
+    template <int B>
+    static constexpr int lds_for = (FaceSizes<N, Q, B, 3, fused>::TOTAL + 5 * N * N * N + 2 * Q * N + Q + 4 * N) *
+                                       (int)sizeof(Real) + 1024;
+    // 128 threads only while four workgroups fit in a compute unit's LDS (two waves per SIMD)
+    static constexpr int threads = Q <= 4 ? 64 : (3 * Q * Q <= 128 && lds_for<128> <= 40 * 1024 ? 128 : 256);
     using FS = FaceSizes<N, Q, threads, 3, fused>;
     using FS1 = FaceSizes<N, Q, threads, 1, fused>;
     static constexpr bool one_pass = 3 * Q * Q <= threads;
-    static constexpr int lds = (FS::TOTAL + 5 * N * N * N + 2 * Q * N + Q + 4 * N) * (int)sizeof(Real) + 1024;
+    static constexpr int lds = lds_for<threads>;
     static_assert(FS1::TOTAL <= FS::TOTAL, "single-face layout inside the three-face layout");
 };
 
@@ -1396,112 +1400,6 @@ dg_face_kernel(OpArgs a, KTab<N, Q, Real> tb) {
     }
 }
 
-// Standalone inverse mass, one x-line of one (component, cell) block per thread: the
-// workgroup's RPB blocks are one contiguous run of RPB N^3 values, which consecutive
-// threads load and store N values apiece (fully coalesced).  The sweep
-// along xi_0 runs in registers; the sweeps along xi_1 and xi_2 re-read the block from
-// LDS as lines of that axis, each thread writing back exactly the values it read, so
-// that one barrier per change of axis suffices (four in all).  In place allowed: a
-// workgroup reads all of its blocks before it writes them.
-constexpr int kMinvLineBlock = 256;
-
-template <int N, bool TRANS, typename Real>
-__device__ __forceinline__ void apply_line(const Real (&M)[N][N], Real (&v)[N]) {
-    Real t[N];
-#pragma unroll
-    for (int o = 0; o < N; ++o) {
-        Real acc = 0;
-#pragma unroll
-        for (int m = 0; m < N; ++m) acc += (TRANS ? M[m][o] : M[o][m]) * v[m];
-        t[o] = acc;
-    }
-#pragma unroll
-    for (int o = 0; o < N; ++o) v[o] = t[o];
-}
-
-template <int N, typename Real, bool GEN>
-__global__ void __launch_bounds__(kMinvLineBlock)
-inverse_mass_line_kernel(const double* R, double* L, int64_t ncell, const double* cell_metric,
-                         const double* mass_jxw, MTab<N, Real> mt) {
-    constexpr int N2 = N * N, N3 = N2 * N, RPB = kMinvLineBlock / N2;
-    __shared__ Real buf[RPB * N3];   // [block][a2][a1][a0]
-    __shared__ Real lwm[N];          // mass-rule weights, indexed per lane
-    const int tid = threadIdx.x;
-    if (tid < N) lwm[tid] = mt.wm[tid];
-    // the N x N table stays a kernel argument up to N = 7; for N = 8 it is read from
-    // an LDS copy (as a kernel argument the compiler keeps that one in scratch memory)
-    const MTab<N, Real>* tp = &mt;
-    if constexpr (N > 7) {
-        __shared__ MTab<N, Real> lmt;
-        copy_table<MTab<N, Real>, Real>(mt, lmt);
-        tp = &lmt;
-        __syncthreads();
-    }
-    const auto& Smi = tp->Smi;
-    const int lr = tid / N2, ln = tid % N2;   // local block, line within the block
-    const int64_t row = (int64_t)blockIdx.x * RPB + lr;   // row = c * ncell + e
-    const bool act = lr < RPB && row < 5 * ncell;
-    Real* blk = buf + lr * N3;
-    Real v[N];
-    // x-lines: line ln = a1 + N a2 holds a0 = 0..N-1
-    if (act) {
-        const double* src = R + row * N3 + ln * N;
-#pragma unroll
-        for (int m = 0; m < N; ++m) v[m] = (Real)src[m];
-        apply_line<N, true>(Smi, v);
-#pragma unroll
-        for (int m = 0; m < N; ++m) blk[ln * N + m] = v[m];
-    }
-    __syncthreads();
-    // y-lines: (a0, a2) = (ln % N, ln / N)
-    const int y0 = ln % N, y2 = ln / N;
-    if (act) {
-#pragma unroll
-        for (int m = 0; m < N; ++m) v[m] = blk[y2 * N2 + m * N + y0];
-        apply_line<N, true>(Smi, v);
-#pragma unroll
-        for (int m = 0; m < N; ++m) blk[y2 * N2 + m * N + y0] = v[m];
-    }
-    __syncthreads();
-    // z-lines: (a0, a1) = (ln % N, ln / N); scaling by 1 / (|J| w) at the mass points
-    const int z0 = ln % N, z1 = ln / N;
-    if (act) {
-#pragma unroll
-        for (int m = 0; m < N; ++m) v[m] = blk[m * N2 + z1 * N + z0];
-        apply_line<N, true>(Smi, v);
-        const int64_t e = row % ncell;
-        if constexpr (GEN) {
-            const double* jw = mass_jxw + e * N3 + z1 * N + z0;
-#pragma unroll
-            for (int m = 0; m < N; ++m) v[m] = v[m] / (Real)jw[m * N2];
-        } else {
-            const Real f = Real(1) / ((Real)cell_metric[e * 10 + 9] * lwm[z0] * lwm[z1]);
-#pragma unroll
-            for (int m = 0; m < N; ++m) v[m] = v[m] * (f / tp->wm[m]);
-        }
-        apply_line<N, false>(Smi, v);
-#pragma unroll
-        for (int m = 0; m < N; ++m) blk[m * N2 + z1 * N + z0] = v[m];
-    }
-    __syncthreads();
-    if (act) {
-#pragma unroll
-        for (int m = 0; m < N; ++m) v[m] = blk[y2 * N2 + m * N + y0];
-        apply_line<N, false>(Smi, v);
-#pragma unroll
-        for (int m = 0; m < N; ++m) blk[y2 * N2 + m * N + y0] = v[m];
-    }
-    __syncthreads();
-    if (act) {
-#pragma unroll
-        for (int m = 0; m < N; ++m) v[m] = blk[ln * N + m];
-        apply_line<N, false>(Smi, v);
-        double* dst = L + row * N3 + ln * N;
-#pragma unroll
-        for (int m = 0; m < N; ++m) dst[m] = (double)v[m];
-    }
-}
-
 // ------------------------------------------------------------------ launchers
 template <int N, int Q, typename Real>
 inline void fill_tables(const Tables1D& t, KTab<N, Q, Real>& kt, MTab<N, Real>& mt) {
@@ -1559,24 +1457,6 @@ inline int launch_op_t(const OpArgs& a, const Tables1D& t, hipStream_t st) {
 template <int N, int Q, typename Real>
 constexpr int64_t face_buffer_bytes_per_cell() {
     return OpBlock<N, Q, Real>::split ? (int64_t)6 * 2 * 5 * N * N * (int64_t)sizeof(Real) : 0;
-}
-
-template <int N, typename Real, bool GEN>
-inline int launch_minv_t(const double* R, double* L, int64_t ncell, const double* cm, const double* mj,
-                         const Tables1D& t, hipStream_t st) {
-    MTab<N, Real> mt;
-    for (int i = 0; i < N; ++i) {
-        for (int j = 0; j < N; ++j) {
-            mt.Sm[i][j] = (Real)t.Sm[i][j];
-            mt.Smi[i][j] = (Real)t.Smi[i][j];
-        }
-        mt.wm[i] = (Real)t.wm[i];
-    }
-    constexpr int RPB = kMinvLineBlock / (N * N);
-    const int64_t grid = (5 * ncell + RPB - 1) / RPB;
-    hipLaunchKernelGGL((inverse_mass_line_kernel<N, Real, GEN>), dim3((unsigned)grid), dim3(kMinvLineBlock), 0, st, R,
-                       L, ncell, cm, mj, mt);
-    return hipGetLastError() == hipSuccess ? 0 : -1;
 }
 
 }  // namespace dgns

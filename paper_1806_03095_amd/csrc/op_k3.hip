@@ -1,6 +1,7 @@
 // Operator (and adjoint) kernels of polynomial degree 3: the supported n_q values.
 #include "adj_impl.h"
 #include "diag_impl.h"
+#include "minv_impl.h"
 #include "dg_kernels.h"
 
 namespace dgns {

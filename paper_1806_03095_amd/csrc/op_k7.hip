@@ -1,6 +1,7 @@
 // Operator (and adjoint) kernels of polynomial degree 7: the supported n_q values.
 #include "op_impl.h"
 #include "diag_impl.h"
+#include "minv_impl.h"
 #include "dg_kernels.h"
 
 namespace dgns {

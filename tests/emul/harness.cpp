@@ -16,6 +16,7 @@
 
 #include "adj_impl.h"
 #include "diag_impl.h"
+#include "minv_impl.h"
 #include "setup.h"
 
 using namespace dgns;

@@ -18,6 +18,7 @@ def build():
     srcs = [os.path.join(EMU, "harness.cpp"), os.path.join(EMU, "hip", "hip_runtime.h"),
             os.path.join(CSRC, "setup.cpp"), os.path.join(CSRC, "setup.h"), os.path.join(CSRC, "op_impl.h"),
             os.path.join(CSRC, "adj_impl.h"), os.path.join(CSRC, "dg_adjoint.h"), os.path.join(CSRC, "diag_impl.h"),
+            os.path.join(CSRC, "minv_impl.h"),
             os.path.join(CSRC, "dg_common.h"), os.path.join(ROOT, "include", "dgns.h")]
     h = hashlib.sha1()
     for s in srcs:
@@ -31,11 +32,12 @@ def build():
     cmd = ["g++", "-std=c++17", "-O1", "-g", "-fsanitize=address,undefined", "-fno-sanitize-recover=all",
            "-fno-omit-frame-pointer", "-I", EMU, "-I", os.path.join(ROOT, "include"), "-I", CSRC,
            "-DEMU_CASES=" + cases, os.path.join(EMU, "harness.cpp"), os.path.join(CSRC, "setup.cpp"),
-           "-o", exe + ".tmp", "-lpthread"]
+           "-o", exe + ".tmp%d" % os.getpid(), "-lpthread"]
+    # a per-process temporary name: parallel test workers may build the same harness at once
     r = subprocess.run(cmd, capture_output=True, text=True)
     if r.returncode != 0:
         raise RuntimeError(r.stderr[-4000:])
-    os.replace(exe + ".tmp", exe)
+    os.replace(exe + ".tmp%d" % os.getpid(), exe)
     return exe
 
 

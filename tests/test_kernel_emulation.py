@@ -82,6 +82,8 @@ def test_emulated_channel_walls_and_force(k, nq):
     ((3, 2, 2), 1, 2, 0, 0.0, "LGL", 0),
     ((2, 2, 2), 2, 3, 2, 0.15, "GL", 0),
     ((3, 1, 2), 3, 6, 0, 0.0, "LGL", 0),
+    # 240 blocks: seven full workgroups of 32 blocks and a ragged eighth
+    ((4, 4, 3), 3, 6, 0, 0.0, "LGL", 0),
     ((1, 2, 2), 3, 6, 2, 0.1, "GL", 1),
     ((2, 1, 1), 4, 7, 2, 0.1, "LGL", 0),
     ((2, 1, 1), 7, 11, 0, 0.0, "LGL", 0),
