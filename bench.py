@@ -51,7 +51,7 @@ CR_STUDY = 0.25
 # diffusion number: the paper's ratio to the critical one (D = 0.02 against 0.036), 0.56 x 0.020;
 # at Re = 1600 the viscous restriction does not bind either way
 D_RUN = 0.011
-MEASURED_TRAFFIC = {"fingerprint": "6a0b39fc83ff80b0", "workload": (32, 3, 6), "bytes": 862692761.6}
+MEASURED_TRAFFIC = {"fingerprint": "6a0b39fc83ff80b0", "workload": (32, 3, 6), "bytes": 862696038.4}
 
 
 def kernel_fingerprint():
@@ -252,7 +252,8 @@ def degree_sweep(target_dofs=10_000_000, calls=20):
     quadrature point (the paper's Cartesian versus deformed comparison, Sec. 5.1.1)."""
     import torch
     from paper_1806_03095_amd import taylor_green
-    qs = {1: (2, 3), 2: (3, 4, 5), 3: (4, 5, 6, 7), 4: (5, 6, 7, 9), 5: (6, 8), 6: (7, 10), 7: (8, 11)}
+    qs = {1: (2, 3), 2: (3, 4, 5), 3: (4, 5, 6, 7), 4: (5, 6, 7, 9), 5: (6, 8), 6: (7, 10), 7: (8, 11),
+          8: (9, 13), 9: (10, 14), 10: (11, 16), 11: (12,), 12: (13,), 13: (14,), 14: (15,), 15: (16,)}
     rows = []
     for k, nqs in qs.items():
         ne = max(2, int(round((target_dofs / (5.0 * (k + 1) ** 3)) ** (1.0 / 3.0))))

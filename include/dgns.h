@@ -70,8 +70,11 @@ typedef struct dgns_ctx dgns_ctx;
 
 /* Discretisation and fluid parameters (Sec. 2.1, 2.2). */
 typedef struct dgns_params {
-    int degree;            /* polynomial degree k, 1..7 */
-    int n_q;               /* Gauss points per direction for the flux integrals */
+    int degree;            /* polynomial degree k, 1..15 */
+    int n_q;               /* Gauss points per direction for the flux integrals; compiled
+                            * pairs: k = 1..7 with n_q = k+1, the 3/2 rule floor((3k+2)/2)
+                            * and 2k+1 for k <= 4; k = 8..15 with n_q = k+1, and the 3/2
+                            * rule for k <= 10 (other pairs: DGNS_EUNSUPPORTED) */
     int basis;             /* DGNS_BASIS_* */
     int precision;         /* DGNS_FP64 or DGNS_FP32 */
     double gamma;          /* ratio of specific heats */
@@ -102,7 +105,12 @@ const char* dgns_last_error(void);
 /* Builds the mesh, the metric terms at every quadrature point (Sec. 2.2.3, eq.
  * IntegralsReferenceSpace), the penalty tau_IP per face (eq. TauIP_Element), and
  * uploads them.  stream: a hipStream_t (NULL = the default stream).  Synchronous.
- * Fails with DGNS_EINVAL if the mapping folds (det J <= 0 at a quadrature point). */
+ * Fails with DGNS_EINVAL if the mapping folds (det J <= 0 at a quadrature point).
+ * Degrees 8..15 stream each cell through the kernels plane by plane (its coefficients
+ * and residual no longer fit on chip); they provide the operator, the residual, the
+ * inverse mass, the Runge-Kutta step and stage update, the time step and the initial
+ * projection, and return DGNS_EUNSUPPORTED for a nonzero body force (at creation) and
+ * from the diagnostics, channel statistics and adjoint entry points. */
 int dgns_create(const dgns_params* params, const dgns_box_mesh* mesh, void* stream, dgns_ctx** out);
 
 /* Releases everything the context owns.  Synchronises its stream first.  NULL is a no-op. */

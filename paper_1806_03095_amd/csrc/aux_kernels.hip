@@ -63,6 +63,30 @@ int launch_rk_update(double* U, double* dU, const double* L, int64_t n, double A
     return hipGetLastError() == hipSuccess ? 0 : -1;
 }
 
+// dU <- A dU + dt L;  U_out <- U_in + B dU, with L possibly aliasing U_out (each entry of
+// L is read before the same entry of U_out is written, by the same thread).
+__global__ void __launch_bounds__(256) rk_update_to_kernel(const double* U_in, double* U_out, double* dU,
+                                                           const double* L, int64_t n, double A, double B,
+                                                           double dt, int first) {
+    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += stride) {
+        const double l = L[i];
+        const double d = rk_increment(first != 0, A, first ? 0.0 : dU[i], dt, l);
+        dU[i] = d;
+        U_out[i] = rk_advance(U_in[i], B, d);
+    }
+}
+
+int launch_rk_update_to(const double* U_in, double* U_out, double* dU, const double* L, int64_t n, double A, double B,
+                        double dt, hipStream_t st) {
+    if (n <= 0) return 0;
+    int64_t blocks = (n + 255) / 256;
+    if (blocks > 256 * 64) blocks = 256 * 64;
+    hipLaunchKernelGGL(rk_update_to_kernel, dim3((unsigned)blocks), dim3(256), 0, st, U_in, U_out, dU, L, n, A, B, dt,
+                       A == 0.0 ? 1 : 0);
+    return hipGetLastError() == hipSuccess ? 0 : -1;
+}
+
 // ------------------------------------------------------------------ diagnostics
 // Totals of the nine per-cell partial sums that diag_kernel (diag_impl.h) writes:
 // [0] int |u|^2/2, [1] int grad u : grad u, [2] -int u.(L_m - u L_rho)/rho,
@@ -175,46 +199,55 @@ __device__ inline void initial_state(int ic, const double* q, double gamma, doub
 }
 
 // out_i = sum_p phi_i(x_p) |det J| w_p U0(x(x_p)) with the n_q rule (before M^{-1}).
+// The components go in passes of cp (all five where their [cp][Q^3] point values fit
+// the dynamic LDS, fewer at the largest n_q); the point values are recomputed per pass.
 __global__ void __launch_bounds__(256) ic_rhs_kernel(OpArgs a, const Tables1D* __restrict__ tp, const double* geo, int ic,
-                                                     const double* icp_d, double* out, int gen) {
-    extern __shared__ double sv[];   // [5][Q^3]
+                                                     const double* icp_d, double* out, int gen, int cp) {
+    extern __shared__ double sv[];   // [cp][Q^3]
     const Tables1D& t = *tp;
     const int N = t.n, Q = t.q, N3 = N * N * N, Q3 = Q * Q * Q;
     const int64_t e = blockIdx.x;
+    const int64_t cs = a.ncell * N3;
     double q[8];
     for (int m = 0; m < 8; ++m) q[m] = icp_d[m];
-    for (int p = threadIdx.x; p < Q3; p += blockDim.x) {
-        const int p0 = p % Q, p1 = (p / Q) % Q, p2 = p / (Q * Q);
-        double x[3] = {0, 0, 0};
-        for (int i = 0; i < N3; ++i) {
-            const int a0 = i % N, a1 = (i / N) % N, a2 = i / (N * N);
-            const double g = t.Sg[p0][a0] * t.Sg[p1][a1] * t.Sg[p2][a2];
-            for (int c = 0; c < 3; ++c) x[c] += g * geo[(e * 3 + c) * N3 + i];
-        }
-        double U[5];
-        initial_state(ic, q, a.gamma, a.R, x, U);
-        const double jxw = gen ? a.cell_metric[(e * 10 + 9) * Q3 + p] : a.cell_metric[e * 10 + 9] * t.w[p0] * t.w[p1] * t.w[p2];
-        for (int c = 0; c < 5; ++c) sv[c * Q3 + p] = U[c] * jxw;
-    }
-    __syncthreads();
-    const int64_t cs = a.ncell * N3;
-    for (int it = threadIdx.x; it < 5 * N3; it += blockDim.x) {
-        const int c = it / N3, i = it % N3;
-        const int a0 = i % N, a1 = (i / N) % N, a2 = i / (N * N);
-        double s = 0;
-        for (int p = 0; p < Q3; ++p) {
+    for (int c0 = 0; c0 < 5; c0 += cp) {
+        const int nc = 5 - c0 < cp ? 5 - c0 : cp;
+        for (int p = threadIdx.x; p < Q3; p += blockDim.x) {
             const int p0 = p % Q, p1 = (p / Q) % Q, p2 = p / (Q * Q);
-            s += t.S[p0][a0] * t.S[p1][a1] * t.S[p2][a2] * sv[c * Q3 + p];
+            double x[3] = {0, 0, 0};
+            for (int i = 0; i < N3; ++i) {
+                const int a0 = i % N, a1 = (i / N) % N, a2 = i / (N * N);
+                const double g = t.Sg[p0][a0] * t.Sg[p1][a1] * t.Sg[p2][a2];
+                for (int c = 0; c < 3; ++c) x[c] += g * geo[(e * 3 + c) * N3 + i];
+            }
+            double U[5];
+            initial_state(ic, q, a.gamma, a.R, x, U);
+            const double jxw =
+                gen ? a.cell_metric[(e * 10 + 9) * Q3 + p] : a.cell_metric[e * 10 + 9] * t.w[p0] * t.w[p1] * t.w[p2];
+            for (int c = 0; c < nc; ++c) sv[c * Q3 + p] = U[c0 + c] * jxw;
         }
-        out[c * cs + e * N3 + i] = s;
+        __syncthreads();
+        for (int it = threadIdx.x; it < nc * N3; it += blockDim.x) {
+            const int c = it / N3, i = it % N3;
+            const int a0 = i % N, a1 = (i / N) % N, a2 = i / (N * N);
+            double s = 0;
+            for (int p = 0; p < Q3; ++p) {
+                const int p0 = p % Q, p1 = (p / Q) % Q, p2 = p / (Q * Q);
+                s += t.S[p0][a0] * t.S[p1][a1] * t.S[p2][a2] * sv[c * Q3 + p];
+            }
+            out[(c0 + c) * cs + e * N3 + i] = s;
+        }
+        __syncthreads();
     }
 }
 
 int launch_ic_rhs(const OpArgs& a, const Tables1D& t, const Tables1D* t_dev, const double* geo_nodes, int ic,
                   const double* icp, double* out, bool gen, hipStream_t st) {
-    const size_t shm = sizeof(double) * 5 * t.q * t.q * t.q;
-    hipLaunchKernelGGL(ic_rhs_kernel, dim3((unsigned)a.ncell), dim3(256), shm, st, a, t_dev, geo_nodes, ic, icp, out,
-                       gen ? 1 : 0);
+    const size_t per = sizeof(double) * t.q * t.q * t.q;
+    int cp = (int)((64 * 1024) / per);
+    cp = cp < 1 ? 1 : (cp > 5 ? 5 : cp);
+    hipLaunchKernelGGL(ic_rhs_kernel, dim3((unsigned)a.ncell), dim3(256), per * cp, st, a, t_dev, geo_nodes, ic, icp,
+                       out, gen ? 1 : 0, cp);
     return hipGetLastError() == hipSuccess ? 0 : -1;
 }
 

@@ -12,8 +12,8 @@
 
 namespace dgns {
 
-constexpr int kMaxN = 8;    // nodes per direction, k <= 7
-constexpr int kMaxQ = 12;   // quadrature points per direction
+constexpr int kMaxN = 16;   // nodes per direction, k <= 15
+constexpr int kMaxQ = 16;   // quadrature points per direction
 constexpr int kBlock = 128; // threads per workgroup of the cell kernels
 
 // 1D tables of one (k, n_q, basis) combination, float64 master copy.
@@ -116,6 +116,9 @@ struct OpArgs {
     // lifts both sides' face terms; the cell kernel gathers its six): per cell and face
     // slot d + 3 s, [2][5][(k+1)^2] values in the operator's working precision
     void* fw;
+    // device copy of the context's 1D tables (read by the kernels of degree >= 8, whose
+    // tables would not fit in the kernel arguments)
+    const Tables1D* tab_dev;
 };
 
 template <typename Real>

@@ -42,8 +42,24 @@ int launch_adjoint_k7(const OpArgs& a, const double* Rb, const Tables1D& t, bool
 constexpr int kSupported[][2] = {{1, 2}, {1, 3}, {2, 3}, {2, 4}, {2, 5}, {3, 4}, {3, 5}, {3, 6}, {3, 7}, {4, 5},
                                  {4, 6}, {4, 7}, {4, 9}, {5, 6}, {5, 8}, {6, 7}, {6, 10}, {7, 8}, {7, 11}};
 
+// Degrees 8..15 (hd_impl.h: the cell streamed through LDS plane by plane): n_q = k+1, and
+// the 3/2 rule where its n_q^2 face points fit one pass of 256 threads (k <= 10).
+constexpr int kSupportedHd[][2] = {{8, 9},  {8, 13},  {9, 10},  {9, 14},  {10, 11}, {10, 16},
+                                   {11, 12}, {12, 13}, {13, 14}, {14, 15}, {15, 16}};
+int launch_operator_hd1(const OpArgs& a, int k, int q, bool fp32, bool gen, hipStream_t st);   // k = 8..11
+int launch_operator_hd2(const OpArgs& a, int k, int q, bool fp32, bool gen, hipStream_t st);   // k = 12..15
+int launch_inverse_mass_hd1(const double* R, double* L, int64_t ncell, const double* cm, const double* mj,
+                            const Tables1D* t_dev, int k, bool fp32, bool gen, hipStream_t st);
+int launch_inverse_mass_hd2(const double* R, double* L, int64_t ncell, const double* cm, const double* mj,
+                            const Tables1D* t_dev, int k, bool fp32, bool gen, hipStream_t st);
+
 // LSRK stage update dU <- A dU + dt L; U <- U + B dU (A == 0: dU <- dt L).
 int launch_rk_update(double* U, double* dU, const double* L, int64_t n, double A, double B, double dt, hipStream_t st);
+
+// The same update into another buffer: dU <- A dU + dt L; U_out <- U_in + B dU.  L may
+// alias U_out (each entry is read before it is written).
+int launch_rk_update_to(const double* U_in, double* U_out, double* dU, const double* L, int64_t n, double A, double B,
+                        double dt, hipStream_t st);
 
 // Per-cell diagnostic partial sums (nine per cell, see diag_impl.h), float64.
 int launch_diagnostics_k1(const OpArgs& a, const Tables1D& t, const double* L, double* partial, bool gen, hipStream_t st);

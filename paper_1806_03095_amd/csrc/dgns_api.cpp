@@ -161,6 +161,7 @@ OpArgs make_args(const dgns_ctx* c, const double* U, double* out, unsigned terms
     a.terms = terms;
     a.fuse_minv = fuse;
     a.fw = c->d_fw;
+    a.tab_dev = c->d_tab;
     return a;
 }
 
@@ -174,6 +175,8 @@ int dispatch_operator(const dgns_ctx* c, const OpArgs& a) {
         case 5: rc = launch_operator_k5(a, c->tab, c->fp32, c->gen, c->stream); break;
         case 6: rc = launch_operator_k6(a, c->tab, c->fp32, c->gen, c->stream); break;
         case 7: rc = launch_operator_k7(a, c->tab, c->fp32, c->gen, c->stream); break;
+        case 8: case 9: case 10: case 11: rc = launch_operator_hd1(a, c->k, c->q, c->fp32, c->gen, c->stream); break;
+        case 12: case 13: case 14: case 15: rc = launch_operator_hd2(a, c->k, c->q, c->fp32, c->gen, c->stream); break;
     }
     if (rc == 1) return fail(DGNS_EUNSUPPORTED, "no operator kernel for degree %d, n_q %d", c->k, c->q);
     if (rc != 0) return fail(DGNS_EHIP, "operator launch failed: %s", hipGetErrorString(hipGetLastError()));
@@ -192,6 +195,12 @@ int dispatch_minv(const dgns_ctx* c, const double* R, double* L) {
         case 5: rc = launch_inverse_mass_k5(R, L, c->ncell, cm, mj, c->tab, c->fp32, c->gen, c->stream); break;
         case 6: rc = launch_inverse_mass_k6(R, L, c->ncell, cm, mj, c->tab, c->fp32, c->gen, c->stream); break;
         case 7: rc = launch_inverse_mass_k7(R, L, c->ncell, cm, mj, c->tab, c->fp32, c->gen, c->stream); break;
+        case 8: case 9: case 10: case 11:
+            rc = launch_inverse_mass_hd1(R, L, c->ncell, cm, mj, c->d_tab, c->k, c->fp32, c->gen, c->stream);
+            break;
+        case 12: case 13: case 14: case 15:
+            rc = launch_inverse_mass_hd2(R, L, c->ncell, cm, mj, c->d_tab, c->k, c->fp32, c->gen, c->stream);
+            break;
     }
     if (rc == 1) return fail(DGNS_EUNSUPPORTED, "no inverse-mass kernel for degree %d", c->k);
     if (rc != 0) return fail(DGNS_EHIP, "inverse-mass launch failed: %s", hipGetErrorString(hipGetLastError()));
@@ -269,7 +278,7 @@ const char* dgns_last_error(void) { return g_err.c_str(); }
 int dgns_create(const dgns_params* prm, const dgns_box_mesh* msh, void* stream, dgns_ctx** out) {
     if (!prm || !msh || !out) return fail(DGNS_EINVAL, "null argument");
     *out = nullptr;
-    if (prm->degree < 1 || prm->degree > 7) return fail(DGNS_EINVAL, "degree %d outside 1..7", prm->degree);
+    if (prm->degree < 1 || prm->degree > 15) return fail(DGNS_EINVAL, "degree %d outside 1..15", prm->degree);
     if (prm->n_q < 1 || prm->n_q > kMaxQ) return fail(DGNS_EINVAL, "n_q %d outside 1..%d", prm->n_q, kMaxQ);
     if (prm->basis != DGNS_BASIS_LGL && prm->basis != DGNS_BASIS_GL) return fail(DGNS_EINVAL, "unknown basis");
     if (prm->precision != DGNS_FP64 && prm->precision != DGNS_FP32) return fail(DGNS_EINVAL, "unknown precision");
@@ -286,7 +295,10 @@ int dgns_create(const dgns_params* prm, const dgns_box_mesh* msh, void* stream, 
     if (ncell > 2147483647LL) return fail(DGNS_EINVAL, "too many cells");
     bool ok = false;
     for (const auto& kq : kSupported) ok |= (kq[0] == prm->degree && kq[1] == prm->n_q);
+    for (const auto& kq : kSupportedHd) ok |= (kq[0] == prm->degree && kq[1] == prm->n_q);
     if (!ok) return fail(DGNS_EUNSUPPORTED, "no kernel for degree %d with n_q %d", prm->degree, prm->n_q);
+    if (prm->degree >= 8 && (prm->body_force[0] != 0 || prm->body_force[1] != 0 || prm->body_force[2] != 0))
+        return fail(DGNS_EUNSUPPORTED, "body forces are supported for degrees up to 7");
 
     dgns_ctx* c = new dgns_ctx();
     rk_default(c);

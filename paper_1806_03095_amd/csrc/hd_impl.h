@@ -1,0 +1,420 @@
+// High-degree operator kernels (k >= 8): the same weak form, sum factorisation and face
+// terms as op_impl.h, for cells too large to hold in LDS.
+//
+// At k >= 8 one cell's coefficients and residual alone take 10 (k+1)^3 values (58 KB at
+// k = 8, 328 KB at k = 15 in float64), so the resident design of op_impl.h (sU and sR in
+// LDS beside the work area) no longer fits a compute unit's 160 KB.  Here a workgroup
+// still evaluates one cell, but streams it through the quadrature planes along xi_2:
+//  - per chunk of PL planes, the z-interpolation reads the coefficient lines of U from
+//    global memory (they stay in the L2 / last-level cache across the chunks);
+//  - the chunk's intermediates live in LDS in two regions that alternate between the
+//    phases (z-swept values, then point fluxes, then y-transposed sums in region A;
+//    y-swept values, then x-transposed sums in region B);
+//  - the z-transposed test sweep accumulates into the cell's own rows of the output
+//    vector (each entry owned by one thread of one workgroup: no atomics), which the
+//    face terms then complete; M^{-1} is the stand-alone kernel applied afterwards.
+// The face terms are evaluated once per face by dg_face_hd_kernel (one face of the cell
+// at a time, own traces read from global memory) into the face buffer, as for the
+// lower degrees.  The 1D tables come from the context's device copy of Tables1D (as
+// kernel arguments they would exceed the argument space) into LDS.  Body forces are not
+// supported at these degrees (the API rejects them).
+#pragma once
+
+#include "dg_kernels.h"
+#include "minv_impl.h"
+
+namespace dgns {
+
+constexpr int kHdBlock = 256;
+
+// Cooperative copy of the 1D tables of (N, Q) from the float64 master into LDS.
+template <int N, int Q, typename Real>
+__device__ __forceinline__ void load_ktab(const Tables1D* t, KTab<N, Q, Real>& lt) {
+    for (int i = threadIdx.x; i < Q * N; i += blockDim.x) {
+        const int p = i / N, j = i % N;
+        lt.S[p][j] = (Real)t->S[p][j];
+        lt.D[p][j] = (Real)t->D[p][j];
+    }
+    for (int i = threadIdx.x; i < Q; i += blockDim.x) lt.w[i] = (Real)t->w[i];
+    for (int i = threadIdx.x; i < 2 * N; i += blockDim.x) {
+        lt.fv[i / N][i % N] = (Real)t->fv[i / N][i % N];
+        lt.fd[i / N][i % N] = (Real)t->fd[i / N][i % N];
+    }
+}
+
+// LDS plan of the streamed cell kernel: PL planes per chunk, as many as keep the two
+// regions within about 60 KB (two workgroups, eight waves, per compute unit).
+template <int N, int Q, typename Real>
+struct HdPlan {
+    static constexpr int RS = (int)sizeof(Real);
+    static constexpr int per_plane(int p) { return 15 * p * Q * (Q + N); }
+    static constexpr int fit(int p) { return p <= 1 ? 1 : (per_plane(p) * RS <= 60 * 1024 ? p : fit(p - 1)); }
+    static constexpr int PL = fit(Q);
+    static constexpr int RA = 15 * PL * Q * Q;   // z-swept [2][5][PL][N^2], fluxes [5][3][PL][Q^2], E [2][5][PL][N^2]
+    static constexpr int RB = 15 * PL * Q * N;   // y-swept [3][5][PL][Q][N], x-transposed [3][5][PL][Q][N]
+    static_assert(Q >= N, "n_q >= k + 1");
+};
+
+// Cell term of the residual, streamed over the quadrature planes along xi_2 (see the
+// file comment); then the six lifted face blocks of the face buffer.  Writes R to a.out.
+template <int N, int Q, typename Real, bool GEN>
+__global__ void __launch_bounds__(kHdBlock) __attribute__((amdgpu_waves_per_eu(2)))
+dg_cell_hd_kernel(OpArgs a) {
+    using HP = HdPlan<N, Q, Real>;
+    constexpr int PL = HP::PL;
+    constexpr int N2 = N * N, N3 = N2 * N, Q2 = Q * Q, Q3 = Q2 * Q, FWB = 2 * 5 * N2;
+    __shared__ Real rA[HP::RA];
+    __shared__ Real rB[HP::RB];
+    __shared__ KTab<N, Q, Real> lt;
+    const int64_t e = blockIdx.x;
+    const int tid = threadIdx.x, nth = blockDim.x;
+    const Phys<Real> ph = make_phys<Real>(a);
+    const bool conv = (a.terms & 1u) != 0;
+    const bool visc = (a.terms & 2u) != 0;
+    const int64_t cstride = a.ncell * N3;
+    const double* Ue = a.U + e * N3;
+    double* Re = a.out + e * N3;
+    load_ktab<N, Q, Real>(a.tab_dev, lt);
+    Real Ji[9], detJ = Real(1);
+    if constexpr (!GEN) {
+#pragma unroll
+        for (int m = 0; m < 9; ++m) Ji[m] = (Real)a.cell_metric[e * 10 + m];
+        detJ = (Real)a.cell_metric[e * 10 + 9];
+    }
+    __syncthreads();
+
+    const bool cell = conv || visc;
+    for (int pz0 = 0; cell && pz0 < Q; pz0 += PL) {
+        const int np = Q - pz0 < PL ? Q - pz0 : PL;
+        // z-sweep: Z0 = S_z U, Z1 = D_z U for the chunk's planes   rA [kind][c][pl][a1][a0]
+        for (int it = tid; it < 5 * N2; it += nth) {
+            const int c = it / N2, r = it % N2;
+            Real v[N];
+#pragma unroll
+            for (int i = 0; i < N; ++i) v[i] = (Real)Ue[c * cstride + i * N2 + r];
+            for (int pl = 0; pl < np; ++pl) {
+                Real z0 = 0, z1 = 0;
+#pragma unroll
+                for (int i = 0; i < N; ++i) {
+                    z0 += lt.S[pz0 + pl][i] * v[i];
+                    z1 += lt.D[pz0 + pl][i] * v[i];
+                }
+                rA[((0 * 5 + c) * PL + pl) * N2 + r] = z0;
+                rA[((1 * 5 + c) * PL + pl) * N2 + r] = z1;
+            }
+        }
+        __syncthreads();
+        // y-sweep: Y00 = S_y Z0, Y10 = D_y Z0, Y01 = S_y Z1   rB [kind][c][pl][py][a0]
+        for (int it = tid; it < 5 * np * Q * N; it += nth) {
+            const int a0 = it % N, py = (it / N) % Q, pl = (it / (N * Q)) % np, c = it / (N * Q * np);
+            const Real* z0p = rA + ((0 * 5 + c) * PL + pl) * N2 + a0;
+            const Real* z1p = rA + ((1 * 5 + c) * PL + pl) * N2 + a0;
+            Real y00 = 0, y10 = 0, y01 = 0;
+#pragma unroll
+            for (int i = 0; i < N; ++i) {
+                const Real z0 = z0p[i * N], z1 = z1p[i * N];
+                y00 += lt.S[py][i] * z0;
+                y10 += lt.D[py][i] * z0;
+                y01 += lt.S[py][i] * z1;
+            }
+            rB[((0 * 5 + c) * PL + pl) * Q * N + py * N + a0] = y00;
+            rB[((1 * 5 + c) * PL + pl) * Q * N + py * N + a0] = y10;
+            rB[((2 * 5 + c) * PL + pl) * Q * N + py * N + a0] = y01;
+        }
+        __syncthreads();
+        // x-sweep and pointwise physics, one point per item   rA [c][dim][pl][py][px]
+        for (int it = tid; it < np * Q2; it += nth) {
+            const int px = it % Q, py = (it / Q) % Q, pl = it / Q2, pz = pz0 + pl;
+            Real Uq[5], Gr[5][3];
+#pragma unroll
+            for (int c = 0; c < 5; ++c) {
+                const Real* y00p = rB + ((0 * 5 + c) * PL + pl) * Q * N + py * N;
+                const Real* y10p = rB + ((1 * 5 + c) * PL + pl) * Q * N + py * N;
+                const Real* y01p = rB + ((2 * 5 + c) * PL + pl) * Q * N + py * N;
+                Real v = 0, dx = 0, dy = 0, dz = 0;
+#pragma unroll 4
+                for (int i = 0; i < N; ++i) {
+                    v += lt.S[px][i] * y00p[i];
+                    dx += lt.D[px][i] * y00p[i];
+                    dy += lt.S[px][i] * y10p[i];
+                    dz += lt.S[px][i] * y01p[i];
+                }
+                Uq[c] = v;
+                Gr[c][0] = dx;
+                Gr[c][1] = dy;
+                Gr[c][2] = dz;
+            }
+            Real J[9], jxw;
+            if constexpr (GEN) {
+                const double* gm = a.cell_metric + e * 10 * Q3 + px + Q * (py + Q * pz);
+#pragma unroll
+                for (int m = 0; m < 9; ++m) J[m] = (Real)gm[m * Q3];
+                jxw = (Real)gm[9 * Q3];
+            } else {
+#pragma unroll
+                for (int m = 0; m < 9; ++m) J[m] = Ji[m];
+                jxw = detJ * lt.w[px] * lt.w[py] * lt.w[pz];
+            }
+            const Prim<Real> sq = primitives(Uq, ph);
+            Real F[5][3];
+            if (conv) {
+                convective_flux(Uq, sq, F);
+            } else {
+#pragma unroll
+                for (int c = 0; c < 5; ++c)
+#pragma unroll
+                    for (int j = 0; j < 3; ++j) F[c][j] = 0;
+            }
+            if (visc) {
+#pragma unroll
+                for (int c = 0; c < 5; ++c) {
+                    const Real g0 = Gr[c][0], g1 = Gr[c][1], g2 = Gr[c][2];
+#pragma unroll
+                    for (int j = 0; j < 3; ++j) Gr[c][j] = J[0 * 3 + j] * g0 + J[1 * 3 + j] * g1 + J[2 * 3 + j] * g2;
+                }
+                subtract_viscous_flux(sq, Gr, ph, F);
+            }
+#pragma unroll
+            for (int c = 0; c < 5; ++c)
+#pragma unroll
+                for (int d = 0; d < 3; ++d) {
+                    const Real fr = J[d * 3 + 0] * F[c][0] + J[d * 3 + 1] * F[c][1] + J[d * 3 + 2] * F[c][2];
+                    rA[((c * 3 + d) * PL + pl) * Q2 + py * Q + px] = jxw * fr;
+                }
+        }
+        __syncthreads();
+        // x-transposed: B1 = D_x^T F_0, B2 = S_x^T F_1, B3 = S_x^T F_2   rB [kind][c][pl][py][a0]
+        for (int it = tid; it < 5 * np * Q * N; it += nth) {
+            const int a0 = it % N, py = (it / N) % Q, pl = (it / (N * Q)) % np, c = it / (N * Q * np);
+            const Real* f0 = rA + ((c * 3 + 0) * PL + pl) * Q2 + py * Q;
+            const Real* f1 = rA + ((c * 3 + 1) * PL + pl) * Q2 + py * Q;
+            const Real* f2 = rA + ((c * 3 + 2) * PL + pl) * Q2 + py * Q;
+            Real b1 = 0, b2 = 0, b3 = 0;
+#pragma unroll
+            for (int px = 0; px < Q; ++px) {
+                b1 += lt.D[px][a0] * f0[px];
+                b2 += lt.S[px][a0] * f1[px];
+                b3 += lt.S[px][a0] * f2[px];
+            }
+            rB[((0 * 5 + c) * PL + pl) * Q * N + py * N + a0] = b1;
+            rB[((1 * 5 + c) * PL + pl) * Q * N + py * N + a0] = b2;
+            rB[((2 * 5 + c) * PL + pl) * Q * N + py * N + a0] = b3;
+        }
+        __syncthreads();
+        // y-transposed: E1 = S_y^T B1 + D_y^T B2, E2 = S_y^T B3   rA [kind][c][pl][a1][a0]
+        for (int it = tid; it < 5 * np * N2; it += nth) {
+            const int a0 = it % N, a1 = (it / N) % N, pl = (it / N2) % np, c = it / (N2 * np);
+            const Real* b1 = rB + ((0 * 5 + c) * PL + pl) * Q * N + a0;
+            const Real* b2 = rB + ((1 * 5 + c) * PL + pl) * Q * N + a0;
+            const Real* b3 = rB + ((2 * 5 + c) * PL + pl) * Q * N + a0;
+            Real e1 = 0, e2 = 0;
+#pragma unroll
+            for (int py = 0; py < Q; ++py) {
+                e1 += lt.S[py][a1] * b1[py * N] + lt.D[py][a1] * b2[py * N];
+                e2 += lt.S[py][a1] * b3[py * N];
+            }
+            rA[((0 * 5 + c) * PL + pl) * N2 + a1 * N + a0] = e1;
+            rA[((1 * 5 + c) * PL + pl) * N2 + a1 * N + a0] = e2;
+        }
+        __syncthreads();
+        // z-transposed into the cell's rows of the output: R (+)= S_z^T E1 + D_z^T E2
+        for (int it = tid; it < 5 * N3; it += nth) {
+            const int c = it / N3, r = it % N3, a2 = r / N2, r2 = r % N2;
+            Real acc = 0;
+            for (int pl = 0; pl < np; ++pl)
+                acc += lt.S[pz0 + pl][a2] * rA[((0 * 5 + c) * PL + pl) * N2 + r2] +
+                       lt.D[pz0 + pl][a2] * rA[((1 * 5 + c) * PL + pl) * N2 + r2];
+            double* rp = Re + c * cstride + r;
+            *rp = pz0 == 0 ? (double)acc : *rp + (double)acc;
+        }
+        // the next chunk's z-sweep overwrites rA
+        __syncthreads();
+    }
+
+    // the six lifted face blocks: R(a, b, m) += W0 l_m(s) + W1 l_m'(s) along each face's normal
+    const Real* fw = static_cast<const Real*>(a.fw) + e * 6 * FWB;
+    for (int it = tid; it < 5 * N3; it += nth) {
+        const int c = it / N3, r = it % N3;
+        const int x0 = r % N, x1 = (r / N) % N, x2 = r / N2;
+        Real acc = 0;
+        if (cell) {
+#pragma unroll
+            for (int s = 0; s < 2; ++s) {
+                const Real* w = fw + 3 * s * FWB + c * N2;
+                acc += w[0 * FWB + x2 * N + x1] * lt.fv[s][x0] + w[0 * FWB + 5 * N2 + x2 * N + x1] * lt.fd[s][x0];
+                acc += w[1 * FWB + x2 * N + x0] * lt.fv[s][x1] + w[1 * FWB + 5 * N2 + x2 * N + x0] * lt.fd[s][x1];
+                acc += w[2 * FWB + x1 * N + x0] * lt.fv[s][x2] + w[2 * FWB + 5 * N2 + x1 * N + x0] * lt.fd[s][x2];
+            }
+        }
+        double* rp = Re + c * cstride + r;
+        *rp = cell ? *rp + (double)acc : 0.0;
+    }
+}
+
+// Face terms once per face (see dg_face_kernel in op_impl.h), one face of the cell at a
+// time so that the traces of both sides fit in LDS; the cell's own traces come from
+// global memory.  One face point per thread: n_q^2 <= 256.
+template <int N, int Q, typename Real, bool GEN>
+__global__ void __launch_bounds__(kHdBlock)
+dg_face_hd_kernel(OpArgs a) {
+    using FS = FaceSizes<N, Q, kHdBlock, 1, false>;
+    constexpr int N2 = N * N, Q2 = Q * Q, FWB = 2 * 5 * N2;
+    static_assert(FS::ALIAS, "one face point per thread");
+    __shared__ Real sW[FS::TOTAL];
+    __shared__ FaceInfo fi;
+    __shared__ Real sTau[6];
+    __shared__ Real sFn[12];
+    __shared__ Real sJr[GEN ? 1 : 27];
+    __shared__ KTab<N, Q, Real> lt;
+
+    const int64_t e = blockIdx.x;
+    const int tid = threadIdx.x;
+    const Phys<Real> ph = make_phys<Real>(a);
+    const bool conv = (a.terms & 1u) != 0;
+    const bool visc = (a.terms & 2u) != 0;
+    Real* fw = static_cast<Real*>(a.fw);
+    load_ktab<N, Q, Real>(a.tab_dev, lt);
+    face_info_setup<Real, GEN>(a, e, fi, sTau, sFn, sJr);
+    Real detJ = Real(1);
+    if constexpr (!GEN) detJ = (Real)a.cell_metric[e * 10 + 9];
+    __syncthreads();
+
+    Real* out = sW + FS::OUT_OFF;
+    Real* t1 = sW + FS::T1_OFF;
+    Real* o = out + tid;
+    const bool act = tid < Q2;
+    Real res[20], res1[15];
+    // the faces xi_d = 1, both sides
+#pragma unroll 1
+    for (int d = 0; d < 3; ++d) {
+        face_traces_sweep<N, Q, Real, 1, FS, true>(a, lt, 1, d, fi, nullptr, sW);
+        if (act) face_point<N, Q, Real, GEN, true>(a, lt, ph, conv, visc, 1, d, fi, sTau, sFn, sJr, detJ, sW, tid, res, res1);
+        __syncthreads();
+        if (act) {
+#pragma unroll
+            for (int m = 0; m < 20; ++m) o[m * Q2] = res[m];
+        }
+        __syncthreads();
+        face_lift<N, Q, Real, 1>(lt, out, t1, [&](int) { return fw + (e * 6 + 3 + d) * FWB; });
+        // the other side's coefficients replace the own side's (its lift has read them)
+        if (act) {
+#pragma unroll
+            for (int c = 0; c < 5; ++c) o[c * Q2] = -res[c];
+#pragma unroll
+            for (int m = 0; m < 15; ++m) o[(5 + m) * Q2] = res1[m];
+        }
+        __syncthreads();
+        face_lift<N, Q, Real, 1>(lt, out, t1, [&](int) { return fi.wall[3 + d] ? nullptr : fw + (fi.enb[3 + d] * 6 + d) * FWB; });
+        __syncthreads();
+    }
+    // wall faces xi_d = 0: the own side only
+#pragma unroll 1
+    for (int d = 0; d < 3; ++d) {
+        if (!fi.wall[d]) continue;   // uniform over the workgroup
+        face_traces_sweep<N, Q, Real, 1, FS, true>(a, lt, 0, d, fi, nullptr, sW);
+        if (act) face_point<N, Q, Real, GEN>(a, lt, ph, conv, visc, 0, d, fi, sTau, sFn, sJr, detJ, sW, tid, res, res1);
+        __syncthreads();
+        if (act) {
+#pragma unroll
+            for (int m = 0; m < 20; ++m) o[m * Q2] = res[m];
+        }
+        __syncthreads();
+        face_lift<N, Q, Real, 1>(lt, out, t1, [&](int) { return fw + (e * 6 + d) * FWB; });
+        __syncthreads();
+    }
+}
+
+// Stand-alone inverse mass of the high degrees: one (component, cell) block per workgroup,
+// one line of N values per thread and axis (N^2 <= 256 lines), tables from the device copy.
+template <int N, typename Real, bool GEN>
+__global__ void __launch_bounds__(kHdBlock)
+inverse_mass_hd_kernel(const double* R, double* L, int64_t ncell, const double* cell_metric, const double* mass_jxw,
+                       const Tables1D* t) {
+    constexpr int N2 = N * N, N3 = N2 * N;
+    static_assert(N2 <= kHdBlock, "one line per thread");
+    __shared__ Real buf[N3];
+    __shared__ Real Smi[N][N];
+    __shared__ Real lwm[N];
+    const int tid = threadIdx.x;
+    for (int i = tid; i < N2; i += blockDim.x) Smi[i / N][i % N] = (Real)t->Smi[i / N][i % N];
+    if (tid < N) lwm[tid] = (Real)t->wm[tid];
+    const int64_t row = blockIdx.x;   // c * ncell + e
+    const bool act = tid < N2;
+    const double* src = R + row * N3;
+    Real v[N];
+    if (act) {
+#pragma unroll
+        for (int m = 0; m < N; ++m) v[m] = (Real)src[tid * N + m];
+    }
+    __syncthreads();
+    if (act) {
+        apply_line<N, true>(Smi, v);
+#pragma unroll
+        for (int m = 0; m < N; ++m) buf[tid * N + m] = v[m];
+    }
+    __syncthreads();
+    if (act) minv_sweep<N, 1, true>(Smi, buf, tid);
+    __syncthreads();
+    if (act) {
+        const int z0 = tid % N, z1 = tid / N;
+#pragma unroll
+        for (int m = 0; m < N; ++m) v[m] = buf[m * N2 + tid];
+        apply_line<N, true>(Smi, v);
+        const int64_t e = row % ncell;
+        if constexpr (GEN) {
+            const double* jw = mass_jxw + e * N3 + tid;
+#pragma unroll
+            for (int m = 0; m < N; ++m) v[m] = v[m] / (Real)jw[m * N2];
+        } else {
+            const Real f = Real(1) / ((Real)cell_metric[e * 10 + 9] * lwm[z0] * lwm[z1]);
+#pragma unroll
+            for (int m = 0; m < N; ++m) v[m] = v[m] * (f / lwm[m]);
+        }
+        apply_line<N, false>(Smi, v);
+#pragma unroll
+        for (int m = 0; m < N; ++m) buf[m * N2 + tid] = v[m];
+    }
+    __syncthreads();
+    if (act) minv_sweep<N, 1, false>(Smi, buf, tid);
+    __syncthreads();
+    if (act) {
+#pragma unroll
+        for (int m = 0; m < N; ++m) v[m] = buf[tid * N + m];
+        apply_line<N, false>(Smi, v);
+        double* dst = L + row * N3;
+#pragma unroll
+        for (int m = 0; m < N; ++m) dst[tid * N + m] = (double)v[m];
+    }
+}
+
+template <int N, typename Real, bool GEN>
+inline int launch_minv_hd_t(const double* R, double* L, int64_t ncell, const double* cm, const double* mj,
+                            const Tables1D* t_dev, hipStream_t st) {
+    hipLaunchKernelGGL((inverse_mass_hd_kernel<N, Real, GEN>), dim3((unsigned)(5 * ncell)), dim3(kHdBlock), 0, st, R, L,
+                       ncell, cm, mj, t_dev);
+    return hipGetLastError() == hipSuccess ? 0 : -1;
+}
+
+// One evaluation at the high degrees: face kernel, streamed cell kernel (R into the output,
+// or into the stage's next-state buffer), then M^{-1} in place and, for a fused Runge-Kutta
+// stage, the stage update from that buffer.
+template <int N, int Q, typename Real, bool GEN>
+inline int launch_op_hd_t(const OpArgs& a0, hipStream_t st) {
+    OpArgs a = a0;
+    const bool stage = a.rk.dU != nullptr;
+    if (stage) a.out = a.rk.U_out;
+    const dim3 grid((unsigned)a.ncell);
+    if (a.terms & 3u) hipLaunchKernelGGL((dg_face_hd_kernel<N, Q, Real, GEN>), grid, dim3(kHdBlock), 0, st, a);
+    hipLaunchKernelGGL((dg_cell_hd_kernel<N, Q, Real, GEN>), grid, dim3(kHdBlock), 0, st, a);
+    if (hipGetLastError() != hipSuccess) return -1;
+    if (a.fuse_minv || stage) {
+        if (launch_minv_hd_t<N, Real, GEN>(a.out, a.out, a.ncell, a.cell_metric, a.mass_jxw, a.tab_dev, st) != 0)
+            return -1;
+    }
+    if (stage)
+        return launch_rk_update_to(a.U, a.rk.U_out, a.rk.dU, a.rk.U_out, 5 * a.ncell * N * N * N, a.rk.A, a.rk.B,
+                                   a.rk.dt, st);
+    return 0;
+}
+
+}  // namespace dgns

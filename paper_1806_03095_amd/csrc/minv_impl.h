@@ -9,15 +9,17 @@
 
 namespace dgns {
 
-// Standalone inverse mass.  A workgroup takes RPB consecutive (component, cell) blocks,
-// one contiguous run of RPB N^3 values, which it loads into LDS with consecutive threads
-// on consecutive values (fully coalesced) and stores back the same way.  In between,
-// each thread owns LPT lines of N values per axis: the sweeps along xi_0, xi_1 and xi_2
-// (then the diagonal scaling and the transposed sweeps back) read a line from LDS into
-// registers and write it back in place, so that one barrier per change of axis suffices.
-// Two lines per thread for N <= 6 double the bytes that a workgroup has in flight,
-// which the kernel needs to stream its vectors at the HBM rate.  In place allowed: a
-// workgroup reads all of its blocks before it writes them.
+// Standalone inverse mass.  A workgroup of 256 threads takes RPB consecutive (component,
+// cell) blocks, one contiguous run of RPB N^3 values; each thread owns LPT lines of N
+// values per axis.  The x-lines are loaded straight from memory (consecutive threads on
+// consecutive lines, so a wave covers one contiguous run) and swept in registers; the
+// sweeps along xi_1 and xi_2 (then the diagonal scaling and the transposed sweeps back)
+// read a line from LDS into registers and write it back in place, so that one barrier
+// per change of axis suffices; the last x sweep stores straight to memory.  Two lines
+// per thread for N <= 6 double the bytes in flight per workgroup (measured 3-11% faster
+// on vectors past the last-level cache; staging whole runs through LDS with coalesced
+// loads was 10-20% slower).  In place allowed: a workgroup reads all of its blocks
+// before it writes them.
 constexpr int kMinvLineBlock = 256;
 
 template <int N>
@@ -59,38 +61,41 @@ __device__ __forceinline__ void minv_sweep(const Real (&M)[N][N], Real* blk, int
 template <int N, typename Real, bool GEN>
 __global__ void __launch_bounds__(kMinvLineBlock)
 inverse_mass_line_kernel(const double* R, double* L, int64_t ncell, const double* cell_metric,
-                         const double* mass_jxw, MTab<N, Real> mt) {
+                           const double* mass_jxw, MTab<N, Real> mt) {
     constexpr int N2 = N * N, N3 = N2 * N, LPT = MinvPlan<N>::LPT, RPB = MinvPlan<N>::RPB;
     constexpr int B = kMinvLineBlock;
-    __shared__ Real buf[RPB * N3];   // [block][a2][a1][a0]
-    __shared__ Real lwm[N];          // mass-rule weights, indexed per lane
+    __shared__ Real buf[RPB * N3];
+    __shared__ Real lwm[N];
     const int tid = threadIdx.x;
     if (tid < N) lwm[tid] = mt.wm[tid];
-    // the N x N table stays a kernel argument up to N = 7; for N = 8 it is read from
-    // an LDS copy (as a kernel argument the compiler keeps that one in scratch memory)
     const MTab<N, Real>* tp = &mt;
     if constexpr (N > 7) {
         __shared__ MTab<N, Real> lmt;
         copy_table<MTab<N, Real>, Real>(mt, lmt);
         tp = &lmt;
+        __syncthreads();
     }
     const auto& Smi = tp->Smi;
-    const int64_t row0 = (int64_t)blockIdx.x * RPB;   // row = c * ncell + e
+    const int64_t row0 = (int64_t)blockIdx.x * RPB;
     const int rows = 5 * ncell - row0 < RPB ? (int)(5 * ncell - row0) : RPB;
-    const int nv = rows * N3;
-    {
-        const double* src = R + row0 * N3;
-#pragma unroll
-        for (int m = 0; m < LPT * N; ++m) {
-            const int i = tid + m * B;
-            if (i < nv) buf[i] = (Real)src[i];
-        }
-    }
-    __syncthreads();
+    Real v[LPT][N];
 #pragma unroll
     for (int j = 0; j < LPT; ++j) {
         const int line = tid + j * B;
-        if (line < rows * N2) minv_sweep<N, 0, true>(Smi, buf + (line / N2) * N3, line % N2);
+        if (line < rows * N2) {
+            const double* src = R + row0 * N3 + (int64_t)line * N;
+#pragma unroll
+            for (int m = 0; m < N; ++m) v[j][m] = (Real)src[m];
+        }
+    }
+#pragma unroll
+    for (int j = 0; j < LPT; ++j) {
+        const int line = tid + j * B;
+        if (line < rows * N2) {
+            apply_line<N, true>(Smi, v[j]);
+#pragma unroll
+            for (int m = 0; m < N; ++m) buf[line * N + m] = v[j][m];
+        }
     }
     __syncthreads();
 #pragma unroll
@@ -99,31 +104,29 @@ inverse_mass_line_kernel(const double* R, double* L, int64_t ncell, const double
         if (line < rows * N2) minv_sweep<N, 1, true>(Smi, buf + (line / N2) * N3, line % N2);
     }
     __syncthreads();
-    // z-lines (a0, a1) = (ln % N, ln / N): sweep, scaling by 1 / (|J| w) at the mass
-    // points, transposed sweep
 #pragma unroll
     for (int j = 0; j < LPT; ++j) {
         const int line = tid + j * B;
         if (line < rows * N2) {
             const int lb = line / N2, ln = line % N2, z0 = ln % N, z1 = ln / N;
             Real* blk = buf + lb * N3;
-            Real v[N];
+            Real w[N];
 #pragma unroll
-            for (int m = 0; m < N; ++m) v[m] = blk[m * N2 + ln];
-            apply_line<N, true>(Smi, v);
+            for (int m = 0; m < N; ++m) w[m] = blk[m * N2 + ln];
+            apply_line<N, true>(Smi, w);
             const int64_t e = (row0 + lb) % ncell;
             if constexpr (GEN) {
                 const double* jw = mass_jxw + e * N3 + ln;
 #pragma unroll
-                for (int m = 0; m < N; ++m) v[m] = v[m] / (Real)jw[m * N2];
+                for (int m = 0; m < N; ++m) w[m] = w[m] / (Real)jw[m * N2];
             } else {
                 const Real f = Real(1) / ((Real)cell_metric[e * 10 + 9] * lwm[z0] * lwm[z1]);
 #pragma unroll
-                for (int m = 0; m < N; ++m) v[m] = v[m] * (f / tp->wm[m]);
+                for (int m = 0; m < N; ++m) w[m] = w[m] * (f / tp->wm[m]);
             }
-            apply_line<N, false>(Smi, v);
+            apply_line<N, false>(Smi, w);
 #pragma unroll
-            for (int m = 0; m < N; ++m) blk[m * N2 + ln] = v[m];
+            for (int m = 0; m < N; ++m) blk[m * N2 + ln] = w[m];
         }
     }
     __syncthreads();
@@ -136,15 +139,13 @@ inverse_mass_line_kernel(const double* R, double* L, int64_t ncell, const double
 #pragma unroll
     for (int j = 0; j < LPT; ++j) {
         const int line = tid + j * B;
-        if (line < rows * N2) minv_sweep<N, 0, false>(Smi, buf + (line / N2) * N3, line % N2);
-    }
-    __syncthreads();
-    {
-        double* dst = L + row0 * N3;
+        if (line < rows * N2) {
 #pragma unroll
-        for (int m = 0; m < LPT * N; ++m) {
-            const int i = tid + m * B;
-            if (i < nv) dst[i] = (double)buf[i];
+            for (int m = 0; m < N; ++m) v[j][m] = buf[line * N + m];
+            apply_line<N, false>(Smi, v[j]);
+            double* dst = L + row0 * N3 + (int64_t)line * N;
+#pragma unroll
+            for (int m = 0; m < N; ++m) dst[m] = (double)v[j][m];
         }
     }
 }

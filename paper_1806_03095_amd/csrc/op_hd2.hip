@@ -1,0 +1,40 @@
+// High-degree operator kernels (hd_impl.h), degrees 12..15.
+#include "hd_impl.h"
+
+namespace dgns {
+
+template <int N, int Q>
+static int op_hd(const OpArgs& a, bool fp32, bool gen, hipStream_t st) {
+    return fp32 ? (gen ? launch_op_hd_t<N, Q, float, true>(a, st) : launch_op_hd_t<N, Q, float, false>(a, st))
+                : (gen ? launch_op_hd_t<N, Q, double, true>(a, st) : launch_op_hd_t<N, Q, double, false>(a, st));
+}
+
+template <int N>
+static int minv_hd(const double* R, double* L, int64_t ncell, const double* cm, const double* mj, const Tables1D* t,
+                   bool fp32, bool gen, hipStream_t st) {
+    return fp32 ? (gen ? launch_minv_hd_t<N, float, true>(R, L, ncell, cm, mj, t, st)
+                       : launch_minv_hd_t<N, float, false>(R, L, ncell, cm, mj, t, st))
+                : (gen ? launch_minv_hd_t<N, double, true>(R, L, ncell, cm, mj, t, st)
+                       : launch_minv_hd_t<N, double, false>(R, L, ncell, cm, mj, t, st));
+}
+
+int launch_operator_hd2(const OpArgs& a, int k, int q, bool fp32, bool gen, hipStream_t st) {
+    if (k == 12 && q == 13) return op_hd<13, 13>(a, fp32, gen, st);
+    if (k == 13 && q == 14) return op_hd<14, 14>(a, fp32, gen, st);
+    if (k == 14 && q == 15) return op_hd<15, 15>(a, fp32, gen, st);
+    if (k == 15 && q == 16) return op_hd<16, 16>(a, fp32, gen, st);
+    return 1;
+}
+
+int launch_inverse_mass_hd2(const double* R, double* L, int64_t ncell, const double* cm, const double* mj,
+                            const Tables1D* t, int k, bool fp32, bool gen, hipStream_t st) {
+    switch (k) {
+        case 12: return minv_hd<13>(R, L, ncell, cm, mj, t, fp32, gen, st);
+        case 13: return minv_hd<14>(R, L, ncell, cm, mj, t, fp32, gen, st);
+        case 14: return minv_hd<15>(R, L, ncell, cm, mj, t, fp32, gen, st);
+        case 15: return minv_hd<16>(R, L, ncell, cm, mj, t, fp32, gen, st);
+        default: return 1;
+    }
+}
+
+}  // namespace dgns

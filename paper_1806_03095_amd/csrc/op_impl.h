@@ -420,13 +420,16 @@ __device__ __forceinline__ void load_face_point(const KTab<N, Q, Real>& tb, cons
 // As load_face_point, with the metric rows already permuted to the face's axes:
 // Jr = rows (t0, t1, d) of J^{-1}, so the physical gradient needs no per-lane
 // selection of reference components.
+// (For N > 8 the line loop is unrolled by four only: fully unrolled, the compiler loads
+// all 15 N operands ahead and spills.)
 template <int N, int Q, typename Real>
 __device__ __forceinline__ void load_face_point_rows(const KTab<N, Q, Real>& tb, const Real* A, int q0, int q1,
                                                      const Real (&Jr)[9], Real U[5], Real G[5][3]) {
+    constexpr int UF = N <= 8 ? N : 4;
 #pragma unroll
     for (int c = 0; c < 5; ++c) {
         Real v = 0, g0 = 0, g1 = 0, gn = 0;
-#pragma unroll
+#pragma unroll UF
         for (int ib = 0; ib < N; ++ib) {
             const Real a0 = A[(0 * 5 + c) * N * Q + ib * Q + q0];
             const Real a1 = A[(1 * 5 + c) * N * Q + ib * Q + q0];
@@ -665,14 +668,15 @@ __device__ __forceinline__ void face_point(const OpArgs& a, const KTab<N, Q, Rea
 }
 
 // Traces of U and of its normal derivative on both sides of the NF faces xi_d = s,
-// d = d0 .. d0 + NF - 1 (own side from sU, the neighbour's from its coefficients in
-// global memory, nothing for the exterior side of a wall), swept along t0:
-// SW = sW [f][side][3][c][N][Q] (value, t0-derivative, normal derivative), using the
-// TR area of the layout FS for unfused traces.  Ends with a barrier.
-template <int N, int Q, typename Real, int NF, typename FS>
+// d = d0 .. d0 + NF - 1 (own side from sU, or with OWNG from the cell's coefficients in
+// global memory; the neighbour's from global memory; nothing for the exterior side of a
+// wall), swept along t0: SW = sW [f][side][3][c][N][Q] (value, t0-derivative, normal
+// derivative), using the TR area of the layout FS for unfused traces.  Ends with a barrier.
+template <int N, int Q, typename Real, int NF, typename FS, bool OWNG = false>
 __device__ __forceinline__ void face_traces_sweep(const OpArgs& a, const KTab<N, Q, Real>& lt, int s, int d0,
                                                   const FaceInfo& fi, const Real* sU, Real* sW) {
     constexpr int N2 = N * N, N3 = N2 * N;
+    static_assert(!(OWNG && FS::FUSED_TRACE), "own coefficients from global memory: unfused traces only");
     Real* r1 = sW;                 // SW
     const int tid = threadIdx.x, nth = blockDim.x;
     const int64_t cstride = a.ncell * N3;
@@ -747,7 +751,8 @@ __device__ __forceinline__ void face_traces_sweep(const OpArgs& a, const KTab<N,
             Real tv = 0, tn = 0, uv = 0, un = 0;
     #pragma unroll
             for (int m = 0; m < N; ++m) {
-                const Real x = sU[c * N3 + base + m * sd];
+                const Real x = OWNG ? (Real)a.U[c * cstride + (int64_t)blockIdx.x * N3 + base + m * sd]
+                                    : sU[c * N3 + base + m * sd];
                 tv += lt.fv[s][m] * x;
                 tn += lt.fd[s][m] * x;
             }
@@ -780,7 +785,10 @@ __device__ __forceinline__ void face_traces_sweep(const OpArgs& a, const KTab<N,
                 tn[ia] = tr[5 * N2 + ia];
             }
             Real* o = r1 + ((f * 2 + side) * 3 * 5 + c) * N * Q + ib * Q;
-    #pragma unroll
+            // (N > 8: the output loop is not unrolled, else the compiler loads the whole
+            // 2 n_q N table ahead and spills)
+            constexpr int UQ = N <= 8 ? Q : 1;
+    #pragma unroll UQ
             for (int q0 = 0; q0 < Q; ++q0) {
                 Real a0 = 0, a1 = 0, an = 0;
     #pragma unroll

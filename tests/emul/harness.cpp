@@ -16,10 +16,18 @@
 
 #include "adj_impl.h"
 #include "diag_impl.h"
+#include "hd_impl.h"
 #include "minv_impl.h"
 #include "setup.h"
 
 using namespace dgns;
+
+// The high-degree launcher's fused Runge-Kutta stage calls the stand-alone update (in
+// aux_kernels.hip, not part of this harness); the harness never runs a stage.
+int dgns::launch_rk_update_to(const double*, double*, double*, const double*, int64_t, double, double, double,
+                              hipStream_t) {
+    return -1;
+}
 
 namespace {
 
@@ -33,6 +41,21 @@ template <int N, int Q>
 int run(const OpArgs& a, const Tables1D& t, int fp32, int gen) {
     if (fp32) return gen ? launch_op_t<N, Q, float, true>(a, t, nullptr) : launch_op_t<N, Q, float, false>(a, t, nullptr);
     return gen ? launch_op_t<N, Q, double, true>(a, t, nullptr) : launch_op_t<N, Q, double, false>(a, t, nullptr);
+}
+
+template <int N, int Q>
+int run_hd(const OpArgs& a, int fp32, int gen) {
+    if (fp32) return gen ? launch_op_hd_t<N, Q, float, true>(a, nullptr) : launch_op_hd_t<N, Q, float, false>(a, nullptr);
+    return gen ? launch_op_hd_t<N, Q, double, true>(a, nullptr) : launch_op_hd_t<N, Q, double, false>(a, nullptr);
+}
+
+template <int N>
+int run_minv_hd(const OpArgs& a, int fp32, int gen) {
+    if (fp32)
+        return gen ? launch_minv_hd_t<N, float, true>(a.U, a.out, a.ncell, a.cell_metric, a.mass_jxw, a.tab_dev, nullptr)
+                   : launch_minv_hd_t<N, float, false>(a.U, a.out, a.ncell, a.cell_metric, a.mass_jxw, a.tab_dev, nullptr);
+    return gen ? launch_minv_hd_t<N, double, true>(a.U, a.out, a.ncell, a.cell_metric, a.mass_jxw, a.tab_dev, nullptr)
+               : launch_minv_hd_t<N, double, false>(a.U, a.out, a.ncell, a.cell_metric, a.mass_jxw, a.tab_dev, nullptr);
 }
 
 template <int N, int Q>
@@ -111,6 +134,7 @@ int main(int argc, char** argv) {
     a.terms = terms;
     a.fuse_minv = fuse == 1 ? 1 : 0;
     a.fw = fw.data();
+    a.tab_dev = &hs.tab;
     const int k = prm.degree, q = prm.n_q, fp32 = prm.precision, gen = hs.gen ? 1 : 0;
     rc = -4;
 #define EMU_CASE(K, Q_) \
@@ -121,6 +145,13 @@ int main(int argc, char** argv) {
                                                  : (fuse == 5 ? run_wall<K + 1, Q_>(a, hs.tab, gen)          \
                                                               : run<K + 1, Q_>(a, hs.tab, fp32, gen))));
     EMU_CASES
+#ifdef EMU_HD_CASES
+    // degrees >= 8: modes 0 (residual), 1 (operator) and 3 (stand-alone inverse mass)
+#define EMU_HD_CASE(K, Q_) \
+    if (k == K && q == Q_)  \
+        rc = fuse == 3 ? run_minv_hd<K + 1>(a, fp32, gen) : (fuse <= 1 ? run_hd<K + 1, Q_>(a, fp32, gen) : -4);
+    EMU_HD_CASES
+#endif
     if (rc != 0) {
         std::fprintf(stderr, "no emulated kernel for k=%d nq=%d\n", k, q);
         return 7;

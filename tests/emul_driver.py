@@ -12,26 +12,30 @@ EMU = os.path.join(ROOT, "tests", "emul")
 CSRC = os.path.join(ROOT, "paper_1806_03095_amd", "csrc")
 BUILD = os.path.join(EMU, "_build")
 CASES = [(1, 2), (2, 3), (3, 6), (4, 5), (4, 7), (7, 11)]
+# degrees >= 8 (hd_impl.h): residual, operator and stand-alone inverse mass
+HD_CASES = [(8, 9)]
 
 
 def build():
     srcs = [os.path.join(EMU, "harness.cpp"), os.path.join(EMU, "hip", "hip_runtime.h"),
             os.path.join(CSRC, "setup.cpp"), os.path.join(CSRC, "setup.h"), os.path.join(CSRC, "op_impl.h"),
             os.path.join(CSRC, "adj_impl.h"), os.path.join(CSRC, "dg_adjoint.h"), os.path.join(CSRC, "diag_impl.h"),
-            os.path.join(CSRC, "minv_impl.h"),
+            os.path.join(CSRC, "minv_impl.h"), os.path.join(CSRC, "hd_impl.h"),
             os.path.join(CSRC, "dg_common.h"), os.path.join(ROOT, "include", "dgns.h")]
     h = hashlib.sha1()
     for s in srcs:
         h.update(open(s, "rb").read())
     h.update(repr(CASES).encode())
+    h.update(repr(HD_CASES).encode())
     exe = os.path.join(BUILD, "harness_" + h.hexdigest()[:12])
     if os.path.exists(exe):
         return exe
     os.makedirs(BUILD, exist_ok=True)
     cases = " ".join("EMU_CASE(%d,%d)" % kq for kq in CASES)
+    hd_cases = " ".join("EMU_HD_CASE(%d,%d)" % kq for kq in HD_CASES)
     cmd = ["g++", "-std=c++17", "-O1", "-g", "-fsanitize=address,undefined", "-fno-sanitize-recover=all",
            "-fno-omit-frame-pointer", "-I", EMU, "-I", os.path.join(ROOT, "include"), "-I", CSRC,
-           "-DEMU_CASES=" + cases, os.path.join(EMU, "harness.cpp"), os.path.join(CSRC, "setup.cpp"),
+           "-DEMU_CASES=" + cases, "-DEMU_HD_CASES=" + hd_cases, os.path.join(EMU, "harness.cpp"), os.path.join(CSRC, "setup.cpp"),
            "-o", exe + ".tmp%d" % os.getpid(), "-lpthread"]
     # a per-process temporary name: parallel test workers may build the same harness at once
     r = subprocess.run(cmd, capture_output=True, text=True)

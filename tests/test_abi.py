@@ -44,9 +44,12 @@ def _mesh(**kw):
 
 @pytest.mark.parametrize("pkw,mkw,code", [
     (dict(degree=0), {}, binding.EINVAL),
-    (dict(degree=8), {}, binding.EINVAL),
+    (dict(degree=16), {}, binding.EINVAL),
     (dict(n_q=0), {}, binding.EINVAL),
+    (dict(n_q=17), {}, binding.EINVAL),
     (dict(n_q=10), {}, binding.EUNSUPPORTED),
+    (dict(degree=8, n_q=12), {}, binding.EUNSUPPORTED),
+    (dict(degree=8, n_q=9, body_force=(ctypes.c_double * 3)(1, 0, 0)), {}, binding.EUNSUPPORTED),
     (dict(basis=5), {}, binding.EINVAL),
     (dict(precision=3), {}, binding.EINVAL),
     (dict(gamma=1.0), {}, binding.EINVAL),

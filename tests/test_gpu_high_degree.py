@@ -1,0 +1,135 @@
+"""GPU parity of the high-degree kernels (k = 8..15: hd_impl.h, the cell streamed through
+LDS plane by plane, faces once per face, stand-alone inverse mass) against the oracle.
+
+Every compiled (k, n_q) -- n_q = k+1 for k = 8..15 and the 3/2 rule for k = 8..10 -- on a
+two-cell periodic mesh, affine and curved in turn, LGL and Gauss nodes in turn:
+  - float64 R and L at Mach 0.3 (Taylor-Green plus noise) against the oracle with the
+    floor rule of tests/floor.py, the extended-precision reference on one cell, for
+    k = 8, 9 at n_q = k+1 (its dense evaluation takes 14 s per cell at k = 9, 40 s at 10);
+  - otherwise per field |gpu - oracle| <= 1e-12 ((k+1)/4)^4 for R and the same times
+    10 for L: the measured floors grow like the square of the 1D derivative matrices'
+    norms, ((k+1)/4)^2 -- at k = 8: 3e-13 (R) and 1.2e-11 (L) -- and the bound leaves
+    another factor ((k+1)/4)^2 (5 at k = 8, 16 at k = 15);
+  - the stand-alone inverse mass (backward error through the oracle's mass matrix);
+  - float32 R per field within 50 times what rounding the input alone to float32 costs.
+Also: two Runge-Kutta steps at k = 8 (stages 1-4 through the high-degree stage path,
+which writes L into the next-state buffer and updates from there) against the oracle's
+steps, the initial-state projection at k = 8, and the entry points without high-degree
+kernels (diagnostics, adjoint) and body forces rejected with DGNS_EUNSUPPORTED.
+"""
+import math
+
+import pytest
+import torch
+
+from oracle import initial, timeint
+from tests import floor
+from tests.gpu_cases import announce, make_pair, rel_err_fields, tgv_input
+
+pytestmark = pytest.mark.gpu
+
+HD = [(8, 9), (8, 13), (9, 10), (9, 14), (10, 11), (10, 16), (11, 12), (12, 13), (13, 14), (14, 15), (15, 16)]
+
+
+def _cuda(t):
+    return t.to("cuda").contiguous()
+
+
+def _case(i):
+    n = [(2, 1, 1), (1, 2, 1)][i % 2]
+    kind, amp = ("curved", 0.1) if i % 2 else ("affine", 0.0)
+    basis = "GL" if i % 3 == 2 else "LGL"
+    return n, kind, amp, basis
+
+
+@pytest.mark.parametrize("kq", HD)
+def test_high_degree_float64(kq):
+    k, nq = kq
+    i = HD.index(kq)
+    n, kind, amp, basis = _case(i)
+    announce("high degree fp64 n=%s k=%d nq=%d %s %s" % (n, k, nq, kind, basis))
+    oop, gop = make_pair(n, k, nq, kind=kind, amp=amp, basis=basis)
+    U = tgv_input(oop, seed=40 + i, mach=0.3)
+    R_gpu = gop.residual(_cuda(U)).cpu()
+    L_gpu = gop.apply(_cuda(U)).cpu()
+    torch.cuda.synchronize()
+    R_ora, L_ora = oop.residual(U), oop.apply(U)
+    if nq == k + 1 and k <= 9:
+        R_ext, L_ext = floor.reference_RL(oop, U, [0])
+        floor.check(R_gpu, R_ora, R_ext, "R k=%d" % k, sub=[0])
+        floor.check(L_gpu, L_ora, L_ext, "L k=%d" % k, sub=[0])
+    else:
+        tol = 1e-12 * ((k + 1) / 4.0) ** 4
+        eR = rel_err_fields(R_gpu, R_ora)
+        eL = rel_err_fields(L_gpu, L_ora)
+        print("k=%d: R vs oracle %s, L vs oracle %s (bounds %.1e, %.1e)"
+              % (k, ["%.1e" % e for e in eR], ["%.1e" % e for e in eL], tol, 10 * tol), flush=True)
+        assert max(eR) <= tol, eR
+        assert max(eL) <= 10 * tol, eL
+    # stand-alone inverse mass: backward error through the oracle's mass matrix
+    X = gop.inverse_mass(_cuda(U)).cpu()
+    torch.cuda.synchronize()
+    M = oop.mass_matrices()
+    MX = torch.einsum("eij,cej->cei", M, X)
+    err = float(torch.linalg.norm(MX - U) / torch.linalg.norm(U))
+    assert err < 1e-13 * ((k + 1) / 4.0) ** 2, err
+
+
+@pytest.mark.parametrize("kq", HD)
+def test_high_degree_float32(kq):
+    k, nq = kq
+    i = HD.index(kq)
+    n, kind, amp, basis = _case(i + 1)
+    announce("high degree fp32 n=%s k=%d nq=%d %s %s" % (n, k, nq, kind, basis))
+    oop, gop = make_pair(n, k, nq, kind=kind, amp=amp, basis=basis, precision="fp32")
+    U = tgv_input(oop, seed=60 + i, mach=0.3)
+    R32 = gop.residual(_cuda(U)).cpu()
+    torch.cuda.synchronize()
+    R64 = oop.residual(U)
+    cast = rel_err_fields(oop.residual(U.float().double()), R64)
+    errs = rel_err_fields(R32, R64)
+    print("fp32 k=%d per field %s; input-rounding floor %s" % (k, ["%.1e" % e for e in errs], ["%.1e" % e for e in cast]),
+          flush=True)
+    for c in range(5):
+        assert errs[c] <= max(50 * cast[c], 1e-6), (c, errs, cast)
+
+
+def test_high_degree_rk_steps_and_projection():
+    announce("high degree k=8 nq=9: projection and two RK steps")
+    oop, gop = make_pair((2, 1, 1), 8, 9)
+    Ug = gop.project_ic("taylor_green", [1.0, 1.0, 0.3, 1.0])
+    torch.cuda.synchronize()
+    Uo = initial.l2_project(oop, lambda x: initial.taylor_green(x, oop.fl, mach=0.3))
+    errs = rel_err_fields(Ug.cpu(), Uo)
+    print("projection vs oracle", ["%.1e" % e for e in errs], flush=True)
+    assert max(errs) < 1e-12, errs
+    U0 = tgv_input(oop, seed=77, mach=0.3)
+    dt = gop.compute_dt(0.2, 0.02, 1.5, 3.0, 1.0, 0.3)
+    Ug = _cuda(U0.clone())
+    work = torch.empty(2 * gop.n_dof, dtype=torch.float64, device="cuda")
+    for s in range(2):
+        gop.rk_step(Ug, work, s * dt, dt)
+    torch.cuda.synchronize()
+    U = U0.clone()
+    for s in range(2):
+        U = timeint.lsrk_step(lambda V, t: oop.apply(V), U, s * dt, dt)
+    e_L = floor.oracle_floor(oop, U0, cells=[0])
+    inc = rel_err_fields(Ug.cpu() - U0, U - U0)
+    print("two RK steps: increment vs oracle %s, oracle L floor %s" % (["%.1e" % e for e in inc],
+                                                                       ["%.1e" % e for e in e_L]), flush=True)
+    st = [20 * 2.0 ** -53 * float(torch.linalg.norm(U0[c]) / torch.linalg.norm((U - U0)[c])) for c in range(5)]
+    for c in range(5):
+        assert inc[c] <= max(1e-12, 4.0 * (e_L[c] + st[c])), (c, inc, e_L, st)
+
+
+def test_high_degree_unsupported_entry_points():
+    from paper_1806_03095_amd import binding
+    oop, gop = make_pair((2, 1, 1), 8, 9)
+    U = _cuda(tgv_input(oop, seed=5, mach=0.3))
+    with pytest.raises(RuntimeError, match="degree|unsupported|kernel"):
+        gop.diagnostics(U)
+    with pytest.raises(RuntimeError, match="degree|unsupported|kernel"):
+        gop.residual_vjp(U, torch.ones_like(U))
+    with pytest.raises(RuntimeError, match="body force"):
+        make_pair((2, 1, 1), 8, 9, force=(1.0, 0.0, 0.0))
+    assert binding is not None

@@ -207,3 +207,32 @@ def test_lds_plan_layout():
         assert r.returncode == 0, r.stderr[-4000:]
         r = subprocess.run([exe], capture_output=True, text=True)
         assert r.returncode == 0 and r.stdout.strip().endswith("all ok"), r.stdout[-4000:]
+
+
+@pytest.mark.parametrize("n,kind,amp,basis", [((2, 1, 1), 0, 0.0, "LGL"), ((1, 2, 1), 2, 0.1, "GL")])
+def test_emulated_high_degree(n, kind, amp, basis):
+    # degree 8 (hd_impl.h: the cell streamed plane by plane, faces once per face, the
+    # stand-alone inverse mass) at Mach 0.1: R and L under the floor rule against the
+    # extended evaluation, M^{-1} by its backward error, float32 R within 50 times the
+    # input-rounding floor
+    k, nq = 8, 9
+    fl = tgv_fluid()
+    om = omesh.BoxMesh(n, PI3[0], PI3[1], k, kind=kind, deform_amp=amp)
+    oop = ooperator.DGOperator(om, fl, nq, basis=basis)
+    U = tgv_input(oop, mach=0.1, seed=31)
+    b = 0 if basis == "LGL" else 1
+    cells = list(range(om.n_cells))
+    R_ext, L_ext = floor.reference_RL(oop, U, cells)
+    R = ed.run(U.numpy(), k, nq, n, *PI3, kind=kind, amp=amp, basis=b, mu=fl.mu, lam=fl.lam, fuse=0)
+    floor.check(R, oop.residual(U), R_ext, "emulated k=8 R")
+    L = ed.run(U.numpy(), k, nq, n, *PI3, kind=kind, amp=amp, basis=b, mu=fl.mu, lam=fl.lam, fuse=1)
+    floor.check(L, oop.apply(U), L_ext, "emulated k=8 L")
+    X = ed.run(U.numpy(), k, nq, n, *PI3, kind=kind, amp=amp, basis=b, mu=fl.mu, lam=fl.lam, fuse=3)
+    MX = torch.einsum("eij,cej->cei", oop.mass_matrices(), torch.as_tensor(X))
+    assert float(torch.linalg.norm(MX - U) / torch.linalg.norm(U)) < 1e-13
+    R32 = ed.run(U.numpy(), k, nq, n, *PI3, kind=kind, amp=amp, basis=b, precision=1, mu=fl.mu, lam=fl.lam, fuse=0)
+    R64 = oop.residual(U)
+    cast = rel_err_fields(oop.residual(U.float().double()), R64)
+    errs = rel_err_fields(torch.as_tensor(R32), R64)
+    for c in range(5):
+        assert errs[c] <= 50 * cast[c], (c, errs, cast)
