@@ -23,7 +23,7 @@ BUILD = os.path.join(PKG, "_build")
 LIB = os.path.join(PKG, "libdgns.so")
 
 SOURCES = ["dgns_api.cpp", "setup.cpp", "aux_kernels.hip"] + ["op_k%d.hip" % k for k in range(1, 8)] + \
-    ["op_hd1.hip", "op_hd2.hip"]
+    ["op_hd0.hip", "op_hd1.hip", "op_hd2.hip"]
 
 HIPCC = shutil.which("hipcc") or "/opt/rocm/bin/hipcc"
 FLAGS = ["--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC",

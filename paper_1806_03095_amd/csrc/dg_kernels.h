@@ -47,6 +47,9 @@ constexpr int kSupported[][2] = {{1, 2}, {1, 3}, {2, 3}, {2, 4}, {2, 5}, {3, 4},
 constexpr int kSupportedHd[][2] = {{8, 9},  {8, 13},  {9, 10},  {9, 14},  {10, 11}, {10, 16},
                                    {11, 12}, {12, 13}, {13, 14}, {14, 15}, {15, 16}};
 int launch_operator_hd1(const OpArgs& a, int k, int q, bool fp32, bool gen, hipStream_t st);   // k = 8..11
+// The streamed kernels at lower degrees where they measured faster (op_hd0.hip).
+bool streamed_preferred(int k, int q, bool fp32, const double force[3]);
+int launch_operator_hd0(const OpArgs& a, int k, int q, bool fp32, bool gen, hipStream_t st);
 int launch_operator_hd2(const OpArgs& a, int k, int q, bool fp32, bool gen, hipStream_t st);   // k = 12..15
 int launch_inverse_mass_hd1(const double* R, double* L, int64_t ncell, const double* cm, const double* mj,
                             const Tables1D* t_dev, int k, bool fp32, bool gen, hipStream_t st);

@@ -167,6 +167,11 @@ OpArgs make_args(const dgns_ctx* c, const double* U, double* out, unsigned terms
 
 int dispatch_operator(const dgns_ctx* c, const OpArgs& a) {
     int rc = 1;
+    if (streamed_preferred(c->k, c->q, c->fp32, c->prm.body_force)) {
+        rc = launch_operator_hd0(a, c->k, c->q, c->fp32, c->gen, c->stream);
+        if (rc != 0) return fail(DGNS_EHIP, "operator launch failed: %s", hipGetErrorString(hipGetLastError()));
+        return 0;
+    }
     switch (c->k) {
         case 1: rc = launch_operator_k1(a, c->tab, c->fp32, c->gen, c->stream); break;
         case 2: rc = launch_operator_k2(a, c->tab, c->fp32, c->gen, c->stream); break;

@@ -324,45 +324,53 @@ dg_face_hd_kernel(OpArgs a) {
     }
 }
 
-// Stand-alone inverse mass of the high degrees: one (component, cell) block per workgroup,
-// one line of N values per thread and axis (N^2 <= 256 lines), tables from the device copy.
+// Stand-alone inverse mass of the high degrees: RPB = 256 / N^2 (component, cell) blocks per
+// workgroup (3 at N = 9, 2 at N = 10, 11, else 1), one line of N values per thread and axis,
+// tables from the device copy.
+template <int N>
+struct MinvHdPlan {
+    static constexpr int RPB = kHdBlock / (N * N) > 0 ? kHdBlock / (N * N) : 1;
+};
+
 template <int N, typename Real, bool GEN>
 __global__ void __launch_bounds__(kHdBlock)
 inverse_mass_hd_kernel(const double* R, double* L, int64_t ncell, const double* cell_metric, const double* mass_jxw,
                        const Tables1D* t) {
-    constexpr int N2 = N * N, N3 = N2 * N;
+    constexpr int N2 = N * N, N3 = N2 * N, RPB = MinvHdPlan<N>::RPB;
     static_assert(N2 <= kHdBlock, "one line per thread");
-    __shared__ Real buf[N3];
+    __shared__ Real buf[RPB * N3];
     __shared__ Real Smi[N][N];
     __shared__ Real lwm[N];
     const int tid = threadIdx.x;
     for (int i = tid; i < N2; i += blockDim.x) Smi[i / N][i % N] = (Real)t->Smi[i / N][i % N];
     if (tid < N) lwm[tid] = (Real)t->wm[tid];
-    const int64_t row = blockIdx.x;   // c * ncell + e
-    const bool act = tid < N2;
-    const double* src = R + row * N3;
+    const int lb = tid / N2, ln = tid % N2;
+    const int64_t row = (int64_t)blockIdx.x * RPB + lb;   // c * ncell + e
+    const bool act = lb < RPB && row < 5 * ncell;
+    Real* blk = buf + lb * N3;
     Real v[N];
     if (act) {
+        const double* src = R + row * N3 + ln * N;
 #pragma unroll
-        for (int m = 0; m < N; ++m) v[m] = (Real)src[tid * N + m];
+        for (int m = 0; m < N; ++m) v[m] = (Real)src[m];
     }
     __syncthreads();
     if (act) {
         apply_line<N, true>(Smi, v);
 #pragma unroll
-        for (int m = 0; m < N; ++m) buf[tid * N + m] = v[m];
+        for (int m = 0; m < N; ++m) blk[ln * N + m] = v[m];
     }
     __syncthreads();
-    if (act) minv_sweep<N, 1, true>(Smi, buf, tid);
+    if (act) minv_sweep<N, 1, true>(Smi, blk, ln);
     __syncthreads();
     if (act) {
-        const int z0 = tid % N, z1 = tid / N;
+        const int z0 = ln % N, z1 = ln / N;
 #pragma unroll
-        for (int m = 0; m < N; ++m) v[m] = buf[m * N2 + tid];
+        for (int m = 0; m < N; ++m) v[m] = blk[m * N2 + ln];
         apply_line<N, true>(Smi, v);
         const int64_t e = row % ncell;
         if constexpr (GEN) {
-            const double* jw = mass_jxw + e * N3 + tid;
+            const double* jw = mass_jxw + e * N3 + ln;
 #pragma unroll
             for (int m = 0; m < N; ++m) v[m] = v[m] / (Real)jw[m * N2];
         } else {
@@ -372,25 +380,27 @@ inverse_mass_hd_kernel(const double* R, double* L, int64_t ncell, const double* 
         }
         apply_line<N, false>(Smi, v);
 #pragma unroll
-        for (int m = 0; m < N; ++m) buf[m * N2 + tid] = v[m];
+        for (int m = 0; m < N; ++m) blk[m * N2 + ln] = v[m];
     }
     __syncthreads();
-    if (act) minv_sweep<N, 1, false>(Smi, buf, tid);
+    if (act) minv_sweep<N, 1, false>(Smi, blk, ln);
     __syncthreads();
     if (act) {
 #pragma unroll
-        for (int m = 0; m < N; ++m) v[m] = buf[tid * N + m];
+        for (int m = 0; m < N; ++m) v[m] = blk[ln * N + m];
         apply_line<N, false>(Smi, v);
-        double* dst = L + row * N3;
+        double* dst = L + row * N3 + ln * N;
 #pragma unroll
-        for (int m = 0; m < N; ++m) dst[tid * N + m] = (double)v[m];
+        for (int m = 0; m < N; ++m) dst[m] = (double)v[m];
     }
 }
 
 template <int N, typename Real, bool GEN>
 inline int launch_minv_hd_t(const double* R, double* L, int64_t ncell, const double* cm, const double* mj,
                             const Tables1D* t_dev, hipStream_t st) {
-    hipLaunchKernelGGL((inverse_mass_hd_kernel<N, Real, GEN>), dim3((unsigned)(5 * ncell)), dim3(kHdBlock), 0, st, R, L,
+    constexpr int RPB = MinvHdPlan<N>::RPB;
+    const int64_t grid = (5 * ncell + RPB - 1) / RPB;
+    hipLaunchKernelGGL((inverse_mass_hd_kernel<N, Real, GEN>), dim3((unsigned)grid), dim3(kHdBlock), 0, st, R, L,
                        ncell, cm, mj, t_dev);
     return hipGetLastError() == hipSuccess ? 0 : -1;
 }

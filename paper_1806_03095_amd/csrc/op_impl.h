@@ -192,6 +192,23 @@ struct OpBlock {
     static constexpr bool even_odd = N >= 4;
 };
 
+// Loops that the compiler would otherwise unroll completely and whose operands it then
+// loads all ahead, past the register budget (spills): unrolled only partly where that
+// measured faster at about 10M DoFs.  face: the line loop of a face point (by four) and
+// the output loop of the traces' first tangential sweep (not unrolled); cell: the x
+// contraction at a cell point (by three).  Float64: k = 5 (both n_q: 918 -> 764 and
+// 1090 -> 988 us) and k = 6, n_q = 7 (1070 -> 911 us), which no longer spill; float32
+// (face only): k = 6, n_q = 7 (511 -> 457 us) and k = 7, n_q = 8 (355 -> 337 us); and
+// every degree >= 8.  Elsewhere the full unroll measured as fast or faster (k = 4: up to
+// 11% slower limited; k = 5 float32: 6-10% slower).
+template <int N, int Q, typename Real>
+struct UnrollLimit {
+    static constexpr bool fp64 = sizeof(Real) == sizeof(double);
+    static constexpr bool face = N > 8 || (fp64 && (N == 6 || (N == 7 && Q == 7))) ||
+                                 (!fp64 && ((N == 7 && Q == 7) || (N == 8 && Q == 8)));
+    static constexpr bool cell = fp64 && (N == 6 || (N == 7 && Q == 7));
+};
+
 // Applies an N x N matrix M along axis `ax` of the NC arrays src[NC][N^3] ->
 // dst[NC][N^3]; TRANS uses M^T.  Cooperative over the workgroup; the caller syncs.
 template <int N, typename Real, bool TRANS, int NC = 5>
@@ -420,12 +437,12 @@ __device__ __forceinline__ void load_face_point(const KTab<N, Q, Real>& tb, cons
 // As load_face_point, with the metric rows already permuted to the face's axes:
 // Jr = rows (t0, t1, d) of J^{-1}, so the physical gradient needs no per-lane
 // selection of reference components.
-// (For N > 8 the line loop is unrolled by four only: fully unrolled, the compiler loads
-// all 15 N operands ahead and spills.)
+// (The line loop is unrolled by four only where UnrollLimit says so: fully unrolled, the
+// compiler loads all 15 N operands ahead and spills.)
 template <int N, int Q, typename Real>
 __device__ __forceinline__ void load_face_point_rows(const KTab<N, Q, Real>& tb, const Real* A, int q0, int q1,
                                                      const Real (&Jr)[9], Real U[5], Real G[5][3]) {
-    constexpr int UF = N <= 8 ? N : 4;
+    constexpr int UF = UnrollLimit<N, Q, Real>::face ? 4 : N;
 #pragma unroll
     for (int c = 0; c < 5; ++c) {
         Real v = 0, g0 = 0, g1 = 0, gn = 0;
@@ -785,9 +802,9 @@ __device__ __forceinline__ void face_traces_sweep(const OpArgs& a, const KTab<N,
                 tn[ia] = tr[5 * N2 + ia];
             }
             Real* o = r1 + ((f * 2 + side) * 3 * 5 + c) * N * Q + ib * Q;
-            // (N > 8: the output loop is not unrolled, else the compiler loads the whole
-            // 2 n_q N table ahead and spills)
-            constexpr int UQ = N <= 8 ? Q : 1;
+            // (UnrollLimit: the output loop is not unrolled, else the compiler loads the
+            // whole 2 n_q N table ahead and spills)
+            constexpr int UQ = UnrollLimit<N, Q, Real>::face ? 1 : Q;
     #pragma unroll UQ
             for (int q0 = 0; q0 < Q; ++q0) {
                 Real a0 = 0, a1 = 0, an = 0;
@@ -1056,7 +1073,7 @@ dg_operator_kernel(OpArgs a, KTab<N, Q, Real> tb, MTab<N, Real> mt, EOTab<N, Q, 
 #pragma unroll
                 for (int c = 0; c < 5; ++c) {
                     Real v = 0, dx = 0, dy = 0, dz = 0;
-#pragma unroll
+#pragma unroll (UnrollLimit<N, Q, Real>::cell ? 3 : N)
                     for (int i = 0; i < N; ++i) {
                         const Real y00 = sY[((0 * 5 + c) * P + pl) * Q * N + py * N + i];
                         const Real y10 = sY[((1 * 5 + c) * P + pl) * Q * N + py * N + i];
