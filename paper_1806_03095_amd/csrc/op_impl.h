@@ -143,11 +143,21 @@ struct OpSizes {
 // 64 threads for n_q <= 4, else 128 or 256 as 3 n_q^2 requires.  The face terms move to
 // this kernel (SPLIT) for every (N, n_q, precision) where one pass covers the points
 // of the three faces and the plan fits a compute unit.
+// LDS layout of the face kernel's copy of the cell's coefficients: component stride CS
+// and xi_2-plane stride PS, padded where that spreads the trace phase's reads over the
+// banks (a model of the 64 banks: at N = 4 the fused trace reads take 160 bank passes
+// unpadded against 44 padded, at N = 6 192 against 146, at N = 8 1040 against 280).
+template <int N>
+struct FaceSU {
+    static constexpr int PS = N == 4 ? 17 : (N == 6 ? 37 : (N == 8 ? 67 : N * N));
+    static constexpr int CS = N == 4 ? 75 : (N == 6 ? 228 : (N == 8 ? 536 : N * N * N));
+};
+
 template <int N, int Q, typename Real>
 struct FaceBlock {
     static constexpr bool fused = N <= 4;
     template <int B>
-    static constexpr int lds_for = (FaceSizes<N, Q, B, 3, fused>::TOTAL + 5 * N * N * N + 2 * Q * N + Q + 4 * N) *
+    static constexpr int lds_for = (FaceSizes<N, Q, B, 3, fused>::TOTAL + 5 * FaceSU<N>::CS + 2 * Q * N + Q + 4 * N) *
                                        (int)sizeof(Real) + 1024;
     // 128 threads only while four workgroups fit in a compute unit's LDS (two waves per SIMD)
     static constexpr int threads = Q <= 4 ? 64 : (3 * Q * Q <= 128 && lds_for<128> <= 40 * 1024 ? 128 : 256);
@@ -689,11 +699,14 @@ __device__ __forceinline__ void face_point(const OpArgs& a, const KTab<N, Q, Rea
 // global memory; the neighbour's from global memory; nothing for the exterior side of a
 // wall), swept along t0: SW = sW [f][side][3][c][N][Q] (value, t0-derivative, normal
 // derivative), using the TR area of the layout FS for unfused traces.  Ends with a barrier.
-template <int N, int Q, typename Real, int NF, typename FS, bool OWNG = false>
+// The own coefficients in LDS are laid out [c][a2][a1][a0] with component stride CS and
+// a2-plane stride PS (N^3 and N^2 unless padded against bank conflicts, see FaceSU).
+template <int N, int Q, typename Real, int NF, typename FS, bool OWNG = false, int CS = N * N * N, int PS = N * N>
 __device__ __forceinline__ void face_traces_sweep(const OpArgs& a, const KTab<N, Q, Real>& lt, int s, int d0,
                                                   const FaceInfo& fi, const Real* sU, Real* sW) {
     constexpr int N2 = N * N, N3 = N2 * N;
     static_assert(!(OWNG && FS::FUSED_TRACE), "own coefficients from global memory: unfused traces only");
+    const auto lstr = [](int ax) { return ax == 0 ? 1 : (ax == 1 ? N : PS); };
     Real* r1 = sW;                 // SW
     const int tid = threadIdx.x, nth = blockDim.x;
     const int64_t cstride = a.ncell * N3;
@@ -714,12 +727,14 @@ __device__ __forceinline__ void face_traces_sweep(const OpArgs& a, const KTab<N,
             const int sd = axis_stride(d, N), st0 = axis_stride(t0, N), bb = ib * axis_stride(t1, N);
             Real tv[N], tn[N];
             if (side == 0) {
+                const Real* own = sU + c * CS + ib * lstr(t1);
+                const int lst0 = lstr(t0), lsd = lstr(d);
     #pragma unroll
                 for (int ia = 0; ia < N; ++ia) {
                     Real v = 0, n = 0;
     #pragma unroll
                     for (int m = 0; m < N; ++m) {
-                        const Real x = sU[c * N3 + bb + ia * st0 + m * sd];
+                        const Real x = own[ia * lst0 + m * lsd];
                         v += lt.fv[s][m] * x;
                         n += lt.fd[s][m] * x;
                     }
@@ -769,7 +784,7 @@ __device__ __forceinline__ void face_traces_sweep(const OpArgs& a, const KTab<N,
     #pragma unroll
             for (int m = 0; m < N; ++m) {
                 const Real x = OWNG ? (Real)a.U[c * cstride + (int64_t)blockIdx.x * N3 + base + m * sd]
-                                    : sU[c * N3 + base + m * sd];
+                                    : sU[c * CS + ia * lstr(t0) + ib * lstr(t1) + m * lstr(d)];
                 tv += lt.fv[s][m] * x;
                 tn += lt.fd[s][m] * x;
             }
@@ -1357,7 +1372,8 @@ dg_face_kernel(OpArgs a, KTab<N, Q, Real> tb) {
     using FS1 = typename FB::FS1;
     constexpr int N2 = N * N, N3 = N2 * N, Q2 = Q * Q, FWB = 2 * 5 * N2;
     static_assert(FB::one_pass && FS::ALIAS && FS1::ALIAS, "one face point per thread");
-    __shared__ Real sU[5 * N3];
+    constexpr int CS = FaceSU<N>::CS, PS = FaceSU<N>::PS;
+    __shared__ Real sU[5 * CS];
     __shared__ Real sW[FS::TOTAL];
     __shared__ FaceInfo fi;
     __shared__ Real sTau[6];
@@ -1373,7 +1389,10 @@ dg_face_kernel(OpArgs a, KTab<N, Q, Real> tb) {
     const int64_t cstride = a.ncell * N3;
     Real* fw = static_cast<Real*>(a.fw);
 
-    for (int i = tid; i < 5 * N3; i += blockDim.x) sU[i] = (Real)a.U[(i / N3) * cstride + e * N3 + i % N3];
+    for (int i = tid; i < 5 * N3; i += blockDim.x) {
+        const int c = i / N3, j = i % N3;
+        sU[c * CS + (j / N2) * PS + j % N2] = (Real)a.U[c * cstride + e * N3 + j];
+    }
     copy_table<KTab<N, Q, Real>, Real>(tb, lt);
     face_info_setup<Real, GEN>(a, e, fi, sTau, sFn, sJr);
     Real detJ = Real(1);
@@ -1381,7 +1400,7 @@ dg_face_kernel(OpArgs a, KTab<N, Q, Real> tb) {
     __syncthreads();
 
     // the three faces xi_d = 1, both sides
-    face_traces_sweep<N, Q, Real, 3, FS>(a, lt, 1, 0, fi, sU, sW);
+    face_traces_sweep<N, Q, Real, 3, FS, false, CS, PS>(a, lt, 1, 0, fi, sU, sW);
     Real res[20], res1[15];
     const bool act = tid < 3 * Q2;
     if (act) face_point<N, Q, Real, GEN, true>(a, lt, ph, conv, visc, 1, 0, fi, sTau, sFn, sJr, detJ, sW, tid, res, res1);
@@ -1410,7 +1429,7 @@ dg_face_kernel(OpArgs a, KTab<N, Q, Real> tb) {
     // wall faces xi_d = 0 (the lower end of a direction with walls): the own side only
     for (int d = 0; d < 3; ++d) {
         if (!fi.wall[d]) continue;   // uniform over the workgroup
-        face_traces_sweep<N, Q, Real, 1, FS1>(a, lt, 0, d, fi, sU, sW);
+        face_traces_sweep<N, Q, Real, 1, FS1, false, CS, PS>(a, lt, 0, d, fi, sU, sW);
         const bool act1 = tid < Q2;
         if (act1) face_point<N, Q, Real, GEN>(a, lt, ph, conv, visc, 0, d, fi, sTau, sFn, sJr, detJ, sW, tid, res, res1);
         __syncthreads();
