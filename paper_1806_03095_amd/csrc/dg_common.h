@@ -16,6 +16,15 @@ constexpr int kMaxN = 16;   // nodes per direction, k <= 15
 constexpr int kMaxQ = 16;   // quadrature points per direction
 constexpr int kBlock = 128; // threads per workgroup of the cell kernels
 
+// A compute unit's 160 KB of LDS taken as 128 granules of 1280 bytes, a workgroup holding
+// whole granules: measured, three workgroups of 54,272 bytes did not share a compute unit
+// (waves per busy cycle 11.8) while three of 51,200 bytes did (20.5).
+constexpr int kLdsGranule = 1280;
+constexpr int kLdsGranules = 128;
+__host__ __device__ constexpr int lds_wg_per_cu(int bytes) {
+    return kLdsGranules / ((bytes + kLdsGranule - 1) / kLdsGranule);
+}
+
 // 1D tables of one (k, n_q, basis) combination, float64 master copy.
 struct Tables1D {
     int n, q;

@@ -20,6 +20,8 @@
 // supported at these degrees (the API rejects them).
 #pragma once
 
+#include <type_traits>
+
 #include "dg_kernels.h"
 #include "minv_impl.h"
 
@@ -42,6 +44,20 @@ __device__ __forceinline__ void load_ktab(const Tables1D* t, KTab<N, Q, Real>& l
     }
 }
 
+// Cooperative fill of an even-odd table (see EOMat) from m(p, i), p < NO, i < NI.
+template <int NO, int NI, typename Real, typename Get>
+__device__ __forceinline__ void fill_eo_dev(EOMat<NO, NI, Real>& M, Get m) {
+    constexpr int HO = (NO + 1) / 2, HI = NI / 2 > 0 ? NI / 2 : 1;
+    for (int it = threadIdx.x; it < HO * HI; it += blockDim.x) {
+        const int p = it / HI, i = it % HI;
+        if (i < NI / 2) {
+            M.E[p][i] = (Real)(0.5 * (m(p, i) + m(p, NI - 1 - i)));
+            M.O[p][i] = (Real)(0.5 * (m(p, i) - m(p, NI - 1 - i)));
+        }
+    }
+    for (int p = threadIdx.x; p < HO; p += blockDim.x) M.C[p] = (NI % 2) ? (Real)m(p, NI / 2) : Real(0);
+}
+
 // LDS plan of the streamed cell kernel: PL planes per chunk, as many as keep the two
 // regions within about 60 KB (two workgroups, eight waves, per compute unit).
 template <int N, int Q, typename Real>
@@ -53,6 +69,12 @@ struct HdPlan {
     static constexpr int RA = 15 * PL * Q * Q;   // z-swept [2][5][PL][N^2], fluxes [5][3][PL][Q^2], E [2][5][PL][N^2]
     static constexpr int RB = 15 * PL * Q * N;   // y-swept [3][5][PL][Q][N], x-transposed [3][5][PL][Q][N]
     static_assert(Q >= N, "n_q >= k + 1");
+    // even-odd sweeps where their tables do not cost a workgroup per compute unit (k = 13
+    // in float64: 54,272 against 51,200 bytes, two against three workgroups; 1583 us per
+    // evaluation with them, 1280 us without)
+    static constexpr int LDS_NOEO = (RA + RB) * RS + (int)sizeof(KTab<N, Q, Real>) + 256;
+    static constexpr int LDS_EO = LDS_NOEO + (int)sizeof(EOTab<N, Q, Real>);
+    static constexpr bool EO = lds_wg_per_cu(LDS_EO) >= lds_wg_per_cu(LDS_NOEO);
 };
 
 // Cell term of the residual, streamed over the quadrature planes along xi_2 (see the
@@ -66,6 +88,10 @@ dg_cell_hd_kernel(OpArgs a) {
     __shared__ Real rA[HP::RA];
     __shared__ Real rB[HP::RB];
     __shared__ KTab<N, Q, Real> lt;
+    // even-odd forms of S and D for the y sweep and the transposed x and y sweeps
+    constexpr bool EO = HP::EO;
+    __shared__ std::conditional_t<EO, EOTab<N, Q, Real>, char> leo;
+    constexpr int HN = N / 2, HQ = Q / 2, HON = (N + 1) / 2, HOQ = (Q + 1) / 2;
     const int64_t e = blockIdx.x;
     const int tid = threadIdx.x, nth = blockDim.x;
     const Phys<Real> ph = make_phys<Real>(a);
@@ -75,6 +101,13 @@ dg_cell_hd_kernel(OpArgs a) {
     const double* Ue = a.U + e * N3;
     double* Re = a.out + e * N3;
     load_ktab<N, Q, Real>(a.tab_dev, lt);
+    if constexpr (EO) {
+        const Tables1D* t = a.tab_dev;
+        fill_eo_dev(leo.S, [&](int p, int i) { return t->S[p][i]; });
+        fill_eo_dev(leo.D, [&](int p, int i) { return t->D[p][i]; });
+        fill_eo_dev(leo.St, [&](int i, int p) { return t->S[p][i]; });
+        fill_eo_dev(leo.Dt, [&](int i, int p) { return t->D[p][i]; });
+    }
     Real Ji[9], detJ = Real(1);
     if constexpr (!GEN) {
 #pragma unroll
@@ -104,6 +137,38 @@ dg_cell_hd_kernel(OpArgs a) {
             }
         }
         __syncthreads();
+        if constexpr (EO) {
+        // y-sweep: Y00 = S_y Z0, Y10 = D_y Z0, Y01 = S_y Z1   rB [kind][c][pl][py][a0], one
+        // item per output pair (py, Q-1-py) in even-odd form
+        for (int it = tid; it < 5 * np * HOQ * N; it += nth) {
+            const int a0 = it % N, ph2 = (it / N) % HOQ, pl = (it / (N * HOQ)) % np, c = it / (N * HOQ * np);
+            const Real* z0p = rA + ((0 * 5 + c) * PL + pl) * N2 + a0;
+            const Real* z1p = rA + ((1 * 5 + c) * PL + pl) * N2 + a0;
+            Real z0[N], z1[N];
+#pragma unroll
+            for (int i = 0; i < N; ++i) {
+                z0[i] = z0p[i * N];
+                z1[i] = z1p[i * N];
+            }
+            Real e0[HN], o0[HN], e1[HN], o1[HN];
+            eo_split<N>(z0, e0, o0);
+            eo_split<N>(z1, e1, o1);
+            const int pm = Q - 1 - ph2;
+            Real* y00p = rB + ((0 * 5 + c) * PL + pl) * Q * N + a0;
+            Real* y10p = rB + ((1 * 5 + c) * PL + pl) * Q * N + a0;
+            Real* y01p = rB + ((2 * 5 + c) * PL + pl) * Q * N + a0;
+            Real ev, ov;
+            eo_row<Q, N>(leo.S, e0, o0, z0[N / 2], ph2, ev, ov);
+            y00p[ph2 * N] = ev + ov;
+            if (ph2 != pm) y00p[pm * N] = ev - ov;
+            eo_row<Q, N>(leo.D, e0, o0, z0[N / 2], ph2, ev, ov);
+            y10p[ph2 * N] = ev + ov;
+            if (ph2 != pm) y10p[pm * N] = ov - ev;
+            eo_row<Q, N>(leo.S, e1, o1, z1[N / 2], ph2, ev, ov);
+            y01p[ph2 * N] = ev + ov;
+            if (ph2 != pm) y01p[pm * N] = ev - ov;
+        }
+        } else {
         // y-sweep: Y00 = S_y Z0, Y10 = D_y Z0, Y01 = S_y Z1   rB [kind][c][pl][py][a0]
         for (int it = tid; it < 5 * np * Q * N; it += nth) {
             const int a0 = it % N, py = (it / N) % Q, pl = (it / (N * Q)) % np, c = it / (N * Q * np);
@@ -120,6 +185,7 @@ dg_cell_hd_kernel(OpArgs a) {
             rB[((0 * 5 + c) * PL + pl) * Q * N + py * N + a0] = y00;
             rB[((1 * 5 + c) * PL + pl) * Q * N + py * N + a0] = y10;
             rB[((2 * 5 + c) * PL + pl) * Q * N + py * N + a0] = y01;
+        }
         }
         __syncthreads();
         // x-sweep and pointwise physics, one point per item   rA [c][dim][pl][py][px]
@@ -183,6 +249,34 @@ dg_cell_hd_kernel(OpArgs a) {
                 }
         }
         __syncthreads();
+        if constexpr (EO) {
+        // x-transposed: B1 = D_x^T F_0, B2 = S_x^T F_1, B3 = S_x^T F_2   rB [kind][c][pl][py][a0],
+        // one item per output pair (a0, N-1-a0) in even-odd form
+        for (int it = tid; it < 5 * np * Q * HON; it += nth) {
+            const int ah = it % HON, py = (it / HON) % Q, pl = (it / (HON * Q)) % np, c = it / (HON * Q * np);
+            const int am = N - 1 - ah;
+            Real* bp = rB + (c * PL + pl) * Q * N + py * N;
+#pragma unroll
+            for (int m = 0; m < 3; ++m) {
+                const Real* fr = rA + ((c * 3 + m) * PL + pl) * Q2 + py * Q;
+                Real f[Q];
+#pragma unroll
+                for (int px = 0; px < Q; ++px) f[px] = fr[px];
+                Real ve[HQ], vo[HQ], ev, ov;
+                eo_split<Q>(f, ve, vo);
+                Real* b = bp + m * 5 * PL * Q * N;
+                if (m == 0) {
+                    eo_row<N, Q>(leo.Dt, ve, vo, f[Q / 2], ah, ev, ov);
+                    b[ah] = ev + ov;
+                    if (ah != am) b[am] = ov - ev;
+                } else {
+                    eo_row<N, Q>(leo.St, ve, vo, f[Q / 2], ah, ev, ov);
+                    b[ah] = ev + ov;
+                    if (ah != am) b[am] = ev - ov;
+                }
+            }
+        }
+        } else {
         // x-transposed: B1 = D_x^T F_0, B2 = S_x^T F_1, B3 = S_x^T F_2   rB [kind][c][pl][py][a0]
         for (int it = tid; it < 5 * np * Q * N; it += nth) {
             const int a0 = it % N, py = (it / N) % Q, pl = (it / (N * Q)) % np, c = it / (N * Q * np);
@@ -200,7 +294,39 @@ dg_cell_hd_kernel(OpArgs a) {
             rB[((1 * 5 + c) * PL + pl) * Q * N + py * N + a0] = b2;
             rB[((2 * 5 + c) * PL + pl) * Q * N + py * N + a0] = b3;
         }
+        }
         __syncthreads();
+        if constexpr (EO) {
+        // y-transposed: E1 = S_y^T B1 + D_y^T B2, E2 = S_y^T B3   rA [kind][c][pl][a1][a0], one
+        // item per output pair (a1, N-1-a1) in even-odd form
+        for (int it = tid; it < 5 * np * N * HON; it += nth) {
+            const int a0 = it % N, ah = (it / N) % HON, pl = (it / (N * HON)) % np, c = it / (N * HON * np);
+            const int am = N - 1 - ah;
+            Real ve[HQ], vo[HQ], es, os, ed, od;
+            Real bv[Q];
+            const Real* b1 = rB + ((0 * 5 + c) * PL + pl) * Q * N + a0;
+            const Real* b2 = rB + ((1 * 5 + c) * PL + pl) * Q * N + a0;
+            const Real* b3 = rB + ((2 * 5 + c) * PL + pl) * Q * N + a0;
+#pragma unroll
+            for (int py = 0; py < Q; ++py) bv[py] = b1[py * N];
+            eo_split<Q>(bv, ve, vo);
+            eo_row<N, Q>(leo.St, ve, vo, bv[Q / 2], ah, es, os);
+#pragma unroll
+            for (int py = 0; py < Q; ++py) bv[py] = b2[py * N];
+            eo_split<Q>(bv, ve, vo);
+            eo_row<N, Q>(leo.Dt, ve, vo, bv[Q / 2], ah, ed, od);
+            Real* e1p = rA + ((0 * 5 + c) * PL + pl) * N2 + a0;
+            Real* e2p = rA + ((1 * 5 + c) * PL + pl) * N2 + a0;
+            e1p[ah * N] = (es + os) + (ed + od);
+            if (ah != am) e1p[am * N] = (es - os) + (od - ed);
+#pragma unroll
+            for (int py = 0; py < Q; ++py) bv[py] = b3[py * N];
+            eo_split<Q>(bv, ve, vo);
+            eo_row<N, Q>(leo.St, ve, vo, bv[Q / 2], ah, es, os);
+            e2p[ah * N] = es + os;
+            if (ah != am) e2p[am * N] = es - os;
+        }
+        } else {
         // y-transposed: E1 = S_y^T B1 + D_y^T B2, E2 = S_y^T B3   rA [kind][c][pl][a1][a0]
         for (int it = tid; it < 5 * np * N2; it += nth) {
             const int a0 = it % N, a1 = (it / N) % N, pl = (it / N2) % np, c = it / (N2 * np);
@@ -215,6 +341,7 @@ dg_cell_hd_kernel(OpArgs a) {
             }
             rA[((0 * 5 + c) * PL + pl) * N2 + a1 * N + a0] = e1;
             rA[((1 * 5 + c) * PL + pl) * N2 + a1 * N + a0] = e2;
+        }
         }
         __syncthreads();
         // z-transposed into the cell's rows of the output: R (+)= S_z^T E1 + D_z^T E2

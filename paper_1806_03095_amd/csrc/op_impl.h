@@ -100,7 +100,12 @@ struct OpSizes {
                                   2 * ((Q + 1) / 2) * (2 * (N / 2 > 0 ? N / 2 : 1) + 1) +
                                   2 * ((N + 1) / 2) * (2 * (Q / 2 > 0 ? Q / 2 : 1) + 1);
     static constexpr int LDS_MAX = 160 * 1024;
-    static constexpr int TARGET = LDS_MAX / (8 * 64 / B);   // LDS per workgroup at eight waves per CU
+    // LDS per workgroup at eight waves per CU; for the float32 kernels whose registers allow
+    // more, fewer planes per chunk for 12 or 16 waves where that measured faster (k=3, n_q=6
+    // and 7: 467 -> 443 and 795 -> 646 us; k=4, n_q=6 and 7: 431 -> 401 and 606 -> 582 us;
+    // elsewhere the extra chunks cost more than the occupancy gains, up to 19%)
+    static constexpr int WAVES_CU = RS != 4 ? 8 : ((N == 4 && (Q == 6 || Q == 7)) ? 16 : ((N == 5 && (Q == 6 || Q == 7)) ? 12 : 8));
+    static constexpr int TARGET = kLdsGranules / (WAVES_CU * 64 / B) * kLdsGranule;
     static constexpr int cell(int p) { return 10 * Q * N * N + 15 * p * Q * (N + Q); }
     // the face phases, or with the face terms in a kernel of their own (SPLIT) the staging
     // of the cell's six lifted face blocks
@@ -115,7 +120,7 @@ struct OpSizes {
     static constexpr int fewer(int nf, int p) { return p <= 1 || lds(nf, p) <= TARGET ? p : fewer(nf, p - 1); }
     // waves per SIMD that the LDS footprint allows, at most two (the register budget)
     static constexpr int waves(int bytes) {
-        return (LDS_MAX / bytes) * (B / 64) / 4 < 2 ? (LDS_MAX / bytes) * (B / 64) / 4 : 2;
+        return lds_wg_per_cu(bytes) * (B / 64) / 4 < 2 ? lds_wg_per_cu(bytes) * (B / 64) / 4 : 2;
     }
     static constexpr int P0 = SPLIT ? Q : ChooseP<N, Q>::v;
     static constexpr bool REACH3 = lds(3, fewer(3, P0)) <= TARGET;
