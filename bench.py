@@ -106,12 +106,20 @@ def time_operator(op, U, L, calls):
     return e0.elapsed_time(e1) / 1e3 / calls
 
 
-def time_call(fn, calls):
-    """Average seconds per call of fn() (HIP events on the current stream)."""
+def time_call(fn, calls, warm_s=0.0):
+    """Average seconds per call of fn() (HIP events on the current stream), after three
+    untimed calls and, with warm_s > 0, further untimed calls for at least warm_s seconds
+    (a GPU coming out of idle runs its first tens of milliseconds of streaming kernels up
+    to 12% slower)."""
     import torch
     for _ in range(3):
         fn()
     torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    while time.perf_counter() - t0 < warm_s:
+        for _ in range(10):
+            fn()
+        torch.cuda.synchronize()
     e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
     e0.record()
     for _ in range(calls):
@@ -127,7 +135,7 @@ def copy_bandwidth(mib=1024, calls=20):
     n = mib * (1 << 20) // 8
     a = torch.ones(n, dtype=torch.float64, device="cuda")
     b = torch.empty_like(a)
-    t = time_call(lambda: b.copy_(a), calls)
+    t = time_call(lambda: b.copy_(a), calls, warm_s=0.1)
     return 2 * 8 * n / t
 
 
@@ -299,9 +307,9 @@ def memops_streamed(calls=20):
         op = taylor_green(k, ne)
         U = torch.rand(op.shape, dtype=torch.float64, device="cuda") + 1.0
         L = torch.empty_like(U)
-        t_m = time_call(lambda: op.inverse_mass(U, L), calls)
+        t_m = time_call(lambda: op.inverse_mass(U, L), calls, warm_s=0.1)
         dU = torch.zeros_like(U)
-        t_u = time_call(lambda: op.rk_stage_update(U, dU, L, 1, 1e-12), calls)
+        t_u = time_call(lambda: op.rk_stage_update(U, dU, L, 1, 1e-12), calls, warm_s=0.1)
         row = {"k": k, "cells": ne ** 3, "n_dof": op.n_dof, "vector_MB": 8e-6 * op.n_dof,
                "M_inv_us": 1e6 * t_m, "M_inv_hbm_frac": 16 * op.n_dof / t_m / PEAK_HBM,
                "M_inv_frac_of_copy": 16 * op.n_dof / t_m / bw,
