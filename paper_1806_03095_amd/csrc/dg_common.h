@@ -44,8 +44,12 @@ struct Tables1D {
 // registers for a whole kernel, the larger tables spill).
 template <int N, int Q, typename Real>
 struct KTab {
-    Real S[Q][N];
-    Real D[Q][N];
+    // rows of 16 values (k = 15) padded by one: a wave's points read the rows of up to 16
+    // quadrature points at once, and rows 128 (64) bytes apart put 8 (4) of them on the
+    // same banks (measured at k = 15 in float64: cell kernel 1452 -> 1019 us)
+    static constexpr int NP = N % 16 == 0 ? N + 1 : N;
+    Real S[Q][NP];
+    Real D[Q][NP];
     Real w[Q];
     Real fv[2][N];
     Real fd[2][N];

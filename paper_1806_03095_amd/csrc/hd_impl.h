@@ -59,15 +59,25 @@ __device__ __forceinline__ void fill_eo_dev(EOMat<NO, NI, Real>& M, Get m) {
 }
 
 // LDS plan of the streamed cell kernel: PL planes per chunk, as many as keep the two
-// regions within about 60 KB (two workgroups, eight waves, per compute unit).
+// regions within about 60 KB (two workgroups, eight waves, per compute unit).  Rows of
+// the flux arrays (pitch FP, over px) and of the y-swept / x-transposed arrays (pitch BP,
+// over a0) that are a multiple of 128 bytes long are padded by one value: the sweeps
+// read and write eight or more rows at once per wave, and with a pitch of 128 bytes
+// every other row starts on the same bank (n_q = 16 in float64: the eight flux rows that
+// a wave of the transposed x sweep reads fall on two bank positions).  Rows of 64 bytes
+// (every fourth row aliased) stay unpadded: at k = 7, n_q = 11 in float64 and k = 10,
+// n_q = 16 in float32 the padding would cost a workgroup per compute unit.
 template <int N, int Q, typename Real>
 struct HdPlan {
     static constexpr int RS = (int)sizeof(Real);
-    static constexpr int per_plane(int p) { return 15 * p * Q * (Q + N); }
+    static constexpr int FP = Q * RS % 128 == 0 ? Q + 1 : Q;
+    static constexpr int BP = N * RS % 128 == 0 ? N + 1 : N;
+    static constexpr int per_plane(int p) { return 15 * p * Q * (FP + BP); }
     static constexpr int fit(int p) { return p <= 1 ? 1 : (per_plane(p) * RS <= 60 * 1024 ? p : fit(p - 1)); }
     static constexpr int PL = fit(Q);
-    static constexpr int RA = 15 * PL * Q * Q;   // z-swept [2][5][PL][N^2], fluxes [5][3][PL][Q^2], E [2][5][PL][N^2]
-    static constexpr int RB = 15 * PL * Q * N;   // y-swept [3][5][PL][Q][N], x-transposed [3][5][PL][Q][N]
+    static constexpr int RA = 15 * PL * Q * FP;  // z-swept [2][5][PL][N^2], fluxes [5][3][PL][Q][FP], E [2][5][PL][N^2]
+    static constexpr int RB = 15 * PL * Q * BP;  // y-swept [3][5][PL][Q][BP], x-transposed [3][5][PL][Q][BP]
+    static_assert(Q * FP >= N * N, "z-swept and E planes inside the flux planes");
     static_assert(Q >= N, "n_q >= k + 1");
     // even-odd sweeps where their tables do not cost a workgroup per compute unit (k = 13
     // in float64: 54,272 against 51,200 bytes, two against three workgroups; 1583 us per
@@ -84,6 +94,7 @@ __global__ void __launch_bounds__(kHdBlock) __attribute__((amdgpu_waves_per_eu(2
 dg_cell_hd_kernel(OpArgs a) {
     using HP = HdPlan<N, Q, Real>;
     constexpr int PL = HP::PL;
+    constexpr int FP = HP::FP, BP = HP::BP, FPL = Q * FP, BPL = Q * BP;   // row pitches and plane sizes
     constexpr int N2 = N * N, N3 = N2 * N, Q2 = Q * Q, Q3 = Q2 * Q, FWB = 2 * 5 * N2;
     __shared__ Real rA[HP::RA];
     __shared__ Real rB[HP::RB];
@@ -154,19 +165,19 @@ dg_cell_hd_kernel(OpArgs a) {
             eo_split<N>(z0, e0, o0);
             eo_split<N>(z1, e1, o1);
             const int pm = Q - 1 - ph2;
-            Real* y00p = rB + ((0 * 5 + c) * PL + pl) * Q * N + a0;
-            Real* y10p = rB + ((1 * 5 + c) * PL + pl) * Q * N + a0;
-            Real* y01p = rB + ((2 * 5 + c) * PL + pl) * Q * N + a0;
+            Real* y00p = rB + ((0 * 5 + c) * PL + pl) * BPL + a0;
+            Real* y10p = rB + ((1 * 5 + c) * PL + pl) * BPL + a0;
+            Real* y01p = rB + ((2 * 5 + c) * PL + pl) * BPL + a0;
             Real ev, ov;
             eo_row<Q, N>(leo.S, e0, o0, z0[N / 2], ph2, ev, ov);
-            y00p[ph2 * N] = ev + ov;
-            if (ph2 != pm) y00p[pm * N] = ev - ov;
+            y00p[ph2 * BP] = ev + ov;
+            if (ph2 != pm) y00p[pm * BP] = ev - ov;
             eo_row<Q, N>(leo.D, e0, o0, z0[N / 2], ph2, ev, ov);
-            y10p[ph2 * N] = ev + ov;
-            if (ph2 != pm) y10p[pm * N] = ov - ev;
+            y10p[ph2 * BP] = ev + ov;
+            if (ph2 != pm) y10p[pm * BP] = ov - ev;
             eo_row<Q, N>(leo.S, e1, o1, z1[N / 2], ph2, ev, ov);
-            y01p[ph2 * N] = ev + ov;
-            if (ph2 != pm) y01p[pm * N] = ev - ov;
+            y01p[ph2 * BP] = ev + ov;
+            if (ph2 != pm) y01p[pm * BP] = ev - ov;
         }
         } else {
         // y-sweep: Y00 = S_y Z0, Y10 = D_y Z0, Y01 = S_y Z1   rB [kind][c][pl][py][a0]
@@ -182,9 +193,9 @@ dg_cell_hd_kernel(OpArgs a) {
                 y10 += lt.D[py][i] * z0;
                 y01 += lt.S[py][i] * z1;
             }
-            rB[((0 * 5 + c) * PL + pl) * Q * N + py * N + a0] = y00;
-            rB[((1 * 5 + c) * PL + pl) * Q * N + py * N + a0] = y10;
-            rB[((2 * 5 + c) * PL + pl) * Q * N + py * N + a0] = y01;
+            rB[((0 * 5 + c) * PL + pl) * BPL + py * BP + a0] = y00;
+            rB[((1 * 5 + c) * PL + pl) * BPL + py * BP + a0] = y10;
+            rB[((2 * 5 + c) * PL + pl) * BPL + py * BP + a0] = y01;
         }
         }
         __syncthreads();
@@ -194,9 +205,9 @@ dg_cell_hd_kernel(OpArgs a) {
             Real Uq[5], Gr[5][3];
 #pragma unroll
             for (int c = 0; c < 5; ++c) {
-                const Real* y00p = rB + ((0 * 5 + c) * PL + pl) * Q * N + py * N;
-                const Real* y10p = rB + ((1 * 5 + c) * PL + pl) * Q * N + py * N;
-                const Real* y01p = rB + ((2 * 5 + c) * PL + pl) * Q * N + py * N;
+                const Real* y00p = rB + ((0 * 5 + c) * PL + pl) * BPL + py * BP;
+                const Real* y10p = rB + ((1 * 5 + c) * PL + pl) * BPL + py * BP;
+                const Real* y01p = rB + ((2 * 5 + c) * PL + pl) * BPL + py * BP;
                 Real v = 0, dx = 0, dy = 0, dz = 0;
 #pragma unroll 4
                 for (int i = 0; i < N; ++i) {
@@ -245,7 +256,7 @@ dg_cell_hd_kernel(OpArgs a) {
 #pragma unroll
                 for (int d = 0; d < 3; ++d) {
                     const Real fr = J[d * 3 + 0] * F[c][0] + J[d * 3 + 1] * F[c][1] + J[d * 3 + 2] * F[c][2];
-                    rA[((c * 3 + d) * PL + pl) * Q2 + py * Q + px] = jxw * fr;
+                    rA[((c * 3 + d) * PL + pl) * FPL + py * FP + px] = jxw * fr;
                 }
         }
         __syncthreads();
@@ -255,16 +266,16 @@ dg_cell_hd_kernel(OpArgs a) {
         for (int it = tid; it < 5 * np * Q * HON; it += nth) {
             const int ah = it % HON, py = (it / HON) % Q, pl = (it / (HON * Q)) % np, c = it / (HON * Q * np);
             const int am = N - 1 - ah;
-            Real* bp = rB + (c * PL + pl) * Q * N + py * N;
+            Real* bp = rB + (c * PL + pl) * BPL + py * BP;
 #pragma unroll
             for (int m = 0; m < 3; ++m) {
-                const Real* fr = rA + ((c * 3 + m) * PL + pl) * Q2 + py * Q;
+                const Real* fr = rA + ((c * 3 + m) * PL + pl) * FPL + py * FP;
                 Real f[Q];
 #pragma unroll
                 for (int px = 0; px < Q; ++px) f[px] = fr[px];
                 Real ve[HQ], vo[HQ], ev, ov;
                 eo_split<Q>(f, ve, vo);
-                Real* b = bp + m * 5 * PL * Q * N;
+                Real* b = bp + m * 5 * PL * BPL;
                 if (m == 0) {
                     eo_row<N, Q>(leo.Dt, ve, vo, f[Q / 2], ah, ev, ov);
                     b[ah] = ev + ov;
@@ -280,9 +291,9 @@ dg_cell_hd_kernel(OpArgs a) {
         // x-transposed: B1 = D_x^T F_0, B2 = S_x^T F_1, B3 = S_x^T F_2   rB [kind][c][pl][py][a0]
         for (int it = tid; it < 5 * np * Q * N; it += nth) {
             const int a0 = it % N, py = (it / N) % Q, pl = (it / (N * Q)) % np, c = it / (N * Q * np);
-            const Real* f0 = rA + ((c * 3 + 0) * PL + pl) * Q2 + py * Q;
-            const Real* f1 = rA + ((c * 3 + 1) * PL + pl) * Q2 + py * Q;
-            const Real* f2 = rA + ((c * 3 + 2) * PL + pl) * Q2 + py * Q;
+            const Real* f0 = rA + ((c * 3 + 0) * PL + pl) * FPL + py * FP;
+            const Real* f1 = rA + ((c * 3 + 1) * PL + pl) * FPL + py * FP;
+            const Real* f2 = rA + ((c * 3 + 2) * PL + pl) * FPL + py * FP;
             Real b1 = 0, b2 = 0, b3 = 0;
 #pragma unroll
             for (int px = 0; px < Q; ++px) {
@@ -290,9 +301,9 @@ dg_cell_hd_kernel(OpArgs a) {
                 b2 += lt.S[px][a0] * f1[px];
                 b3 += lt.S[px][a0] * f2[px];
             }
-            rB[((0 * 5 + c) * PL + pl) * Q * N + py * N + a0] = b1;
-            rB[((1 * 5 + c) * PL + pl) * Q * N + py * N + a0] = b2;
-            rB[((2 * 5 + c) * PL + pl) * Q * N + py * N + a0] = b3;
+            rB[((0 * 5 + c) * PL + pl) * BPL + py * BP + a0] = b1;
+            rB[((1 * 5 + c) * PL + pl) * BPL + py * BP + a0] = b2;
+            rB[((2 * 5 + c) * PL + pl) * BPL + py * BP + a0] = b3;
         }
         }
         __syncthreads();
@@ -304,15 +315,15 @@ dg_cell_hd_kernel(OpArgs a) {
             const int am = N - 1 - ah;
             Real ve[HQ], vo[HQ], es, os, ed, od;
             Real bv[Q];
-            const Real* b1 = rB + ((0 * 5 + c) * PL + pl) * Q * N + a0;
-            const Real* b2 = rB + ((1 * 5 + c) * PL + pl) * Q * N + a0;
-            const Real* b3 = rB + ((2 * 5 + c) * PL + pl) * Q * N + a0;
+            const Real* b1 = rB + ((0 * 5 + c) * PL + pl) * BPL + a0;
+            const Real* b2 = rB + ((1 * 5 + c) * PL + pl) * BPL + a0;
+            const Real* b3 = rB + ((2 * 5 + c) * PL + pl) * BPL + a0;
 #pragma unroll
-            for (int py = 0; py < Q; ++py) bv[py] = b1[py * N];
+            for (int py = 0; py < Q; ++py) bv[py] = b1[py * BP];
             eo_split<Q>(bv, ve, vo);
             eo_row<N, Q>(leo.St, ve, vo, bv[Q / 2], ah, es, os);
 #pragma unroll
-            for (int py = 0; py < Q; ++py) bv[py] = b2[py * N];
+            for (int py = 0; py < Q; ++py) bv[py] = b2[py * BP];
             eo_split<Q>(bv, ve, vo);
             eo_row<N, Q>(leo.Dt, ve, vo, bv[Q / 2], ah, ed, od);
             Real* e1p = rA + ((0 * 5 + c) * PL + pl) * N2 + a0;
@@ -320,7 +331,7 @@ dg_cell_hd_kernel(OpArgs a) {
             e1p[ah * N] = (es + os) + (ed + od);
             if (ah != am) e1p[am * N] = (es - os) + (od - ed);
 #pragma unroll
-            for (int py = 0; py < Q; ++py) bv[py] = b3[py * N];
+            for (int py = 0; py < Q; ++py) bv[py] = b3[py * BP];
             eo_split<Q>(bv, ve, vo);
             eo_row<N, Q>(leo.St, ve, vo, bv[Q / 2], ah, es, os);
             e2p[ah * N] = es + os;
@@ -330,14 +341,14 @@ dg_cell_hd_kernel(OpArgs a) {
         // y-transposed: E1 = S_y^T B1 + D_y^T B2, E2 = S_y^T B3   rA [kind][c][pl][a1][a0]
         for (int it = tid; it < 5 * np * N2; it += nth) {
             const int a0 = it % N, a1 = (it / N) % N, pl = (it / N2) % np, c = it / (N2 * np);
-            const Real* b1 = rB + ((0 * 5 + c) * PL + pl) * Q * N + a0;
-            const Real* b2 = rB + ((1 * 5 + c) * PL + pl) * Q * N + a0;
-            const Real* b3 = rB + ((2 * 5 + c) * PL + pl) * Q * N + a0;
+            const Real* b1 = rB + ((0 * 5 + c) * PL + pl) * BPL + a0;
+            const Real* b2 = rB + ((1 * 5 + c) * PL + pl) * BPL + a0;
+            const Real* b3 = rB + ((2 * 5 + c) * PL + pl) * BPL + a0;
             Real e1 = 0, e2 = 0;
 #pragma unroll
             for (int py = 0; py < Q; ++py) {
-                e1 += lt.S[py][a1] * b1[py * N] + lt.D[py][a1] * b2[py * N];
-                e2 += lt.S[py][a1] * b3[py * N];
+                e1 += lt.S[py][a1] * b1[py * BP] + lt.D[py][a1] * b2[py * BP];
+                e2 += lt.S[py][a1] * b3[py * BP];
             }
             rA[((0 * 5 + c) * PL + pl) * N2 + a1 * N + a0] = e1;
             rA[((1 * 5 + c) * PL + pl) * N2 + a1 * N + a0] = e2;
@@ -453,28 +464,75 @@ dg_face_hd_kernel(OpArgs a) {
 
 // Stand-alone inverse mass of the high degrees: RPB = 256 / N^2 (component, cell) blocks per
 // workgroup (3 at N = 9, 2 at N = 10, 11, else 1), one line of N values per thread and axis,
-// tables from the device copy.
-template <int N>
+// tables from the device copy.  In LDS a block is stored with x-lines XP values apart and
+// xi_2-planes YP apart; an x-line of 64 or 128 bytes (N = 16) is padded by one value, since
+// consecutive threads own consecutive lines and would otherwise fall on 4 or 2 bank positions.
+template <int N, typename Real>
 struct MinvHdPlan {
     static constexpr int RPB = kHdBlock / (N * N) > 0 ? kHdBlock / (N * N) : 1;
+    // the whole inverse in registers while it fits (float32, N <= 11: 3-5% faster there),
+    // else one output at a time from LDS
+    static constexpr bool REG = sizeof(Real) == 4 && N <= 11;
+    static constexpr int XP = N * (int)sizeof(Real) % 64 == 0 ? N + 1 : N;
+    static constexpr int YP = N * XP;
+    static constexpr int BS = N * YP;
 };
+
+// One line of the inverse mass: out(o, sum_m M[o][m] v[m]) for o < N, from the row o of M,
+// which the caller passes transposed for M^T; the line's input stays in registers, so the
+// outputs may overwrite it in place.  REG: completely unrolled (all of M in registers);
+// otherwise one output at a time (unrolled by two), since holding M in registers exceeds
+// the register file for N >= 11 in float64.
+template <int N, bool REG, typename Real, typename Put>
+__device__ __forceinline__ void minv_line_hd(const Real (&M)[N][N], const Real (&v)[N], Put put) {
+    if constexpr (REG) {
+        Real t[N];
+#pragma unroll
+        for (int o = 0; o < N; ++o) {
+            Real acc = 0;
+#pragma unroll
+            for (int m = 0; m < N; ++m) acc += M[o][m] * v[m];
+            t[o] = acc;
+        }
+#pragma unroll
+        for (int o = 0; o < N; ++o) put(o, t[o]);
+    } else {
+#pragma unroll 2
+        for (int o = 0; o < N; ++o) {
+            Real acc = 0;
+#pragma unroll
+            for (int m = 0; m < N; ++m) acc += M[o][m] * v[m];
+            put(o, acc);
+        }
+    }
+}
 
 template <int N, typename Real, bool GEN>
 __global__ void __launch_bounds__(kHdBlock)
 inverse_mass_hd_kernel(const double* R, double* L, int64_t ncell, const double* cell_metric, const double* mass_jxw,
                        const Tables1D* t) {
-    constexpr int N2 = N * N, N3 = N2 * N, RPB = MinvHdPlan<N>::RPB;
+    using MP = MinvHdPlan<N, Real>;
+    constexpr int N2 = N * N, N3 = N2 * N, RPB = MP::RPB, XP = MP::XP, YP = MP::YP;
     static_assert(N2 <= kHdBlock, "one line per thread");
-    __shared__ Real buf[RPB * N3];
-    __shared__ Real Smi[N][N];
+    __shared__ Real buf[RPB * MP::BS];
+    __shared__ Real Smi[N][N];    // S^{-1}
+    __shared__ Real SmiT[N][N];   // its transpose
     __shared__ Real lwm[N];
     const int tid = threadIdx.x;
-    for (int i = tid; i < N2; i += blockDim.x) Smi[i / N][i % N] = (Real)t->Smi[i / N][i % N];
+    for (int i = tid; i < N2; i += blockDim.x) {
+        Smi[i / N][i % N] = (Real)t->Smi[i / N][i % N];
+        SmiT[i % N][i / N] = (Real)t->Smi[i / N][i % N];
+    }
     if (tid < N) lwm[tid] = (Real)t->wm[tid];
-    const int lb = tid / N2, ln = tid % N2;
+    const int lb = tid / N2, ln = tid % N2, l0 = ln % N, l1 = ln / N;
     const int64_t row = (int64_t)blockIdx.x * RPB + lb;   // c * ncell + e
     const bool act = lb < RPB && row < 5 * ncell;
-    Real* blk = buf + lb * N3;
+    Real* blk = buf + lb * MP::BS;
+    // the thread's line along x (a1 = l0, a2 = l1), along y (a0 = l0, a2 = l1) and along
+    // z (a0 = l0, a1 = l1) in the LDS block
+    Real* xl = blk + l0 * XP + l1 * YP;
+    Real* yl = blk + l0 + l1 * YP;
+    Real* zl = blk + l0 + l1 * XP;
     Real v[N];
     if (act) {
         const double* src = R + row * N3 + ln * N;
@@ -482,50 +540,51 @@ inverse_mass_hd_kernel(const double* R, double* L, int64_t ncell, const double* 
         for (int m = 0; m < N; ++m) v[m] = (Real)src[m];
     }
     __syncthreads();
+    if (act) minv_line_hd<N, MP::REG>(SmiT, v, [&](int o, Real r) { xl[o] = r; });
+    __syncthreads();
     if (act) {
-        apply_line<N, true>(Smi, v);
 #pragma unroll
-        for (int m = 0; m < N; ++m) blk[ln * N + m] = v[m];
+        for (int m = 0; m < N; ++m) v[m] = yl[m * XP];
+        minv_line_hd<N, MP::REG>(SmiT, v, [&](int o, Real r) { yl[o * XP] = r; });
     }
     __syncthreads();
-    if (act) minv_sweep<N, 1, true>(Smi, blk, ln);
-    __syncthreads();
     if (act) {
-        const int z0 = ln % N, z1 = ln / N;
+        // z: S^{-T}, the diagonal 1 / (|J| w) at the mass points, then S^{-1}, on the
+        // thread's own line (its writes are visible to its own later reads)
 #pragma unroll
-        for (int m = 0; m < N; ++m) v[m] = blk[m * N2 + ln];
-        apply_line<N, true>(Smi, v);
+        for (int m = 0; m < N; ++m) v[m] = zl[m * YP];
+        minv_line_hd<N, MP::REG>(SmiT, v, [&](int o, Real r) { zl[o * YP] = r; });
         const int64_t e = row % ncell;
         if constexpr (GEN) {
             const double* jw = mass_jxw + e * N3 + ln;
 #pragma unroll
-            for (int m = 0; m < N; ++m) v[m] = v[m] / (Real)jw[m * N2];
+            for (int m = 0; m < N; ++m) v[m] = zl[m * YP] / (Real)jw[m * N2];
         } else {
-            const Real f = Real(1) / ((Real)cell_metric[e * 10 + 9] * lwm[z0] * lwm[z1]);
+            const Real f = Real(1) / ((Real)cell_metric[e * 10 + 9] * lwm[l0] * lwm[l1]);
 #pragma unroll
-            for (int m = 0; m < N; ++m) v[m] = v[m] * (f / lwm[m]);
+            for (int m = 0; m < N; ++m) v[m] = zl[m * YP] * (f / lwm[m]);
         }
-        apply_line<N, false>(Smi, v);
-#pragma unroll
-        for (int m = 0; m < N; ++m) blk[m * N2 + ln] = v[m];
+        minv_line_hd<N, MP::REG>(Smi, v, [&](int o, Real r) { zl[o * YP] = r; });
     }
-    __syncthreads();
-    if (act) minv_sweep<N, 1, false>(Smi, blk, ln);
     __syncthreads();
     if (act) {
 #pragma unroll
-        for (int m = 0; m < N; ++m) v[m] = blk[ln * N + m];
-        apply_line<N, false>(Smi, v);
-        double* dst = L + row * N3 + ln * N;
+        for (int m = 0; m < N; ++m) v[m] = yl[m * XP];
+        minv_line_hd<N, MP::REG>(Smi, v, [&](int o, Real r) { yl[o * XP] = r; });
+    }
+    __syncthreads();
+    if (act) {
 #pragma unroll
-        for (int m = 0; m < N; ++m) dst[m] = (double)v[m];
+        for (int m = 0; m < N; ++m) v[m] = xl[m];
+        double* dst = L + row * N3 + ln * N;
+        minv_line_hd<N, MP::REG>(Smi, v, [&](int o, Real r) { dst[o] = (double)r; });
     }
 }
 
 template <int N, typename Real, bool GEN>
 inline int launch_minv_hd_t(const double* R, double* L, int64_t ncell, const double* cm, const double* mj,
                             const Tables1D* t_dev, hipStream_t st) {
-    constexpr int RPB = MinvHdPlan<N>::RPB;
+    constexpr int RPB = MinvHdPlan<N, Real>::RPB;
     const int64_t grid = (5 * ncell + RPB - 1) / RPB;
     hipLaunchKernelGGL((inverse_mass_hd_kernel<N, Real, GEN>), dim3((unsigned)grid), dim3(kHdBlock), 0, st, R, L,
                        ncell, cm, mj, t_dev);

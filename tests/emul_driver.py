@@ -12,8 +12,9 @@ EMU = os.path.join(ROOT, "tests", "emul")
 CSRC = os.path.join(ROOT, "paper_1806_03095_amd", "csrc")
 BUILD = os.path.join(EMU, "_build")
 CASES = [(1, 2), (2, 3), (3, 6), (4, 5), (4, 7), (7, 11)]
-# degrees >= 8 (hd_impl.h): residual, operator and stand-alone inverse mass
-HD_CASES = [(8, 9)]
+# degrees >= 8 (hd_impl.h): residual, operator and stand-alone inverse mass; k = 15 for the
+# padded LDS rows of n_q = 16 and N = 16 in float64 (and the unpadded float32 ones)
+HD_CASES = [(8, 9), (15, 16)]
 
 
 def build():

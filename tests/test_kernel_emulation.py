@@ -236,3 +236,28 @@ def test_emulated_high_degree(n, kind, amp, basis):
     errs = rel_err_fields(torch.as_tensor(R32), R64)
     for c in range(5):
         assert errs[c] <= 50 * cast[c], (c, errs, cast)
+
+
+def test_emulated_degree_15_padded_rows():
+    # degree 15, n_q = 16: the streamed cell kernel's flux and y-swept rows and the
+    # stand-alone inverse mass's x-lines are padded in float64 (128-byte rows); R and L per
+    # field within 1e-12 ((k+1)/4)^4 (L: 10 times) of the oracle as on the GPU, M^{-1} by its
+    # backward error, float32 R within 50 times the input-rounding floor
+    k, nq, n = 15, 16, (2, 1, 1)
+    fl, oop, U = _tgv_case(n, k, nq)
+    tol = 1e-12 * ((k + 1) / 4.0) ** 4
+    R = ed.run(U.numpy(), k, nq, n, *PI3, mu=fl.mu, lam=fl.lam, fuse=0)
+    eR = rel_err_fields(torch.as_tensor(R), oop.residual(U))
+    assert max(eR) <= tol, eR
+    L = ed.run(U.numpy(), k, nq, n, *PI3, mu=fl.mu, lam=fl.lam, fuse=1)
+    eL = rel_err_fields(torch.as_tensor(L), oop.apply(U))
+    assert max(eL) <= 10 * tol, eL
+    X = ed.run(U.numpy(), k, nq, n, *PI3, mu=fl.mu, lam=fl.lam, fuse=3)
+    MX = torch.einsum("eij,cej->cei", oop.mass_matrices(), torch.as_tensor(X))
+    assert float(torch.linalg.norm(MX - U) / torch.linalg.norm(U)) < 1e-13 * ((k + 1) / 4.0) ** 2
+    R32 = ed.run(U.numpy(), k, nq, n, *PI3, precision=1, mu=fl.mu, lam=fl.lam, fuse=0)
+    R64 = oop.residual(U)
+    cast = rel_err_fields(oop.residual(U.float().double()), R64)
+    errs = rel_err_fields(torch.as_tensor(R32), R64)
+    for c in range(5):
+        assert errs[c] <= max(50 * cast[c], 1e-6), (c, errs, cast)
