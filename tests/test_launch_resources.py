@@ -4,13 +4,14 @@ object file) and the block sizes of the LDS plan (tests/emul/plan_check.cpp).
 
 The launch plan picks block sizes so that registers, not LDS, set the occupancy: a
 128-thread workgroup relies on four of them fitting in a compute unit's 160 KB of LDS
-for two waves per SIMD.  The plan sizes LDS from its own arithmetic plus an allowance
+for two waves per SIMD, LDS counted in whole 1280-byte granules (128 per compute unit).  The plan sizes LDS from its own arithmetic plus an allowance
 for the small per-workgroup variables; these tests check the compiler's actual
 figures: every kernel exists for every supported (degree, n_q) in both precisions and
 both metric forms, LDS allows at least as many waves per SIMD as the registers do (up
 to the two the register budget aims at), and the float32 kernels and the float64
-kernels of degree <= 3 do not spill.  Runs on the CPU; builds the library if no
-resource report is present.
+kernels of degree <= 3 do not spill.  The streamed kernels of degrees 8..15: every one
+is reported, none spills, and the cell kernel's LDS plan leaves at least two workgroups
+per compute unit.  Runs on the CPU; builds the library if no resource report is present.
 """
 import glob
 import os
@@ -23,16 +24,20 @@ import pytest
 from tests import emul_driver as ed
 
 BUILD = os.path.join(ed.ROOT, "paper_1806_03095_amd", "_build")
-LDS_CU = 160 * 1024
+LDS_GRANULE, LDS_GRANULES = 1280, 128   # a compute unit's 160 KB, allocated in granules
 VGPR_FILE = 512          # VGPRs per lane of one SIMD's register file (wave64)
 
 
-def _reports():
-    files = sorted(glob.glob(os.path.join(BUILD, "op_k*.resources.txt")))
-    if len(files) < 7:
+def _wg_per_cu(lds):
+    return LDS_GRANULES // max(1, (lds + LDS_GRANULE - 1) // LDS_GRANULE)
+
+
+def _reports(pattern="op_k*.resources.txt", count=7):
+    files = sorted(glob.glob(os.path.join(BUILD, pattern)))
+    if len(files) < count:
         from paper_1806_03095_amd import build as b
         b.build()
-        files = sorted(glob.glob(os.path.join(BUILD, "op_k*.resources.txt")))
+        files = sorted(glob.glob(os.path.join(BUILD, pattern)))
     out = {}
     for f in files:
         cur = None
@@ -64,9 +69,10 @@ def _block_sizes():
     return blocks
 
 
-def _supported():
+def _supported(name="kSupported"):
     src = open(os.path.join(ed.CSRC, "dg_kernels.h")).read()
-    body = src[src.index("kSupported"):src.index(";", src.index("kSupported"))]
+    start = re.search(name + r"\s*\[", src).start()
+    body = src[start:src.index(";", start)]
     return [(int(a), int(b)) for a, b in re.findall(r"\{(\d+), (\d+)\}", body)]
 
 
@@ -87,7 +93,7 @@ def table():
         rows[(k, q, prec, int(m.group(5)), kind)] = {
             "B": b, "vgpr": vg, "spill": int(v["VGPRs Spill"]), "scratch": int(v["ScratchSize"]), "lds": lds,
             "waves_vgpr": min(8, VGPR_FILE // ((vg + 7) // 8 * 8)),
-            "waves_lds": (LDS_CU // max(lds, 1)) * (b // 64) / 4.0}
+            "waves_lds": _wg_per_cu(lds) * (b // 64) / 4.0}
     return rows
 
 
@@ -111,3 +117,25 @@ def test_no_spills_where_the_budget_allows(table):
     bad = [(key, r) for key, r in sorted(table.items())
            if (key[2] == "fp32" or key[0] <= 3) and (r["spill"] or r["scratch"])]
     assert not bad, "\n".join("%s: %s" % b for b in bad)
+
+
+def test_streamed_kernels_reported_spill_free_two_workgroups():
+    rep = _reports("op_hd*.resources.txt", 3)
+    def find(pat):
+        hits = [v for n, v in rep.items() if re.match(pat, n)]
+        assert len(hits) == 1, pat
+        return hits[0]
+    bad = []
+    for k, q in _supported("kSupportedHd"):
+        n = k + 1
+        for t in ("d", "f"):
+            for gen in (0, 1):
+                cell = find(r"_ZN4dgns17dg_cell_hd_kernelILi%dELi%dE%sLb%dE" % (n, q, t, gen))
+                face = find(r"_ZN4dgns17dg_face_hd_kernelILi%dELi%dE%sLb%dE" % (n, q, t, gen))
+                minv = find(r"_ZN4dgns22inverse_mass_hd_kernelILi%dE%sLb%dE" % (n, t, gen))
+                for what, v in (("cell", cell), ("face", face), ("minv", minv)):
+                    if int(v["VGPRs Spill"]) or int(v["ScratchSize"]):
+                        bad.append((k, q, t, gen, what, v))
+                if _wg_per_cu(int(cell["LDS Size"])) < 2:
+                    bad.append((k, q, t, gen, "cell LDS", cell))
+    assert not bad, "\n".join("%s" % (b,) for b in bad)
