@@ -59,7 +59,8 @@ __device__ __forceinline__ void fill_eo_dev(EOMat<NO, NI, Real>& M, Get m) {
 }
 
 // LDS plan of the streamed cell kernel: PL planes per chunk, as many as keep the two
-// regions within about 60 KB (two workgroups, eight waves, per compute unit).  Rows of
+// regions within about 60 KB (two workgroups, eight waves, per compute unit; 40 KB for the
+// float32 pairs listed below).  Rows of
 // the flux arrays (pitch FP, over px) and of the y-swept / x-transposed arrays (pitch BP,
 // over a0) that are a multiple of 128 bytes long are padded by one value: the sweeps
 // read and write eight or more rows at once per wave, and with a pitch of 128 bytes
@@ -73,7 +74,12 @@ struct HdPlan {
     static constexpr int FP = Q * RS % 128 == 0 ? Q + 1 : Q;
     static constexpr int BP = N * RS % 128 == 0 ? N + 1 : N;
     static constexpr int per_plane(int p) { return 15 * p * Q * (FP + BP); }
-    static constexpr int fit(int p) { return p <= 1 ? 1 : (per_plane(p) * RS <= 60 * 1024 ? p : fit(p - 1)); }
+    // float32 pairs whose registers allow more waves and whose chunk keeps two or more planes
+    // at 40 KB: measured faster there (k=8 n_q=9 563 -> 493 us, n_q=13 853 -> 813; k=9 n_q=14
+    // 945 -> 805; k=10 n_q=11 593 -> 569) and 9-30% slower with the smaller budget elsewhere
+    static constexpr int BUDGET_KB =
+        RS == 4 && ((N == 9 && (Q == 9 || Q == 13)) || (N == 10 && Q == 14) || (N == 11 && Q == 11)) ? 40 : 60;
+    static constexpr int fit(int p) { return p <= 1 ? 1 : (per_plane(p) * RS <= BUDGET_KB * 1024 ? p : fit(p - 1)); }
     static constexpr int PL = fit(Q);
     static constexpr int RA = 15 * PL * Q * FP;  // z-swept [2][5][PL][N^2], fluxes [5][3][PL][Q][FP], E [2][5][PL][N^2]
     static constexpr int RB = 15 * PL * Q * BP;  // y-swept [3][5][PL][Q][BP], x-transposed [3][5][PL][Q][BP]
