@@ -11,7 +11,9 @@ two-cell periodic mesh, affine and curved in turn, LGL and Gauss nodes in turn:
     norms, ((k+1)/4)^2 -- at k = 8: 3e-13 (R) and 1.2e-11 (L) -- and the bound leaves
     another factor ((k+1)/4)^2 (5 at k = 8, 16 at k = 15);
   - the stand-alone inverse mass (backward error through the oracle's mass matrix);
-  - float32 R per field within 50 times what rounding the input alone to float32 costs.
+  - float32 R and L per field within 50 times what rounding the input alone to float32
+    costs, and the stand-alone inverse mass by its backward error (the float64 bound times
+    2^29, the ratio of the unit roundoffs).
 Also: two Runge-Kutta steps at k = 8 (stages 1-4 through the high-degree stage path,
 which writes L into the next-state buffer and updates from there) against the oracle's
 steps, the initial-state projection at k = 8, and the entry points without high-degree
@@ -83,15 +85,29 @@ def test_high_degree_float32(kq):
     announce("high degree fp32 n=%s k=%d nq=%d %s %s" % (n, k, nq, kind, basis))
     oop, gop = make_pair(n, k, nq, kind=kind, amp=amp, basis=basis, precision="fp32")
     U = tgv_input(oop, seed=60 + i, mach=0.3)
+    U32 = U.float().double()
     R32 = gop.residual(_cuda(U)).cpu()
+    L32 = gop.apply(_cuda(U)).cpu()
+    X32 = gop.inverse_mass(_cuda(U)).cpu()
     torch.cuda.synchronize()
-    R64 = oop.residual(U)
-    cast = rel_err_fields(oop.residual(U.float().double()), R64)
-    errs = rel_err_fields(R32, R64)
-    print("fp32 k=%d per field %s; input-rounding floor %s" % (k, ["%.1e" % e for e in errs], ["%.1e" % e for e in cast]),
-          flush=True)
-    for c in range(5):
-        assert errs[c] <= max(50 * cast[c], 1e-6), (c, errs, cast)
+    # R and L per field within 50 times what rounding the input alone to float32 costs in the
+    # oracle
+    for name, got, f in (("R", R32, oop.residual), ("L", L32, oop.apply)):
+        ref = f(U)
+        cast = rel_err_fields(f(U32), ref)
+        errs = rel_err_fields(got, ref)
+        print("fp32 k=%d %s per field %s; input-rounding floor %s" % (k, name, ["%.1e" % e for e in errs],
+                                                                     ["%.1e" % e for e in cast]), flush=True)
+        for c in range(5):
+            assert errs[c] <= max(50 * cast[c], 1e-6), (name, c, errs, cast)
+    # the stand-alone inverse mass of the streamed path (the register form at N <= 11, one
+    # output at a time from LDS above): backward error through the oracle's mass matrix within
+    # the float64 bound times the ratio of the unit roundoffs, 2^29
+    M = oop.mass_matrices()
+    MX = torch.einsum("eij,cej->cei", M, X32)
+    err = float(torch.linalg.norm(MX - U) / torch.linalg.norm(U))
+    print("fp32 k=%d M^-1 backward error %.1e" % (k, err), flush=True)
+    assert err < 1e-13 * 2.0 ** 29 * ((k + 1) / 4.0) ** 2, err
 
 
 def test_high_degree_rk_steps_and_projection():
