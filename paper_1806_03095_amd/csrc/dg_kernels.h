@@ -49,6 +49,9 @@ constexpr int kSupportedHd[][2] = {{8, 9},  {8, 13},  {9, 10},  {9, 14},  {10, 1
 int launch_operator_hd1(const OpArgs& a, int k, int q, bool fp32, bool gen, hipStream_t st);   // k = 8..11
 // The streamed kernels at lower degrees where they measured faster (op_hd0.hip).
 bool streamed_preferred(int k, int q, bool fp32, const double force[3]);
+// whether the streamed kernels can serve (k, n_q, precision) for some body force: the
+// context then sizes the face buffer for their scratch as well
+bool streamed_possible(int k, int q, bool fp32);
 int launch_operator_hd0(const OpArgs& a, int k, int q, bool fp32, bool gen, hipStream_t st);
 int launch_operator_hd2(const OpArgs& a, int k, int q, bool fp32, bool gen, hipStream_t st);   // k = 12..15
 int launch_inverse_mass_hd1(const double* R, double* L, int64_t ncell, const double* cm, const double* mj,

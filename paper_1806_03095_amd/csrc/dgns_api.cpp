@@ -345,8 +345,11 @@ int dgns_create(const dgns_params* prm, const dgns_box_mesh* msh, void* stream, 
     if (rc == 0) rc = noalloc_workspace(&c->noalloc);
     if (rc == 0) {
         // the face buffer of the kernels that evaluate each face once: six blocks of
-        // 2 x 5 (k+1)^2 values per cell (float64 size, which also covers float32)
-        const int64_t nfw = ncell * 6 * 10 * (int64_t)c->n * c->n;
+        // 2 x 5 (k+1)^2 values per cell (float64 size, which also covers float32); where the
+        // streamed kernels may run, followed by their per-cell scratch of z-swept planes,
+        // [n_q][2][5][(k+1)^2] values per cell
+        int64_t nfw = ncell * 6 * 10 * (int64_t)c->n * c->n;
+        if (streamed_possible(c->k, c->q, c->fp32)) nfw += ncell * 10 * (int64_t)c->q * c->n * c->n;
         if (hipMalloc((void**)&c->d_fw, sizeof(double) * nfw) != hipSuccess) {
             c->d_fw = nullptr;
             rc = fail(DGNS_ENOMEM, "face buffer (%lld doubles)", (long long)nfw);

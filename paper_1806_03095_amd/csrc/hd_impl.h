@@ -6,13 +6,19 @@
 // LDS beside the work area) no longer fits a compute unit's 160 KB.  Here a workgroup
 // still evaluates one cell, but streams it through the quadrature planes along xi_2:
 //  - per chunk of PL planes, the z-interpolation reads the coefficient lines of U from
-//    global memory (they stay in the L2 / last-level cache across the chunks);
+//    global memory (they stay in the L2 / last-level cache across the chunks; sweeping
+//    every plane once into scratch up front fetched a third as much at k = 15 but was up
+//    to 10% slower, the up-front phase overlapping nothing);
 //  - the chunk's intermediates live in LDS in two regions that alternate between the
 //    phases (z-swept values, then point fluxes, then y-transposed sums in region A;
 //    y-swept values, then x-transposed sums in region B);
-//  - the z-transposed test sweep accumulates into the cell's own rows of the output
-//    vector (each entry owned by one thread of one workgroup: no atomics), which the
-//    face terms then complete; M^{-1} is the stand-alone kernel applied afterwards.
+//  - each chunk's y-transposed sums (the two planes E1, E2 per quadrature plane) go to
+//    the cell's own area of a scratch buffer behind the face buffer; after the last
+//    chunk one pass forms the z-transposed test sweep over all planes, adds the face
+//    terms and writes the cell's rows of the output vector once (accumulating into the
+//    output chunk by chunk instead read and wrote the whole residual block per chunk:
+//    1.4 GB written per evaluation at k = 15, 0.25 GB this way); M^{-1} is the
+//    stand-alone kernel applied afterwards.
 // The face terms are evaluated once per face by dg_face_hd_kernel (one face of the cell
 // at a time, own traces read from global memory) into the face buffer, as for the
 // lower degrees.  The 1D tables come from the context's device copy of Tables1D (as
@@ -117,6 +123,8 @@ dg_cell_hd_kernel(OpArgs a) {
     const int64_t cstride = a.ncell * N3;
     const double* Ue = a.U + e * N3;
     double* Re = a.out + e * N3;
+    // the cell's scratch area behind the face buffer: [n_q][2][5][N^2] values
+    Real* ew = static_cast<Real*>(a.fw) + a.ncell * 6 * FWB + e * 10 * Q * N2;
     load_ktab<N, Q, Real>(a.tab_dev, lt);
     if constexpr (EO) {
         const Tables1D* t = a.tab_dev;
@@ -361,25 +369,28 @@ dg_cell_hd_kernel(OpArgs a) {
         }
         }
         __syncthreads();
-        // z-transposed into the cell's rows of the output: R (+)= S_z^T E1 + D_z^T E2
-        for (int it = tid; it < 5 * N3; it += nth) {
-            const int c = it / N3, r = it % N3, a2 = r / N2, r2 = r % N2;
-            Real acc = 0;
-            for (int pl = 0; pl < np; ++pl)
-                acc += lt.S[pz0 + pl][a2] * rA[((0 * 5 + c) * PL + pl) * N2 + r2] +
-                       lt.D[pz0 + pl][a2] * rA[((1 * 5 + c) * PL + pl) * N2 + r2];
-            double* rp = Re + c * cstride + r;
-            *rp = pz0 == 0 ? (double)acc : *rp + (double)acc;
+        // the chunk's planes E1, E2 to the cell's scratch area   ew [pz][kind][c][a1][a0]
+        for (int it = tid; it < 10 * np * N2; it += nth) {
+            const int r2 = it % N2, c = (it / N2) % 5, kind = (it / (5 * N2)) % 2, pl = it / (10 * N2);
+            ew[((pz0 + pl) * 2 + kind) * 5 * N2 + c * N2 + r2] = rA[((kind * 5 + c) * PL + pl) * N2 + r2];
         }
-        // the next chunk's z-sweep overwrites rA
+        // the next chunk's z-sweep overwrites rA; after the last chunk the barrier also
+        // orders the scratch writes before the pass below reads them
         __syncthreads();
     }
 
-    // the six lifted face blocks: R(a, b, m) += W0 l_m(s) + W1 l_m'(s) along each face's normal
+    // R = S_z^T E1 + D_z^T E2 over all quadrature planes, plus the six lifted face blocks:
+    // R(a, b, m) += W0 l_m(s) + W1 l_m'(s) along each face's normal
     const Real* fw = static_cast<const Real*>(a.fw) + e * 6 * FWB;
     for (int it = tid; it < 5 * N3; it += nth) {
         const int c = it / N3, r = it % N3;
         const int x0 = r % N, x1 = (r / N) % N, x2 = r / N2;
+        double zt = 0.0;
+        if (cell) {
+            const Real* e1 = ew + c * N2 + (r % N2);
+            for (int pz = 0; pz < Q; ++pz)
+                zt += (double)(lt.S[pz][x2] * e1[pz * 10 * N2] + lt.D[pz][x2] * e1[pz * 10 * N2 + 5 * N2]);
+        }
         Real acc = 0;
         if (cell) {
 #pragma unroll
@@ -390,8 +401,7 @@ dg_cell_hd_kernel(OpArgs a) {
                 acc += w[2 * FWB + x1 * N + x0] * lt.fv[s][x2] + w[2 * FWB + 5 * N2 + x1 * N + x0] * lt.fd[s][x2];
             }
         }
-        double* rp = Re + c * cstride + r;
-        *rp = cell ? *rp + (double)acc : 0.0;
+        Re[c * cstride + r] = cell ? zt + (double)acc : 0.0;
     }
 }
 

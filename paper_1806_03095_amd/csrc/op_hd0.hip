@@ -10,6 +10,10 @@ static int op_hd(const OpArgs& a, bool gen, hipStream_t st) {
     return gen ? launch_op_hd_t<N, Q, double, true>(a, st) : launch_op_hd_t<N, Q, double, false>(a, st);
 }
 
+bool streamed_possible(int k, int q, bool fp32) {
+    return k >= 8 || (!fp32 && ((k == 6 && q == 10) || (k == 7 && q == 11)));
+}
+
 bool streamed_preferred(int k, int q, bool fp32, const double force[3]) {
     return !fp32 && force[0] == 0 && force[1] == 0 && force[2] == 0 && ((k == 6 && q == 10) || (k == 7 && q == 11));
 }
