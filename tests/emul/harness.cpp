@@ -104,10 +104,11 @@ int main(int argc, char** argv) {
                                    : (fuse == 5 ? (int64_t)2 * msh.n[0] * msh.n[2] * kWallSums : ndof);
     std::vector<double> U(ndof), out(nout, -12345.0), Rb;
     // face buffer of the split evaluation: six lifted blocks [2][5][N^2] per cell (sized
-    // for float64, enough for float32), at the high degrees followed by the streamed cell
-    // kernel's scratch [n_q][2][5][N^2] per cell, as the library sizes it; filled with a value
-    // that would show if read unwritten
-    const int64_t nfw_hd = prm.degree >= 8 ? (int64_t)hs.ncell * 10 * prm.n_q * (prm.degree + 1) * (prm.degree + 1) : 0;
+    // for float64, enough for float32), followed by the streamed cell kernel's scratch
+    // [n_q][2][5][N^2] per cell as the library sizes it where those kernels can run (here
+    // always, so that any case may run them); filled with a value that would show if read
+    // unwritten
+    const int64_t nfw_hd = (int64_t)hs.ncell * 10 * prm.n_q * (prm.degree + 1) * (prm.degree + 1);
     std::vector<double> fw(hs.ncell * 6 * 10 * (prm.degree + 1) * (prm.degree + 1) + nfw_hd, 1e300);
     if ((int64_t)std::fread(U.data(), 8, ndof, f) != ndof) return 6;
     if (fuse == 2) {
