@@ -110,7 +110,11 @@ const char* dgns_last_error(void);
  * and residual no longer fit on chip); they provide the operator, the residual, the
  * inverse mass, the Runge-Kutta step and stage update, the time step and the initial
  * projection, and return DGNS_EUNSUPPORTED for a nonzero body force (at creation) and
- * from the diagnostics, channel statistics and adjoint entry points. */
+ * from the diagnostics, channel statistics and adjoint entry points.
+ * Device memory owned by the context besides the mesh data: a face buffer of
+ * 60 (k+1)^2 doubles per cell, plus 10 n_q (k+1)^2 doubles per cell where the streamed
+ * kernels can run (k >= 8; k = 6, n_q = 10 and k = 7, n_q = 11 in float64); DGNS_ENOMEM
+ * if that allocation fails. */
 int dgns_create(const dgns_params* params, const dgns_box_mesh* mesh, void* stream, dgns_ctx** out);
 
 /* Releases everything the context owns.  Synchronises its stream first.  NULL is a no-op. */
