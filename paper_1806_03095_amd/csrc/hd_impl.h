@@ -65,8 +65,8 @@ __device__ __forceinline__ void fill_eo_dev(EOMat<NO, NI, Real>& M, Get m) {
 }
 
 // LDS plan of the streamed cell kernel: PL planes per chunk, as many as keep the two
-// regions within about 60 KB (two workgroups, eight waves, per compute unit; 40 KB for the
-// float32 pairs listed below).  Rows of
+// regions within about 60 KB (two workgroups, eight waves, per compute unit; 40 or 30 KB
+// for the pairs listed below).  Rows of
 // the flux arrays (pitch FP, over px) and of the y-swept / x-transposed arrays (pitch BP,
 // over a0) that are a multiple of 128 bytes long are padded by one value: the sweeps
 // read and write eight or more rows at once per wave, and with a pitch of 128 bytes
@@ -80,11 +80,16 @@ struct HdPlan {
     static constexpr int FP = Q * RS % 128 == 0 ? Q + 1 : Q;
     static constexpr int BP = N * RS % 128 == 0 ? N + 1 : N;
     static constexpr int per_plane(int p) { return 15 * p * Q * (FP + BP); }
-    // float32 pairs whose registers allow more waves and whose chunk keeps two or more planes
-    // at 40 KB: measured faster there (k=8 n_q=9 563 -> 493 us, n_q=13 853 -> 813; k=9 n_q=14
-    // 945 -> 805; k=10 n_q=11 593 -> 569) and 9-30% slower with the smaller budget elsewhere
+    // smaller chunks, for more workgroups per compute unit, where they measured faster at about
+    // 10M DoFs (us per evaluation, 60 KB against the budget taken): float64 k=6 n_q=10 1449 ->
+    // 1298 and k=8 n_q=9 809 -> 770 at 40 KB; float32 k=8 n_q=9 467 -> 436 and k=11 n_q=12 455
+    // -> 423 at 30 KB, k=8 n_q=13 853 -> 813, k=9 n_q=10 523 -> 479, n_q=14 945 -> 805 and k=10
+    // n_q=11 593 -> 569 at 40 KB.  Elsewhere 40 or 30 KB measured as fast or slower (to -12%).
     static constexpr int BUDGET_KB =
-        RS == 4 && ((N == 9 && (Q == 9 || Q == 13)) || (N == 10 && Q == 14) || (N == 11 && Q == 11)) ? 40 : 60;
+        RS == 8 ? (((N == 7 && Q == 10) || (N == 9 && Q == 9)) ? 40 : 60)
+                : (((N == 9 && Q == 9) || (N == 12 && Q == 12))
+                       ? 30
+                       : (((N == 9 && Q == 13) || (N == 10 && (Q == 10 || Q == 14)) || (N == 11 && Q == 11)) ? 40 : 60));
     static constexpr int fit(int p) { return p <= 1 ? 1 : (per_plane(p) * RS <= BUDGET_KB * 1024 ? p : fit(p - 1)); }
     static constexpr int PL = fit(Q);
     static constexpr int RA = 15 * PL * Q * FP;  // z-swept [2][5][PL][N^2], fluxes [5][3][PL][Q][FP], E [2][5][PL][N^2]
