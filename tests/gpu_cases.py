@@ -62,10 +62,17 @@ def channel_input(oop, seed=7, noise=1e-2, umax=18.3, mach=0.1):
 
 
 def rel_err_fields(a, b):
-    """Per-field ||a - b||_2 / ||b||_2."""
+    """Per-field ||a - b||_2 / ||b||_2.  A field that is identically zero in b (rho w of the
+    Taylor-Green state) is measured against the norm of the whole of b instead, so that it
+    gives 0 when a's field is zero too and a finite error otherwise, never NaN."""
     a = torch.as_tensor(a, dtype=torch.float64).cpu()
     b = torch.as_tensor(b, dtype=torch.float64).cpu()
-    return [float(torch.linalg.norm(a[c] - b[c]) / torch.linalg.norm(b[c])) for c in range(a.shape[0])]
+    whole = float(torch.linalg.norm(b))
+    out = []
+    for c in range(a.shape[0]):
+        d, nb = float(torch.linalg.norm(a[c] - b[c])), float(torch.linalg.norm(b[c]))
+        out.append(d / nb if nb > 0 else (d / whole if whole > 0 else d))
+    return out
 
 
 def sample_cells(n, count, seed):

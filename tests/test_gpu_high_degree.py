@@ -16,7 +16,8 @@ two-cell periodic mesh, affine and curved in turn, LGL and Gauss nodes in turn:
     2^29, the ratio of the unit roundoffs).
 Also: two Runge-Kutta steps at k = 8 (stages 1-4 through the high-degree stage path,
 which writes L into the next-state buffer and updates from there) against the oracle's
-steps, the initial-state projection at k = 8, and the entry points without high-degree
+steps, the initial-state projection at k = 8, both again at k = 12 and 15 on a curved
+mesh under the per-field float64 bound, and the entry points without high-degree
 kernels (diagnostics, adjoint) and body forces rejected with DGNS_EUNSUPPORTED.
 """
 import math
@@ -35,6 +36,19 @@ HD = [(8, 9), (8, 13), (9, 10), (9, 14), (10, 11), (10, 16), (11, 12), (12, 13),
 
 def _cuda(t):
     return t.to("cuda").contiguous()
+
+
+def _projection_errors(Ug, Uo):
+    """Per-field relative error of a projected state; a field that is identically zero in the
+    oracle (rho w of the Taylor-Green state) must be exactly zero on the GPU too."""
+    errs = []
+    for c in range(5):
+        if float(torch.linalg.norm(Uo[c])) == 0.0:
+            assert float(torch.linalg.norm(Ug[c])) == 0.0, c
+            errs.append(0.0)
+        else:
+            errs.append(float(torch.linalg.norm(Ug[c] - Uo[c]) / torch.linalg.norm(Uo[c])))
+    return errs
 
 
 def _case(i):
@@ -116,7 +130,7 @@ def test_high_degree_rk_steps_and_projection():
     Ug = gop.project_ic("taylor_green", [1.0, 1.0, 0.3, 1.0])
     torch.cuda.synchronize()
     Uo = initial.l2_project(oop, lambda x: initial.taylor_green(x, oop.fl, mach=0.3))
-    errs = rel_err_fields(Ug.cpu(), Uo)
+    errs = _projection_errors(Ug.cpu(), Uo)
     print("projection vs oracle", ["%.1e" % e for e in errs], flush=True)
     assert max(errs) < 1e-12, errs
     U0 = tgv_input(oop, seed=77, mach=0.3)
@@ -136,6 +150,38 @@ def test_high_degree_rk_steps_and_projection():
     st = [20 * 2.0 ** -53 * float(torch.linalg.norm(U0[c]) / torch.linalg.norm((U - U0)[c])) for c in range(5)]
     for c in range(5):
         assert inc[c] <= max(1e-12, 4.0 * (e_L[c] + st[c])), (c, inc, e_L, st)
+
+
+@pytest.mark.parametrize("kq", [(12, 13), (15, 16)])
+def test_high_degree_rk_steps_and_projection_large_k(kq):
+    # the stage path of the streamed kernels (L into the next-state buffer, the residual
+    # through the cell's scratch, M^{-1} in place, the update from there) at degrees whose
+    # extended-precision floor is too slow to evaluate: the increment of two RK steps per
+    # field within 10 times the float64 bound of L above, 1e-11 ((k+1)/4)^4 relative; the
+    # projection within 1e-12 ((k+1)/4)^2
+    k, nq = kq
+    announce("high degree k=%d nq=%d: projection and two RK steps" % (k, nq))
+    oop, gop = make_pair((2, 1, 1), k, nq, kind="curved", amp=0.1)
+    Ug = gop.project_ic("taylor_green", [1.0, 1.0, 0.3, 1.0])
+    torch.cuda.synchronize()
+    Uo = initial.l2_project(oop, lambda x: initial.taylor_green(x, oop.fl, mach=0.3))
+    errs = _projection_errors(Ug.cpu(), Uo)
+    print("projection vs oracle", ["%.1e" % e for e in errs], flush=True)
+    assert max(errs) < 1e-12 * ((k + 1) / 4.0) ** 2, errs
+    U0 = tgv_input(oop, seed=78, mach=0.3)
+    dt = gop.compute_dt(0.2, 0.02, 1.5, 3.0, 1.0, 0.3)
+    Ug = _cuda(U0.clone())
+    work = torch.empty(2 * gop.n_dof, dtype=torch.float64, device="cuda")
+    for s in range(2):
+        gop.rk_step(Ug, work, s * dt, dt)
+    torch.cuda.synchronize()
+    U = U0.clone()
+    for s in range(2):
+        U = timeint.lsrk_step(lambda V, t: oop.apply(V), U, s * dt, dt)
+    inc = rel_err_fields(Ug.cpu() - U0, U - U0)
+    tol = 10 * 1e-12 * ((k + 1) / 4.0) ** 4
+    print("two RK steps: increment vs oracle %s (bound %.1e)" % (["%.1e" % e for e in inc], tol), flush=True)
+    assert max(inc) <= tol, inc
 
 
 def test_high_degree_unsupported_entry_points():
