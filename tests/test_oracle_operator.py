@@ -9,7 +9,11 @@
   linearised about a uniform flow is dissipative (no eigenvalue with Re > 0);
 * the tensor-product inverse mass matrix equals the dense inverse;
 * the Taylor-Green initial kinetic energy and dissipation converge to their
-  closed forms at the expected rate; nodal bases LGL and GL give the same L.
+  closed forms at the expected rate; nodal bases LGL and GL give the same L;
+* the wall state: a fluid at rest at the wall temperature is steady, heat flows from
+  the warmer of wall and fluid and friction opposes a flow along the wall (planted
+  adiabatic and slip walls fail), and the residual of the exact steady compressible
+  Poiseuille flow converges at the order of the scheme.
 """
 import math
 
@@ -295,3 +299,107 @@ def test_wall_heat_flux_direction(T_fluid, sign):
     interior = float(R[4, [1, 2], :].abs().max())
     assert interior < 1e-10 * abs(E_wall)
     assert float(R[0].abs().max()) < 1e-10 * abs(E_wall)
+
+
+def _poiseuille(op, f, p0, Tw):
+    """Steady compressible channel flow driven by the body force f (per volume) between
+    isothermal no-slip walls at y = -1, 1, constant mu and lambda: the x-momentum balance
+    mu u'' + f = 0 gives u = U (1 - y^2), U = f / (2 mu); the pressure is uniform; the
+    energy balance (mu u u')' + lambda T'' + f u = 0 gives T = Tw + mu U^2 (1 - y^4) / (3
+    lambda); rho = p0 / (R T)."""
+    fl = op.fl
+    U = f / (2.0 * fl.mu)
+
+    def field(x):
+        y = torch.as_tensor(x[..., 1])
+        T = Tw + fl.mu * U ** 2 * (1.0 - y ** 4) / (3.0 * fl.lam)
+        rho = p0 / (fl.R * T)
+        u = torch.zeros(y.shape + (3,), dtype=torch.float64)
+        u[..., 0] = U * (1.0 - y ** 2)
+        return physics.conserved_from_primitive(rho, u, p0 * torch.ones_like(y), fl)
+
+    return initial.l2_project(op, field)
+
+
+def _poiseuille_residuals(k, ny_list):
+    f, Tw = 0.04, 1.0
+    out = []
+    for ny in ny_list:
+        op = make(n=(1, ny, 1), k=k, nq=k + 2, periodic=(True, False, True), lo=(0.0, -1.0, 0.0),
+                  hi=(0.5, 1.0, 0.5), wall_T=Tw, force=(f, 0.0, 0.0))
+        U = _poiseuille(op, f, op.fl.R * Tw, Tw)
+        out.append(float(op.residual(U).abs().max()))
+    return out
+
+
+def test_wall_state_poiseuille_steady_state_converges():
+    # The wall state (no-slip and isothermal through the mirror exterior state, a reading
+    # of Sec. 2.2 / 5.3) against a closed form: the residual of the projected steady
+    # Poiseuille state (shear and heat flux at the walls) vanishes under refinement; its
+    # largest entries sit in the wall cells' energy rows and fall at about the order k of
+    # the scheme (measured at k = 3: rates 2.5 and 2.9 over ny = 2, 4, 8)
+    k = 3
+    e = _poiseuille_residuals(k, (2, 4, 8))
+    rates = [math.log2(e[i] / e[i + 1]) for i in range(len(e) - 1)]
+    print("Poiseuille residual:", ["%.2e" % v for v in e], "rates", ["%.2f" % r for r in rates])
+    assert min(rates) > k - 0.75, rates
+
+
+def _uniform_flow(op, rho, u0, T):
+    E, N = op.mesh.n_cells, (op.mesh.k + 1) ** 3
+    u = torch.tensor([u0, 0.0, 0.0], dtype=torch.float64)
+    Uc = physics.conserved_from_primitive(torch.tensor(rho, dtype=torch.float64), u,
+                                          torch.tensor(rho * op.fl.R * T, dtype=torch.float64), op.fl)
+    return Uc[:, None, None].expand(5, E, N).clone()
+
+
+def _wall_friction(op):
+    U = _uniform_flow(op, 1.0, 0.5, op.wall_T)
+    R = op.residual(U)
+    return float(R[1, [0, 3], :].sum()), float(R[1, [1, 2], :].abs().max()), float(R[0].abs().max())
+
+
+def test_wall_friction_opposes_the_flow():
+    # fluid moving uniformly along the walls at the wall temperature: the no-slip wall
+    # decelerates it (x-momentum rows of the wall cells negative), the interior cells and
+    # the mass rows see nothing
+    op = make(n=(1, 4, 1), k=2, nq=4, periodic=(True, False, True), lo=(0, -1, 0), hi=(1.0, 1.0, 1.0), wall_T=1.0)
+    wall, interior, mass = _wall_friction(op)
+    assert wall < 0
+    assert interior < 1e-10 * abs(wall)
+    assert mass < 1e-10 * abs(wall)
+
+
+def test_wall_friction_pin_detects_planted_slip():
+    # the same with a slip wall planted in the oracle's mirror state (u+ = u-): no friction
+    def slip(self, Um, Gm):
+        Up, Gp = operator.DGOperator._mirror(self, Um, Gm)
+        Up = Up.clone()
+        Up[..., 1:4] = Um[..., 1:4]
+        return Up, Gp
+
+    good = make(n=(1, 4, 1), k=2, nq=4, periodic=(True, False, True), lo=(0, -1, 0), hi=(1.0, 1.0, 1.0), wall_T=1.0)
+    bad = make(n=(1, 4, 1), k=2, nq=4, periodic=(True, False, True), lo=(0, -1, 0), hi=(1.0, 1.0, 1.0), wall_T=1.0)
+    bad._mirror = slip.__get__(bad)
+    w_good, _, _ = _wall_friction(good)
+    w_bad, _, _ = _wall_friction(bad)
+    print("wall friction: no-slip %.3e, planted slip %.3e" % (w_good, w_bad))
+    assert abs(w_bad) < 1e-6 * abs(w_good)
+
+
+def test_wall_heat_flux_pin_detects_planted_adiabatic_wall():
+    # the heat-flux direction pin with an adiabatic wall planted in the oracle's mirror
+    # state (T+ = T-, no-slip kept): a fluid colder than the walls no longer gains energy
+    def adiabatic(self, Um, Gm):
+        Up = Um.clone()
+        Up[..., 1:4] = -Um[..., 1:4]
+        return Up, Gm
+
+    Tw = 300.0
+    good = make(n=(1, 4, 1), k=2, nq=4, periodic=(True, False, True), lo=(0, -1, 0), hi=(1.0, 1.0, 1.0), wall_T=Tw)
+    bad = make(n=(1, 4, 1), k=2, nq=4, periodic=(True, False, True), lo=(0, -1, 0), hi=(1.0, 1.0, 1.0), wall_T=Tw)
+    bad._mirror = adiabatic.__get__(bad)
+    e_good = float(good.residual(_rest(good, 1.0, 250.0))[4, [0, 3], :].sum())
+    e_bad = float(bad.residual(_rest(bad, 1.0, 250.0))[4, [0, 3], :].sum())
+    print("wall heat gain: isothermal %.3e, planted adiabatic %.3e" % (e_good, e_bad))
+    assert e_good > 0 and abs(e_bad) < 1e-6 * e_good
