@@ -51,7 +51,7 @@ CR_STUDY = 0.25
 # diffusion number: the paper's ratio to the critical one (D = 0.02 against 0.036), 0.56 x 0.020;
 # at Re = 1600 the viscous restriction does not bind either way
 D_RUN = 0.011
-MEASURED_TRAFFIC = {"fingerprint": "325b63b5c086a9ef", "workload": (32, 3, 6), "bytes": 862704140.8}
+MEASURED_TRAFFIC = {"fingerprint": "3e8cab51b4fc250f", "workload": (32, 3, 6), "bytes": 862688972.8}
 
 
 def kernel_fingerprint():

@@ -413,20 +413,28 @@ dg_cell_hd_kernel(OpArgs a) {
 // Workgroup of the streamed face kernel: one face point per thread, 128 threads where the
 // n_q^2 points of a face fit at k >= 8 (k = 8..10 at n_q = k+1), else 256 (at k = 6, 7,
 // n_q = 10, 11 the two-wave register budget of 128 threads spills 500-700 dwords).
-template <int N, int Q>
+// Float64 at 128 threads and at k >= 13 keeps the traces inside the t0-sweep area (see
+// FaceSizes), which frees LDS for more workgroups per compute unit: k = 9 three -> four
+// (709 -> 691 us per evaluation at about 10M DoFs), k = 13..15 one -> two, there with the
+// registers held to two waves per SIMD (k = 13 1013 -> 931 us, k = 14 889 -> 806 with 6
+// dwords spilled, k = 15 1067 -> 1003 with 32).
+template <int N, int Q, typename Real>
 struct HdFaceBlock {
+    static constexpr bool F64 = sizeof(Real) == 8;
     static constexpr int B = N >= 9 && Q * Q <= 128 ? 128 : kHdBlock;
-    // 128-thread workgroups held to two waves per SIMD (256 registers), as with 256
-    static constexpr int W = B == 128 ? 2 : 1;
+    // waves per SIMD the registers are held to (256 registers at two)
+    static constexpr int W = (B == 128 || (F64 && N >= 14)) ? 2 : 1;
+    static constexpr bool TRIN = F64 && (B == 128 || N >= 14);
 };
 
 // Face terms once per face (see dg_face_kernel in op_impl.h), one face of the cell at a
 // time so that the traces of both sides fit in LDS; the cell's own traces come from
 // global memory.  One face point per thread: n_q^2 <= 256.
 template <int N, int Q, typename Real, bool GEN>
-__global__ void __launch_bounds__((HdFaceBlock<N, Q>::B)) __attribute__((amdgpu_waves_per_eu(HdFaceBlock<N, Q>::W)))
+__global__ void __launch_bounds__((HdFaceBlock<N, Q, Real>::B)) __attribute__((amdgpu_waves_per_eu(HdFaceBlock<N, Q, Real>::W)))
 dg_face_hd_kernel(OpArgs a) {
-    using FS = FaceSizes<N, Q, HdFaceBlock<N, Q>::B, 1, false>;
+    using HB = HdFaceBlock<N, Q, Real>;
+    using FS = FaceSizes<N, Q, HB::B, 1, false, HB::TRIN>;
     constexpr int N2 = N * N, Q2 = Q * Q, FWB = 2 * 5 * N2;
     static_assert(FS::ALIAS, "one face point per thread");
     __shared__ Real sW[FS::TOTAL];
@@ -631,7 +639,7 @@ inline int launch_op_hd_t(const OpArgs& a0, hipStream_t st) {
     const bool stage = a.rk.dU != nullptr;
     if (stage) a.out = a.rk.U_out;
     const dim3 grid((unsigned)a.ncell);
-    constexpr int FB = HdFaceBlock<N, Q>::B;
+    constexpr int FB = HdFaceBlock<N, Q, Real>::B;
     if (a.terms & 3u) hipLaunchKernelGGL((dg_face_hd_kernel<N, Q, Real, GEN>), grid, dim3(FB), 0, st, a);
     hipLaunchKernelGGL((dg_cell_hd_kernel<N, Q, Real, GEN>), grid, dim3(kHdBlock), 0, st, a);
     if (hipGetLastError() != hipSuccess) return -1;

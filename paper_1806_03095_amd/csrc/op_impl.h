@@ -39,7 +39,7 @@ namespace dgns {
 template <int A, int B>
 struct CMax { static constexpr int v = A > B ? A : B; };
 
-template <int N, int Q, int B, int NF = 3, bool FUSED = (N <= 4)>
+template <int N, int Q, int B, int NF = 3, bool FUSED = (N <= 4), bool TRIN = false>
 struct FaceSizes {
     static constexpr int N2 = N * N, Q2 = Q * Q;
     // FUSED: the traces are computed inside the sweep along t0 and never stored.
@@ -57,10 +57,17 @@ struct FaceSizes {
     // With one face point per thread, OUT can overwrite SW (the point results wait
     // in registers across a barrier): SW | TR, then OUT | T1, then W | T1.
     static constexpr bool ALIAS = NF * Q2 <= B;
-    static constexpr int TR_OFF = ALIAS ? SW : R1;
+    // TRIN: the traces also lie at the start of SW.  With one t0-sweep item per thread, each
+    // item loads its two trace lines into registers before a barrier and then writes its
+    // sweep over them, so TR takes no room of its own.
+    static constexpr bool TR_IN_SW = TRIN && ALIAS && !FUSED && NF * 2 * 5 * N <= B;
+    static_assert(!TRIN || TR_IN_SW, "traces inside SW: one face point and one sweep item per thread");
+    static_assert(TR <= SW, "traces fit in SW");
+    static constexpr int TR_OFF = TR_IN_SW ? 0 : (ALIAS ? SW : R1);
     static constexpr int OUT_OFF = ALIAS ? 0 : R1;
     static constexpr int T1_OFF = ALIAS ? OUT : 0;
-    static constexpr int TOTAL = ALIAS ? CMax<CMax<SW + TR, OUT + T1>::v, W>::v : SPLIT_TOTAL;
+    static constexpr int TOTAL = TR_IN_SW ? CMax<CMax<SW, OUT + T1>::v, W>::v
+                                          : (ALIAS ? CMax<CMax<SW + TR, OUT + T1>::v, W>::v : SPLIT_TOTAL);
 };
 
 template <int N, int Q, int P>
@@ -811,6 +818,40 @@ __device__ __forceinline__ void face_traces_sweep(const OpArgs& a, const KTab<N,
         __syncthreads();
 
         // sweep along t0: A0 = S tv, A1 = D tv, An = S tn     r1 [f][side][3][c][b][q0]
+        if constexpr (FS::TR_IN_SW) {
+            // one item per thread: its two trace lines into registers, a barrier that
+            // separates every read of TR from the writes of SW over it, then the sweep
+            const int it = tid;
+            const int ib = it % N, c = (it / N) % 5, side = (it / (5 * N)) % 2, f = it / (10 * N), d = d0 + f;
+            const bool on = it < NF * 2 * 5 * N && !(side == 1 && fi.wall[d + 3 * s]);
+            Real tv[N], tn[N];
+            if (on) {
+                const Real* tr = rtr + f * (2 * 2 * 5 * N2) + side * (2 * 5 * N2) + c * N2 + ib * N;
+    #pragma unroll
+                for (int ia = 0; ia < N; ++ia) {
+                    tv[ia] = tr[ia];
+                    tn[ia] = tr[5 * N2 + ia];
+                }
+            }
+            __syncthreads();
+            if (on) {
+                Real* o = r1 + ((f * 2 + side) * 3 * 5 + c) * N * Q + ib * Q;
+                constexpr int UQ = UnrollLimit<N, Q, Real>::face ? 1 : Q;
+    #pragma unroll UQ
+                for (int q0 = 0; q0 < Q; ++q0) {
+                    Real a0 = 0, a1 = 0, an = 0;
+    #pragma unroll
+                    for (int ia = 0; ia < N; ++ia) {
+                        a0 += lt.S[q0][ia] * tv[ia];
+                        a1 += lt.D[q0][ia] * tv[ia];
+                        an += lt.S[q0][ia] * tn[ia];
+                    }
+                    o[q0] = a0;
+                    o[5 * N * Q + q0] = a1;
+                    o[2 * 5 * N * Q + q0] = an;
+                }
+            }
+        } else {
         for (int it = tid; it < NF * 2 * 5 * N; it += nth) {
             const int ib = it % N, c = (it / N) % 5, side = (it / (5 * N)) % 2, f = it / (10 * N), d = d0 + f;
             if (side == 1 && fi.wall[d + 3 * s]) continue;
@@ -838,6 +879,7 @@ __device__ __forceinline__ void face_traces_sweep(const OpArgs& a, const KTab<N,
                 o[5 * N * Q + q0] = a1;
                 o[2 * 5 * N * Q + q0] = an;
             }
+        }
         }
         __syncthreads();
     }

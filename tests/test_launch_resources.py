@@ -10,8 +10,11 @@ figures: every kernel exists for every supported (degree, n_q) in both precision
 both metric forms, LDS allows at least as many waves per SIMD as the registers do (up
 to the two the register budget aims at), and the float32 kernels and the float64
 kernels of degree <= 3 do not spill.  The streamed kernels of degrees 8..15: every one
-is reported, none spills, and the cell kernel's LDS plan leaves at least two workgroups
-per compute unit.  Runs on the CPU; builds the library if no resource report is present.
+is reported, none spills (except the float64 face kernels at k = 14, 15, held to two waves
+per SIMD, within the 32 dwords their plan was measured with), the cell kernel's LDS plan
+leaves at least two workgroups per compute unit, and the float64 face kernels that keep
+their traces inside the sweep area reach the workgroups per compute unit they are planned
+for (four 128-thread workgroups at k = 8..10, n_q = k+1; two of 256 threads at k = 13..15).  Runs on the CPU; builds the library if no resource report is present.
 """
 import glob
 import os
@@ -134,8 +137,17 @@ def test_streamed_kernels_reported_spill_free_two_workgroups():
                 face = find(r"_ZN4dgns17dg_face_hd_kernelILi%dELi%dE%sLb%dE" % (n, q, t, gen))
                 minv = find(r"_ZN4dgns22inverse_mass_hd_kernelILi%dE%sLb%dE" % (n, t, gen))
                 for what, v in (("cell", cell), ("face", face), ("minv", minv)):
-                    if int(v["VGPRs Spill"]) or int(v["ScratchSize"]):
+                    allowed = 32 if (what == "face" and t == "d" and k >= 14) else 0
+                    if int(v["VGPRs Spill"]) > allowed or (not allowed and int(v["ScratchSize"])):
                         bad.append((k, q, t, gen, what, v))
                 if _wg_per_cu(int(cell["LDS Size"])) < 2:
                     bad.append((k, q, t, gen, "cell LDS", cell))
+                if t == "d" and (q == n or k >= 13) and (q * q <= 128 or k >= 13):
+                    # in-place traces: LDS and registers both allow the planned workgroups
+                    threads = 128 if q * q <= 128 else 256
+                    want = 4 if threads == 128 else 2
+                    regs = int(face["VGPRs"]) + int(face["AGPRs"])
+                    by_regs = (VGPR_FILE // max(1, (regs + 7) // 8 * 8)) * 4 // (threads // 64)
+                    if min(_wg_per_cu(int(face["LDS Size"])), by_regs) < want:
+                        bad.append((k, q, t, gen, "face workgroups", face))
     assert not bad, "\n".join("%s" % (b,) for b in bad)
