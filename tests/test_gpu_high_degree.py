@@ -17,8 +17,9 @@ two-cell periodic mesh, affine and curved in turn, LGL and Gauss nodes in turn:
 Also: two Runge-Kutta steps at k = 8 (stages 1-4 through the high-degree stage path,
 which writes L into the next-state buffer and updates from there) against the oracle's
 steps, the initial-state projection at k = 8, both again at k = 12 and 15 on a curved
-mesh under the per-field float64 bound, and the entry points without high-degree
-kernels (diagnostics, adjoint) and body forces rejected with DGNS_EUNSUPPORTED.
+mesh under the per-field float64 bound, the wall branches on a channel with isothermal
+no-slip walls at k = 8, 13 and 15, and the entry points without high-degree kernels
+(diagnostics, adjoint) and body forces rejected with DGNS_EUNSUPPORTED.
 """
 import math
 
@@ -27,7 +28,7 @@ import torch
 
 from oracle import initial, timeint
 from tests import floor
-from tests.gpu_cases import announce, make_pair, rel_err_fields, tgv_input
+from tests.gpu_cases import announce, channel_input, make_pair, rel_err_fields, tgv_fluid, tgv_input
 
 pytestmark = pytest.mark.gpu
 
@@ -182,6 +183,49 @@ def test_high_degree_rk_steps_and_projection_large_k(kq):
     tol = 10 * 1e-12 * ((k + 1) / 4.0) ** 4
     print("two RK steps: increment vs oracle %s (bound %.1e)" % (["%.1e" % e for e in inc], tol), flush=True)
     assert max(inc) <= tol, inc
+
+
+@pytest.mark.parametrize("kq", [(8, 9), (13, 14), (15, 16)])
+def test_high_degree_channel_walls(kq):
+    # the streamed kernels' wall branches (the face kernel's own-side-only lower wall faces and
+    # upper faces without an exterior side, in its 128- and 256-thread forms) on a 1x2x1
+    # stretched channel with isothermal no-slip walls at both ends of x2, no body force: float64
+    # R and L at k = 8 under the floor rule against the extended evaluation, above per field
+    # within 1e-12 ((k+1)/4)^4 (L: 10 times) of the oracle; float32 R and L within 50 times the
+    # input-rounding floor
+    k, nq = kq
+    announce("high degree channel 1x2x1 k=%d nq=%d walls" % (k, nq))
+    fl = tgv_fluid(mu=1.0 / 180.0)
+    T0 = (18.3 / 0.1) ** 2 / (1.4 * 287.0)
+    geo = dict(lo=(0, -1, 0), hi=(2 * math.pi, 1, math.pi), periodic=(1, 0, 1), kind="channel", fluid=fl,
+               wall_T=T0)
+    oop, gop = make_pair((1, 2, 1), k, nq, **geo)
+    U = channel_input(oop)
+    R_gpu = gop.residual(_cuda(U)).cpu()
+    L_gpu = gop.apply(_cuda(U)).cpu()
+    torch.cuda.synchronize()
+    R_ora, L_ora = oop.residual(U), oop.apply(U)
+    if k == 8:
+        R_ext, L_ext = floor.reference_RL(oop, U, [0, 1])
+        floor.check(R_gpu, R_ora, R_ext, "R channel k=8")
+        floor.check(L_gpu, L_ora, L_ext, "L channel k=8")
+    else:
+        tol = 1e-12 * ((k + 1) / 4.0) ** 4
+        eR, eL = rel_err_fields(R_gpu, R_ora), rel_err_fields(L_gpu, L_ora)
+        print("channel k=%d: R vs oracle %s, L vs oracle %s (bounds %.1e, %.1e)"
+              % (k, ["%.1e" % e for e in eR], ["%.1e" % e for e in eL], tol, 10 * tol), flush=True)
+        assert max(eR) <= tol, eR
+        assert max(eL) <= 10 * tol, eL
+    _, g32 = make_pair((1, 2, 1), k, nq, precision="fp32", **geo)
+    U32 = U.float().double()
+    for name, got, f in (("R", g32.residual(_cuda(U)).cpu(), oop.residual), ("L", g32.apply(_cuda(U)).cpu(), oop.apply)):
+        ref = f(U)
+        cast = rel_err_fields(f(U32), ref)
+        errs = rel_err_fields(got, ref)
+        print("channel fp32 k=%d %s per field %s; input-rounding floor %s"
+              % (k, name, ["%.1e" % e for e in errs], ["%.1e" % e for e in cast]), flush=True)
+        for c in range(5):
+            assert errs[c] <= max(50 * cast[c], 1e-6), (name, c, errs, cast)
 
 
 def test_high_degree_unsupported_entry_points():

@@ -209,6 +209,41 @@ def test_lds_plan_layout():
         assert r.returncode == 0 and r.stdout.strip().endswith("all ok"), r.stdout[-4000:]
 
 
+@pytest.mark.parametrize("k,nq", [(8, 9), (15, 16)])
+def test_emulated_high_degree_channel_walls(k, nq):
+    # the streamed kernels' wall branches on a 1x2x1 stretched channel with isothermal no-slip
+    # walls at both ends of x2 (each cell has one wall face: the lower one lifted on the own
+    # side only, the upper one with no exterior side), no body force: at k = 8 R and L under the
+    # floor rule against the extended evaluation, at k = 15 per field within 1e-12 ((k+1)/4)^4
+    # (L: 10 times) of the oracle as on the GPU; float32 R within 50 times the input-rounding
+    # floor
+    fl = tgv_fluid(mu=1.0 / 180.0)
+    T0 = (18.3 / 0.1) ** 2 / (1.4 * 287.0)
+    lo, hi, n = (0, -1, 0), (2 * math.pi, 1, math.pi), (1, 2, 1)
+    om = omesh.BoxMesh(n, lo, hi, k, periodic=(True, False, True), kind=omesh.CHANNEL)
+    oop = ooperator.DGOperator(om, fl, nq, wall_T=T0)
+    U = channel_input(oop)
+    args = dict(periodic=(1, 0, 1), kind=1, mu=fl.mu, lam=fl.lam, wall_T=T0)
+    R = ed.run(U.numpy(), k, nq, n, lo, hi, fuse=0, **args)
+    L = ed.run(U.numpy(), k, nq, n, lo, hi, fuse=1, **args)
+    Ro, Lo = oop.residual(U), oop.apply(U)
+    if k == 8:
+        R_ext, L_ext = floor.reference_RL(oop, U, [0, 1])
+        floor.check(R, Ro, R_ext, "emulated channel k=8 R")
+        floor.check(L, Lo, L_ext, "emulated channel k=8 L")
+    else:
+        tol = 1e-12 * ((k + 1) / 4.0) ** 4
+        eR = rel_err_fields(torch.as_tensor(R), Ro)
+        eL = rel_err_fields(torch.as_tensor(L), Lo)
+        assert max(eR) <= tol, eR
+        assert max(eL) <= 10 * tol, eL
+    R32 = ed.run(U.numpy(), k, nq, n, lo, hi, fuse=0, precision=1, **args)
+    cast = rel_err_fields(oop.residual(U.float().double()), Ro)
+    errs = rel_err_fields(torch.as_tensor(R32), Ro)
+    for c in range(5):
+        assert errs[c] <= max(50 * cast[c], 1e-6), (c, errs, cast)
+
+
 @pytest.mark.parametrize("n,kind,amp,basis", [((2, 1, 1), 0, 0.0, "LGL"), ((1, 2, 1), 2, 0.1, "GL")])
 def test_emulated_high_degree(n, kind, amp, basis):
     # degree 8 (hd_impl.h: the cell streamed plane by plane, faces once per face, the
