@@ -108,9 +108,10 @@ const char* dgns_last_error(void);
  * Fails with DGNS_EINVAL if the mapping folds (det J <= 0 at a quadrature point).
  * Degrees 8..15 stream each cell through the kernels plane by plane (its coefficients
  * and residual no longer fit on chip); they provide the operator, the residual, the
- * inverse mass, the Runge-Kutta step and stage update, the time step and the initial
- * projection, and return DGNS_EUNSUPPORTED for a nonzero body force (at creation) and
- * from the diagnostics, channel statistics and adjoint entry points.
+ * inverse mass, the Runge-Kutta step and stage update, the time step, the initial
+ * projection, the diagnostics and the kinetic energy (one quadrature plane at a time), and
+ * return DGNS_EUNSUPPORTED for a nonzero body force (at creation) and from the channel
+ * statistics and adjoint entry points.
  * Device memory owned by the context besides the mesh data: a face buffer of
  * 60 (k+1)^2 doubles per cell, plus 10 n_q (k+1)^2 doubles per cell where the streamed
  * kernels can run (k >= 8; k = 6, n_q = 10 and k = 7, n_q = 11 in float64); DGNS_ENOMEM

@@ -77,6 +77,10 @@ int launch_diagnostics_k6(const OpArgs& a, const Tables1D& t, const double* L, d
 int launch_diagnostics_k7(const OpArgs& a, const Tables1D& t, const double* L, double* partial, bool gen, hipStream_t st);
 
 // Deterministic totals of the nine per-cell partial sums.
+// Diagnostics at degrees 8..11 and 12..15 (diag_impl.h: diag_hd_kernel, one quadrature
+// plane at a time); 1 if the pair has no kernel.
+int launch_diagnostics_hd1(const OpArgs& a, int k, int q, const double* L, double* partial, bool gen, hipStream_t st);
+int launch_diagnostics_hd2(const OpArgs& a, int k, int q, const double* L, double* partial, bool gen, hipStream_t st);
 int launch_diag_total(const double* partial, int64_t ncell, double* total, hipStream_t st);
 
 // out8 (device) = the eight diagnostics from the nine totals (device).

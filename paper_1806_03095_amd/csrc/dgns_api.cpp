@@ -227,6 +227,12 @@ int dispatch_diagnostics(const dgns_ctx* c, const OpArgs& a, const double* L, do
         case 5: rc = launch_diagnostics_k5(a, c->tab, L, partial, c->gen, c->stream); break;
         case 6: rc = launch_diagnostics_k6(a, c->tab, L, partial, c->gen, c->stream); break;
         case 7: rc = launch_diagnostics_k7(a, c->tab, L, partial, c->gen, c->stream); break;
+        case 8: case 9: case 10: case 11:
+            rc = launch_diagnostics_hd1(a, c->k, c->q, L, partial, c->gen, c->stream);
+            break;
+        case 12: case 13: case 14: case 15:
+            rc = launch_diagnostics_hd2(a, c->k, c->q, L, partial, c->gen, c->stream);
+            break;
     }
     if (rc == 0) rc = launch_diag_total(partial, c->ncell, total, c->stream);
     if (rc == 1) return fail(DGNS_EUNSUPPORTED, "no diagnostics kernel for degree %d, n_q %d", c->k, c->q);

@@ -494,6 +494,210 @@ inline int launch_diag_t(const OpArgs& a, const Tables1D& t, const double* L, do
     return hipGetLastError() == hipSuccess ? 0 : -1;
 }
 
+// diag_kernel for the high degrees (k >= 8), where a cell's U and L do not fit in LDS: the
+// same nine partial sums, one quadrature plane along xi_2 at a time.  Per plane the z sweep
+// reads the coefficient lines of rho, m (and L_rho, L_m) from global memory, then the y and x
+// sweeps and the integrands as above; the conserved totals take a second pass, one plane of
+// mass points at a time (the k+1 rule of the inverse mass matrix).  Tables from the device
+// copy of Tables1D.
+constexpr int kDiagHdBlock = 256;
+
+template <int N, int Q>
+struct DiagHdSizes {
+    static constexpr int N2 = N * N;
+    static constexpr int Z = 12 * N2;      // Z0 [8][a1 a0], Z1 [4][a1 a0] of one plane
+    static constexpr int Y = 16 * Q * N;   // Y00 [8][py][a0], Y10 [4][py][a0], Y01 [4][py][a0]
+    static constexpr int WORK = CMax<Z + Y, 10 * N2>::v;   // mass pass: [5][a1 a0] twice
+};
+
+template <int N, int Q, bool GEN>
+__global__ void __launch_bounds__(kDiagHdBlock)
+diag_hd_kernel(OpArgs a, const double* L, double* partial) {
+    using DS = DiagHdSizes<N, Q>;
+    constexpr int N2 = N * N, N3 = N2 * N, Q2 = Q * Q, Q3 = Q2 * Q;
+    __shared__ double sW[DS::WORK];
+    __shared__ double red[kDiagSums * kDiagHdBlock];
+    __shared__ double S[Q][N], D[Q][N], w[Q], Sm[N][N], wm[N];
+    const Tables1D* t = a.tab_dev;
+    const int64_t e = blockIdx.x;
+    const int tid = threadIdx.x, nth = blockDim.x;
+    const int64_t cs = a.ncell * N3;
+    for (int i = tid; i < Q * N; i += nth) {
+        S[i / N][i % N] = t->S[i / N][i % N];
+        D[i / N][i % N] = t->D[i / N][i % N];
+    }
+    for (int i = tid; i < N2; i += nth) Sm[i / N][i % N] = t->Sm[i / N][i % N];
+    if (tid < Q) w[tid] = t->w[tid];
+    if (tid < N) wm[tid] = t->wm[tid];
+    double Jc[9], detJ = 1;
+    if constexpr (!GEN) {
+#pragma unroll
+        for (int m = 0; m < 9; ++m) Jc[m] = a.cell_metric[e * 10 + m];
+        detJ = a.cell_metric[e * 10 + 9];
+    }
+    double acc[kDiagSums];
+#pragma unroll
+    for (int m = 0; m < kDiagSums; ++m) acc[m] = 0;
+    __syncthreads();
+
+    // interpolated components c < 8: rho, m (rows 0..3 of U), L_rho, L_m (rows 0..3 of L)
+    double* Z = sW;
+    double* Yb = sW + DS::Z;
+    for (int pz = 0; pz < Q; ++pz) {
+        // z: Z0[c] = (S_z X_c)(pz), Z1[c] = (D_z X_c)(pz) for c < 4     [c][a1 a0]
+        for (int it = tid; it < 8 * N2; it += nth) {
+            const int c = it / N2, r = it % N2;
+            double z0 = 0, z1 = 0;
+            if (c < 4 || L) {
+                const double* x = (c < 4 ? a.U + c * cs : L + (c - 4) * cs) + e * N3 + r;
+#pragma unroll 4
+                for (int i = 0; i < N; ++i) {
+                    const double v = x[i * N2];
+                    z0 += S[pz][i] * v;
+                    z1 += D[pz][i] * v;
+                }
+            }
+            Z[c * N2 + r] = z0;
+            if (c < 4) Z[(8 + c) * N2 + r] = z1;
+        }
+        __syncthreads();
+        // y: Y00 = S_y Z0 (8), Y10 = D_y Z0 (4), Y01 = S_y Z1 (4)     [kind c][py][a0]
+        for (int it = tid; it < 8 * Q * N; it += nth) {
+            const int a0 = it % N, py = (it / N) % Q, c = it / (N * Q);
+            double y00 = 0, y10 = 0, y01 = 0;
+#pragma unroll 4
+            for (int i = 0; i < N; ++i) {
+                const double z0 = Z[c * N2 + i * N + a0];
+                y00 += S[py][i] * z0;
+                if (c < 4) {
+                    y10 += D[py][i] * z0;
+                    y01 += S[py][i] * Z[(8 + c) * N2 + i * N + a0];
+                }
+            }
+            Yb[(c * Q + py) * N + a0] = y00;
+            if (c < 4) {
+                Yb[((8 + c) * Q + py) * N + a0] = y10;
+                Yb[((12 + c) * Q + py) * N + a0] = y01;
+            }
+        }
+        __syncthreads();
+        // points of the plane: x contraction and the integrands
+        for (int it = tid; it < Q2; it += nth) {
+            const int px = it % Q, py = it / Q;
+            double v[8], g[4][3];
+#pragma unroll
+            for (int c = 0; c < 8; ++c) {
+                double sv = 0, dx = 0, dy = 0, dz = 0;
+#pragma unroll 4
+                for (int i = 0; i < N; ++i) {
+                    const double y00 = Yb[(c * Q + py) * N + i];
+                    sv += S[px][i] * y00;
+                    if (c < 4) {
+                        dx += D[px][i] * y00;
+                        dy += S[px][i] * Yb[((8 + c) * Q + py) * N + i];
+                        dz += S[px][i] * Yb[((12 + c) * Q + py) * N + i];
+                    }
+                }
+                v[c] = sv;
+                if (c < 4) {
+                    g[c][0] = dx;
+                    g[c][1] = dy;
+                    g[c][2] = dz;
+                }
+            }
+            double J[9], jxw;
+            if constexpr (GEN) {
+                const double* gm = a.cell_metric + e * 10 * Q3 + px + Q * (py + Q * pz);
+#pragma unroll
+                for (int m = 0; m < 9; ++m) J[m] = gm[m * Q3];
+                jxw = gm[9 * Q3];
+            } else {
+#pragma unroll
+                for (int m = 0; m < 9; ++m) J[m] = Jc[m];
+                jxw = detJ * w[px] * w[py] * w[pz];
+            }
+            const double rinv = 1.0 / v[0];
+            const double u[3] = {v[1] * rinv, v[2] * rinv, v[3] * rinv};
+            double gg = 0;
+#pragma unroll
+            for (int al = 0; al < 3; ++al)
+#pragma unroll
+                for (int j = 0; j < 3; ++j) {
+                    double gm_ = 0, gr = 0;
+#pragma unroll
+                    for (int d = 0; d < 3; ++d) {
+                        gm_ += J[d * 3 + j] * g[1 + al][d];
+                        gr += J[d * 3 + j] * g[0][d];
+                    }
+                    const double du = (gm_ - u[al] * gr) * rinv;
+                    gg += du * du;
+                }
+            acc[0] += 0.5 * (u[0] * u[0] + u[1] * u[1] + u[2] * u[2]) * jxw;
+            acc[1] += gg * jxw;
+            if (L) {
+                double r = 0;
+#pragma unroll
+                for (int al = 0; al < 3; ++al) r += u[al] * (v[5 + al] - u[al] * v[4]) * rinv;
+                acc[2] -= r * jxw;
+            }
+            acc[8] += jxw;
+        }
+        __syncthreads();
+    }
+
+    // conserved totals with the k+1 rule, one plane pm of mass points at a time
+    double* A = sW;            // S_m along xi_2   [c][a1 a0]
+    double* B = sW + 5 * N2;   // then along xi_1  [c][p1][a0]
+    for (int pm = 0; pm < N; ++pm) {
+        for (int it = tid; it < 5 * N2; it += nth) {
+            const int c = it / N2, r = it % N2;
+            const double* x = a.U + c * cs + e * N3 + r;
+            double sv = 0;
+#pragma unroll 4
+            for (int i = 0; i < N; ++i) sv += Sm[pm][i] * x[i * N2];
+            A[c * N2 + r] = sv;
+        }
+        __syncthreads();
+        for (int it = tid; it < 5 * N2; it += nth) {
+            const int a0 = it % N, p1 = (it / N) % N, c = it / N2;
+            double sv = 0;
+#pragma unroll 4
+            for (int i = 0; i < N; ++i) sv += Sm[p1][i] * A[c * N2 + i * N + a0];
+            B[c * N2 + p1 * N + a0] = sv;
+        }
+        __syncthreads();
+        for (int it = tid; it < N2; it += nth) {
+            const int p0 = it % N, p1 = it / N;
+            double jxw;
+            if constexpr (GEN) jxw = a.mass_jxw[e * N3 + p0 + N * (p1 + N * pm)];
+            else jxw = detJ * wm[p0] * wm[p1] * wm[pm];
+#pragma unroll
+            for (int c = 0; c < 5; ++c) {
+                double sv = 0;
+#pragma unroll 4
+                for (int i = 0; i < N; ++i) sv += Sm[p0][i] * B[c * N2 + p1 * N + i];
+                acc[3 + c] += sv * jxw;
+            }
+        }
+        __syncthreads();
+    }
+    block_sums<kDiagSums>(acc, red);
+    if (tid < kDiagSums) {
+        double sv = 0;
+#pragma unroll
+        for (int m = 0; m < kDiagSums; ++m)
+            if (m == tid) sv = acc[m];
+        partial[e * kDiagSums + tid] = sv;
+    }
+}
+
+template <int N, int Q, bool GEN>
+inline int launch_diag_hd_t(const OpArgs& a, const double* L, double* partial, hipStream_t st) {
+    hipLaunchKernelGGL((diag_hd_kernel<N, Q, GEN>), dim3((unsigned)a.ncell), dim3(kDiagHdBlock), 0, st, a, L,
+                       partial);
+    return hipGetLastError() == hipSuccess ? 0 : -1;
+}
+
 template <int N, int Q, bool GEN>
 inline int launch_ke_vjp_t(const OpArgs& a, const Tables1D& t, double* Ub, hipStream_t st) {
     KTab<N, Q, double> kt;

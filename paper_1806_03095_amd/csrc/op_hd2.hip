@@ -1,4 +1,5 @@
 // High-degree operator kernels (hd_impl.h), degrees 12..15.
+#include "diag_impl.h"
 #include "hd_impl.h"
 
 namespace dgns {
@@ -7,6 +8,11 @@ template <int N, int Q>
 static int op_hd(const OpArgs& a, bool fp32, bool gen, hipStream_t st) {
     return fp32 ? (gen ? launch_op_hd_t<N, Q, float, true>(a, st) : launch_op_hd_t<N, Q, float, false>(a, st))
                 : (gen ? launch_op_hd_t<N, Q, double, true>(a, st) : launch_op_hd_t<N, Q, double, false>(a, st));
+}
+
+template <int N, int Q>
+static int diag_hd(const OpArgs& a, const double* L, double* partial, bool gen, hipStream_t st) {
+    return gen ? launch_diag_hd_t<N, Q, true>(a, L, partial, st) : launch_diag_hd_t<N, Q, false>(a, L, partial, st);
 }
 
 template <int N>
@@ -35,6 +41,15 @@ int launch_inverse_mass_hd2(const double* R, double* L, int64_t ncell, const dou
         case 15: return minv_hd<16>(R, L, ncell, cm, mj, t, fp32, gen, st);
         default: return 1;
     }
+}
+
+int launch_diagnostics_hd2(const OpArgs& a, int k, int q, const double* L, double* partial, bool gen,
+                          hipStream_t st) {
+    if (k == 12 && q == 13) return diag_hd<13, 13>(a, L, partial, gen, st);
+    if (k == 13 && q == 14) return diag_hd<14, 14>(a, L, partial, gen, st);
+    if (k == 14 && q == 15) return diag_hd<15, 15>(a, L, partial, gen, st);
+    if (k == 15 && q == 16) return diag_hd<16, 16>(a, L, partial, gen, st);
+    return 1;
 }
 
 }  // namespace dgns

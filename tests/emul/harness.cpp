@@ -59,6 +59,11 @@ int run_minv_hd(const OpArgs& a, int fp32, int gen) {
 }
 
 template <int N, int Q>
+int run_diag_hd(const OpArgs& a, const double* L, int gen) {
+    return gen ? launch_diag_hd_t<N, Q, true>(a, L, a.out, nullptr) : launch_diag_hd_t<N, Q, false>(a, L, a.out, nullptr);
+}
+
+template <int N, int Q>
 int run_stats(const OpArgs& a, const Tables1D& t, int gen) {
     return gen ? launch_chan_stats_t<N, Q, true>(a, t, a.out, nullptr) : launch_chan_stats_t<N, Q, false>(a, t, a.out, nullptr);
 }
@@ -101,7 +106,8 @@ int main(int argc, char** argv) {
     }
     const int64_t ndof = 5 * hs.ncell * hs.n3;
     const int64_t nout = fuse == 4 ? hs.ncell * prm.n_q * kStats
-                                   : (fuse == 5 ? (int64_t)2 * msh.n[0] * msh.n[2] * kWallSums : ndof);
+                                   : (fuse == 5 ? (int64_t)2 * msh.n[0] * msh.n[2] * kWallSums
+                                                : (fuse == 6 ? hs.ncell * kDiagSums : ndof));
     std::vector<double> U(ndof), out(nout, -12345.0), Rb;
     // face buffer of the split evaluation: six lifted blocks [2][5][N^2] per cell (sized
     // for float64, enough for float32), followed by the streamed cell kernel's scratch
@@ -111,7 +117,7 @@ int main(int argc, char** argv) {
     const int64_t nfw_hd = (int64_t)hs.ncell * 10 * prm.n_q * (prm.degree + 1) * (prm.degree + 1);
     std::vector<double> fw(hs.ncell * 6 * 10 * (prm.degree + 1) * (prm.degree + 1) + nfw_hd, 1e300);
     if ((int64_t)std::fread(U.data(), 8, ndof, f) != ndof) return 6;
-    if (fuse == 2) {
+    if (fuse == 2 || fuse == 6) {
         Rb.resize(ndof);
         if ((int64_t)std::fread(Rb.data(), 8, ndof, f) != ndof) return 6;
     }
@@ -150,10 +156,13 @@ int main(int argc, char** argv) {
                                                               : run<K + 1, Q_>(a, hs.tab, fp32, gen))));
     EMU_CASES
 #ifdef EMU_HD_CASES
-    // degrees >= 8: modes 0 (residual), 1 (operator) and 3 (stand-alone inverse mass)
+    // degrees >= 8: modes 0 (residual), 1 (operator), 3 (stand-alone inverse mass) and 6
+    // (diagnostics partial sums [n_cells][9] of U with the second input as L)
 #define EMU_HD_CASE(K, Q_) \
     if (k == K && q == Q_)  \
-        rc = fuse == 3 ? run_minv_hd<K + 1>(a, fp32, gen) : (fuse <= 1 ? run_hd<K + 1, Q_>(a, fp32, gen) : -4);
+        rc = fuse == 3 ? run_minv_hd<K + 1>(a, fp32, gen)                                               \
+                       : (fuse == 6 ? run_diag_hd<K + 1, Q_>(a, Rb.data(), gen)                         \
+                                    : (fuse <= 1 ? run_hd<K + 1, Q_>(a, fp32, gen) : -4));
     EMU_HD_CASES
 #endif
     if (rc != 0) {

@@ -63,7 +63,8 @@ def run(U, k, nq, n, lo, hi, periodic=(1, 1, 1), kind=0, basis=0, precision=0, g
         lam=0.0, rho_ref=1.0, force=(0, 0, 0), wall_T=0.0, amp=0.0, C=1.8, terms=7, fuse=0, Rbar=None):
     """fuse: 0 residual, 1 operator (with M^{-1}), 2 residual adjoint of Rbar, 3 standalone M^{-1} U,
     4 channel-statistics partial sums (returned as [n_cells, n_q, 9]), 5 wall-shear partial sums
-    (returned as [2 n0 n2, 3])."""
+    (returned as [2 n0 n2, 3]), 6 diagnostics partial sums of the streamed kernels (k >= 8) with
+    Rbar as L (returned as [n_cells, 9])."""
     exe = build()
     p = _Params(k, nq, basis, precision, gamma, R, mu, lam, rho_ref, (ctypes.c_double * 3)(*force), wall_T)
     m = _Mesh((ctypes.c_int * 3)(*n), (ctypes.c_double * 3)(*lo), (ctypes.c_double * 3)(*hi),
@@ -77,7 +78,7 @@ def run(U, k, nq, n, lo, hi, periodic=(1, 1, 1), kind=0, basis=0, precision=0, g
             f.write(np.uint32(terms).tobytes())
             f.write(np.int32(fuse).tobytes())
             f.write(U.tobytes())
-            if fuse == 2:
+            if fuse in (2, 6):
                 f.write(np.ascontiguousarray(Rbar, dtype=np.float64).tobytes())
         r = subprocess.run([exe, fi, fo], capture_output=True, text=True)
         if r.returncode != 0:
@@ -85,4 +86,6 @@ def run(U, k, nq, n, lo, hi, periodic=(1, 1, 1), kind=0, basis=0, precision=0, g
         out = np.fromfile(fo, dtype=np.float64)
         if fuse == 5:
             return out.reshape(-1, 3)
+        if fuse == 6:
+            return out.reshape(-1, 9)
         return out.reshape(-1, nq, 9) if fuse == 4 else out.reshape(U.shape)

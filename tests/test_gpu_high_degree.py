@@ -18,15 +18,17 @@ Also: two Runge-Kutta steps at k = 8 (stages 1-4 through the high-degree stage p
 which writes L into the next-state buffer and updates from there) against the oracle's
 steps, the initial-state projection at k = 8, both again at k = 12 and 15 on a curved
 mesh under the per-field float64 bound, the wall branches on a channel with isothermal
-no-slip walls at k = 8, 13 and 15, and the entry points without high-degree kernels
-(diagnostics, adjoint) and body forces rejected with DGNS_EUNSUPPORTED.
+no-slip walls at k = 8, 13 and 15, the diagnostics at k = 8, 12 and 15 against the oracle's,
+and the entry points without high-degree kernels (adjoint) and body forces rejected with
+DGNS_EUNSUPPORTED.
 """
 import math
 
+import numpy as np
 import pytest
 import torch
 
-from oracle import initial, timeint
+from oracle import diagnostics as odiag, initial, timeint
 from tests import floor
 from tests.gpu_cases import announce, channel_input, make_pair, rel_err_fields, tgv_fluid, tgv_input
 
@@ -228,12 +230,33 @@ def test_high_degree_channel_walls(kq):
             assert errs[c] <= max(50 * cast[c], 1e-6), (name, c, errs, cast)
 
 
+@pytest.mark.parametrize("kq", [(8, 9), (12, 13), (15, 16)])
+def test_high_degree_diagnostics(kq):
+    # the streamed diagnostics (one quadrature plane at a time, the conserved totals one plane
+    # of mass points at a time) against the oracle's on the same U and L: e_k, eps, mass and
+    # energy to 1e-13 relative, -de_k/dt to 1e-12, the momentum totals (sums that cancel) to
+    # 1e-13 of the mass; affine at k = 8, 15, curved at k = 12
+    k, nq = kq
+    curved = k == 12
+    announce("high degree diagnostics k=%d nq=%d %s" % (k, nq, "curved" if curved else "affine"))
+    oop, gop = make_pair((2, 1, 1), k, nq, kind="curved" if curved else "affine", amp=0.1 if curved else 0.0)
+    U = tgv_input(oop, seed=90 + k, mach=0.1)
+    L = oop.apply(U)
+    dg = gop.diagnostics(_cuda(U), _cuda(L))
+    torch.cuda.synchronize()
+    do = odiag.diagnostics(oop, U, L)
+    print("k=%d diagnostics:" % k, {key: "%.2e" % (abs(dg[key] - do[key]) / abs(do[key]))
+                                    for key in ("e_k", "eps", "rate", "mass", "energy")}, flush=True)
+    for key in ("e_k", "eps", "mass", "energy"):
+        assert abs(dg[key] - do[key]) <= 1e-13 * abs(do[key]), (key, dg[key], do[key])
+    assert abs(dg["rate"] - do["rate"]) <= 1e-12 * abs(do["rate"]), (dg["rate"], do["rate"])
+    assert np.allclose(dg["mom"], do["mom"], rtol=0.0, atol=1e-13 * abs(do["mass"])), (dg["mom"], do["mom"])
+
+
 def test_high_degree_unsupported_entry_points():
     from paper_1806_03095_amd import binding
     oop, gop = make_pair((2, 1, 1), 8, 9)
     U = _cuda(tgv_input(oop, seed=5, mach=0.3))
-    with pytest.raises(RuntimeError, match="degree|unsupported|kernel"):
-        gop.diagnostics(U)
     with pytest.raises(RuntimeError, match="degree|unsupported|kernel"):
         gop.residual_vjp(U, torch.ones_like(U))
     with pytest.raises(RuntimeError, match="body force"):

@@ -209,6 +209,30 @@ def test_lds_plan_layout():
         assert r.returncode == 0 and r.stdout.strip().endswith("all ok"), r.stdout[-4000:]
 
 
+@pytest.mark.parametrize("k,nq,kind,amp", [(8, 9, 0, 0.0), (15, 16, 2, 0.1)])
+def test_emulated_high_degree_diagnostics(k, nq, kind, amp):
+    # the streamed diagnostics (one quadrature plane at a time, the totals one plane of mass
+    # points at a time): the nine per-cell partial sums summed over the cells against the
+    # oracle's unnormalised integrals of the same U and L -- |u|^2/2, grad u : grad u,
+    # -u.du/dt, the conserved totals at the mass points and the volume -- to 1e-13 relative
+    # (the rate 1e-12; the momentum totals, sums that cancel to 1e-5 of their terms, to 1e-13
+    # of the mass), affine at k = 8, curved at k = 15 (measured: 3e-15, 7e-14, 5e-17)
+    fl = tgv_fluid()
+    n = (2, 1, 1)
+    om = omesh.BoxMesh(n, PI3[0], PI3[1], k, kind=kind, deform_amp=amp)
+    oop = ooperator.DGOperator(om, fl, nq)
+    U = tgv_input(oop, mach=0.1, seed=33)
+    L = oop.apply(U)
+    part = ed.run(U.numpy(), k, nq, n, *PI3, kind=kind, amp=amp, mu=fl.mu, lam=fl.lam, fuse=6, Rbar=L.numpy())
+    got = part.sum(axis=0)
+    d = odiag.diagnostics(oop, U, L)
+    V = d["volume"]
+    want = [d["e_k"] * V, d["eps"] * V / fl.nu, d["rate"] * V, d["mass"], *d["mom"], d["energy"], V]
+    for m in range(9):
+        bound = 1e-13 * abs(want[3]) if m in (4, 5, 6) else (1e-12 if m == 2 else 1e-13) * abs(want[m])
+        assert abs(got[m] - want[m]) <= bound, (m, got[m], want[m])
+
+
 @pytest.mark.parametrize("k,nq", [(8, 9), (15, 16)])
 def test_emulated_high_degree_channel_walls(k, nq):
     # the streamed kernels' wall branches on a 1x2x1 stretched channel with isothermal no-slip
