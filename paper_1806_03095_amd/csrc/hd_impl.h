@@ -512,6 +512,11 @@ struct MinvHdPlan {
     // the whole inverse in registers while it fits (float32, N <= 11: 3-5% faster there),
     // else one output at a time from LDS
     static constexpr bool REG = sizeof(Real) == 4 && N <= 11;
+    // even-odd rows (minv_line_eo) where they measured faster than whole rows from LDS, odd
+    // N >= 11 (at about 10M DoFs, us per launch: N = 13 106 -> 89 in float64, 78 -> 71 in
+    // float32; N = 15 92 -> 79 and 68 -> 62; N = 11 float64 72 -> 70); at even N they measured
+    // 1-33% slower
+    static constexpr bool EO = !REG && N % 2 == 1 && N >= 11;
     static constexpr int XP = N * (int)sizeof(Real) % 64 == 0 ? N + 1 : N;
     static constexpr int YP = N * XP;
     static constexpr int BS = N * YP;
@@ -546,6 +551,24 @@ __device__ __forceinline__ void minv_line_hd(const Real (&M)[N][N], const Real (
     }
 }
 
+// One line of the inverse mass in even-odd form (see EOMat): S^{-1} and its transpose are
+// centrosymmetric, since the mass points and the nodes are symmetric about the cell centre,
+// so the outputs o and N-1-o come from one row pair of E and O, half the multiply-adds of
+// minv_line_hd.  The line's input stays in registers, so the outputs may overwrite it.
+template <int N, typename Real, typename Put>
+__device__ __forceinline__ void minv_line_eo(const EOMat<N, N, Real>& M, const Real (&v)[N], Put put) {
+    constexpr int HI = N / 2 > 0 ? N / 2 : 1, HO = (N + 1) / 2;
+    Real ve[HI], vo[HI];
+    eo_split<N>(v, ve, vo);
+#pragma unroll 2
+    for (int p = 0; p < HO; ++p) {
+        Real e, o;
+        eo_row<N, N>(M, ve, vo, v[N / 2], p, e, o);
+        put(p, e + o);
+        if (p != N - 1 - p) put(N - 1 - p, e - o);
+    }
+}
+
 template <int N, typename Real, bool GEN>
 __global__ void __launch_bounds__(kHdBlock)
 inverse_mass_hd_kernel(const double* R, double* L, int64_t ncell, const double* cell_metric, const double* mass_jxw,
@@ -554,14 +577,25 @@ inverse_mass_hd_kernel(const double* R, double* L, int64_t ncell, const double* 
     constexpr int N2 = N * N, N3 = N2 * N, RPB = MP::RPB, XP = MP::XP, YP = MP::YP;
     static_assert(N2 <= kHdBlock, "one line per thread");
     __shared__ Real buf[RPB * MP::BS];
-    __shared__ Real Smi[N][N];    // S^{-1}
-    __shared__ Real SmiT[N][N];   // its transpose
+    // S^{-1} and its transpose: whole rows, or in even-odd form
+    using MT = std::conditional_t<MP::EO, EOMat<N, N, Real>, Real[N][N]>;
+    __shared__ MT Smi;
+    __shared__ MT SmiT;
     __shared__ Real lwm[N];
     const int tid = threadIdx.x;
-    for (int i = tid; i < N2; i += blockDim.x) {
-        Smi[i / N][i % N] = (Real)t->Smi[i / N][i % N];
-        SmiT[i % N][i / N] = (Real)t->Smi[i / N][i % N];
+    if constexpr (MP::EO) {
+        fill_eo_dev(Smi, [&](int p, int i) { return t->Smi[p][i]; });
+        fill_eo_dev(SmiT, [&](int p, int i) { return t->Smi[i][p]; });
+    } else {
+        for (int i = tid; i < N2; i += blockDim.x) {
+            Smi[i / N][i % N] = (Real)t->Smi[i / N][i % N];
+            SmiT[i % N][i / N] = (Real)t->Smi[i / N][i % N];
+        }
     }
+    const auto line = [&](const MT& M, const Real (&v)[N], auto put) {
+        if constexpr (MP::EO) minv_line_eo<N>(M, v, put);
+        else minv_line_hd<N, MP::REG>(M, v, put);
+    };
     if (tid < N) lwm[tid] = (Real)t->wm[tid];
     const int lb = tid / N2, ln = tid % N2, l0 = ln % N, l1 = ln / N;
     const int64_t row = (int64_t)blockIdx.x * RPB + lb;   // c * ncell + e
@@ -579,12 +613,12 @@ inverse_mass_hd_kernel(const double* R, double* L, int64_t ncell, const double* 
         for (int m = 0; m < N; ++m) v[m] = (Real)src[m];
     }
     __syncthreads();
-    if (act) minv_line_hd<N, MP::REG>(SmiT, v, [&](int o, Real r) { xl[o] = r; });
+    if (act) line(SmiT, v, [&](int o, Real r) { xl[o] = r; });
     __syncthreads();
     if (act) {
 #pragma unroll
         for (int m = 0; m < N; ++m) v[m] = yl[m * XP];
-        minv_line_hd<N, MP::REG>(SmiT, v, [&](int o, Real r) { yl[o * XP] = r; });
+        line(SmiT, v, [&](int o, Real r) { yl[o * XP] = r; });
     }
     __syncthreads();
     if (act) {
@@ -592,7 +626,7 @@ inverse_mass_hd_kernel(const double* R, double* L, int64_t ncell, const double* 
         // thread's own line (its writes are visible to its own later reads)
 #pragma unroll
         for (int m = 0; m < N; ++m) v[m] = zl[m * YP];
-        minv_line_hd<N, MP::REG>(SmiT, v, [&](int o, Real r) { zl[o * YP] = r; });
+        line(SmiT, v, [&](int o, Real r) { zl[o * YP] = r; });
         const int64_t e = row % ncell;
         if constexpr (GEN) {
             const double* jw = mass_jxw + e * N3 + ln;
@@ -603,20 +637,20 @@ inverse_mass_hd_kernel(const double* R, double* L, int64_t ncell, const double* 
 #pragma unroll
             for (int m = 0; m < N; ++m) v[m] = zl[m * YP] * (f / lwm[m]);
         }
-        minv_line_hd<N, MP::REG>(Smi, v, [&](int o, Real r) { zl[o * YP] = r; });
+        line(Smi, v, [&](int o, Real r) { zl[o * YP] = r; });
     }
     __syncthreads();
     if (act) {
 #pragma unroll
         for (int m = 0; m < N; ++m) v[m] = yl[m * XP];
-        minv_line_hd<N, MP::REG>(Smi, v, [&](int o, Real r) { yl[o * XP] = r; });
+        line(Smi, v, [&](int o, Real r) { yl[o * XP] = r; });
     }
     __syncthreads();
     if (act) {
 #pragma unroll
         for (int m = 0; m < N; ++m) v[m] = xl[m];
         double* dst = L + row * N3 + ln * N;
-        minv_line_hd<N, MP::REG>(Smi, v, [&](int o, Real r) { dst[o] = (double)r; });
+        line(Smi, v, [&](int o, Real r) { dst[o] = (double)r; });
     }
 }
 
